@@ -1,0 +1,365 @@
+"""Adaptive sketch-size PCG and IHS, written from the paper's algorithms.  Test infrastructure.
+
+Problem (eq. "main optimization problem"): minimise f(x) = 1/2 x^T H x - b^T x with
+H = A^T A + nu^2 Lambda, A in R^{n x d}, Lambda diagonal.
+
+* ``adaptive_pcg`` follows Algorithm 2 (adaptive PCG): PCG steps (eq. "pcg update") with
+  preconditioner H_S; after each candidate step the approximate Newton decrement ratio is
+  compared with c(rho) * phi(rho)^(t+1-I), phi = (1-sqrt(1-rho))/(1+sqrt(1-rho)),
+  c = 4 (1+sqrt rho)/(1-sqrt rho); on failure I <- t, m <- 2m, a fresh S is drawn, H_S is
+  refactored and the residual r_t = b - H x_t is recomputed explicitly.
+* ``adaptive_ihs`` follows Algorithm 1 with the IHS update (eq. "ihs") and the constants of
+  Theorem "rate IHS": step mu = 1 - rho, phi = rho, alpha = 1, so c = (1+sqrt rho)/(1-sqrt rho);
+  its decrement carries the 1/2 of Sec. 2.3.  A rejection needs no pass over A: the gradient
+  at x_t is unchanged.
+
+Readings where the paper is silent (each also listed in the design notes):
+  * test in the log domain; equality passes (the paper rejects on ">"); a candidate with
+    decrement <= 0 passes;
+  * m is capped at n' (the padded Hadamard size) for both embeddings; at the cap a failed test
+    is accepted and ``m_cap_reached`` is set;
+  * x_0 = 0 gives r_0 = b (-b for the IHS gradient) without a pass over A, and so does a
+    restart at x_t = 0;
+  * stop rules (the paper prescribes none, Sec. 1.3 and the Remark on termination):
+      'xrel'       (default) (1+sqrt rho) * D <= nu^2 min(lambda) tol^2 ||x_t||^2 with D the
+                   decrement r^T H_S^{-1} r (= 2 x the 1/2-weighted decrement); from the
+                   decrement lemma, delta <= (1+sqrt rho) * delta~ under the embedding event,
+                   and delta >= 1/2 nu^2 min(lambda) ||x - x*||^2;
+      'dtilde_rel' D_t / D_0 <= tol^2;
+      'fixed'      exactly max_iter accepted steps (the algorithms' iteration number T);
+      'remark'     delta~_t <= tol / (m_delta + 1), m_delta from the SRHT concentration
+                   theorem with d_e replaced by d and failure probability 1/d;
+    always: stop a column when its decrement or residual is exactly zero;
+  * matrix variables (c right-hand sides, Sec. 5 "accounts for matrix variables"): the
+    columns share S and H_S; a candidate step is rejected if any active column fails the
+    test; on rejection every active column restarts at its own x_t; a column that meets the
+    stop rule is frozen.  With c = 1 this is exactly Algorithm 2 / Algorithm 1.
+  * ``max_iter`` bounds the number of accepted steps t (the loop "while t < T").
+
+Pins (tests/test_oracle_solvers.py): one-step convergence when m = n' (H_S = H); Krylov
+optimality of PCG (Theorem "rate cg") by brute-force least squares on tiny problems; the IHS
+error recursion (proof of Theorem "rate IHS"); the decrement bracket (proof of the decrement
+lemma); invariants of the adaptive control (accepted steps satisfy the test, m doubles, K
+bounded, forced rejections recompute r_t = b - H x_t); rel. error <= 1e-10 against the
+refined direct solution.
+"""
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import sketch as sk
+from .factor import NotSPDError, SketchedHessian
+
+
+@dataclass
+class Options:
+    method: str = "pcg"          # 'pcg' | 'ihs'
+    sketch: str = "srht"         # 'srht' | 'gauss'
+    rho: float = 0.125
+    m_init: int = 1
+    m_max: int = 0               # 0 -> n'
+    max_iter: int = 200
+    stop: str = "xrel"           # 'xrel' | 'dtilde_rel' | 'fixed' | 'remark'
+    tol: float = 1e-10
+    seed: int = 0
+    problem: int = 0
+    adaptive: bool = True
+    force_reject_at: tuple = ()  # values of t at which the first candidate step is rejected
+    x0: object = None
+    keep_iterates: bool = False  # store the committed x in the trace (tests)
+
+
+@dataclass
+class Info:
+    status: str = "ok"           # 'ok' | 'max_iter' | 'not_spd' | 'nonfinite'
+    iterations: int = 0          # accepted steps t
+    attempts: int = 0            # candidate steps (accepted + rejected)
+    final_m: int = 0
+    resketches: int = 0
+    a_passes: int = 0            # passes over A (H.v products and explicit residuals)
+    m_cap_reached: bool = False
+    dtilde_final: object = None
+    trace: list = field(default_factory=list)
+
+
+def pcg_constants(rho):
+    """(phi, c) of Algorithm 2."""
+    s = math.sqrt(1.0 - rho)
+    phi = (1.0 - s) / (1.0 + s)
+    c = 4.0 * (1.0 + math.sqrt(rho)) / (1.0 - math.sqrt(rho))
+    return phi, c
+
+
+def ihs_constants(rho):
+    """(phi, c, mu) for the IHS: phi = rho, alpha = 1, mu = 1 - rho (Theorem "rate IHS")."""
+    c = (1.0 + math.sqrt(rho)) / (1.0 - math.sqrt(rho))
+    return rho, c, 1.0 - rho
+
+
+def remark_m_delta(n, d, delta=None):
+    """m_delta of the SRHT concentration theorem with d_e := d (Remark on termination)."""
+    de = float(d)
+    delta = 1.0 / d if delta is None else delta
+    return 16.0 * math.log(16.0 * de / delta) * (math.sqrt(de) + math.sqrt(8.0 * math.log(2.0 * n / delta))) ** 2
+
+
+def hess_apply(A, nu, lam, P):
+    """H P = A^T (A P) + nu^2 Lambda P."""
+    return A.T @ (A @ P) + (nu ** 2) * lam[:, None] * P
+
+
+def _validate(A, b, nu, lam, o):
+    n, d = A.shape
+    if n < 1 or d < 1:
+        raise ValueError("n and d must be >= 1")
+    if b.shape[0] != d:
+        raise ValueError("b must have d rows")
+    if not (np.isfinite(nu) and nu > 0):
+        raise ValueError("nu must be finite and > 0")
+    if np.any(~np.isfinite(lam)) or np.any(lam <= 0):
+        raise ValueError("Lambda must have finite positive entries")
+    if not 0.0 < o.rho < 1.0:
+        raise ValueError("rho must lie in (0, 1)")
+    if o.m_init < 1:
+        raise ValueError("m_init must be >= 1")
+    if o.tol <= 0 and o.stop != "fixed":
+        raise ValueError("tol must be > 0")
+    if o.method not in ("pcg", "ihs"):
+        raise ValueError("method must be 'pcg' or 'ihs'")
+
+
+class _Stopper:
+    """Stop rules, evaluated per column after initialisation and after each accepted step."""
+
+    def __init__(self, o, n, d, nu, lam, half):
+        self.o = o
+        self.scale = (nu ** 2) * float(np.min(lam)) * o.tol ** 2
+        self.sr = 1.0 + math.sqrt(o.rho)
+        self.half = half  # True when the stored decrement carries the 1/2 (IHS)
+        self.D0 = None
+        if o.stop == "remark":
+            self.remark_thr = o.tol / (remark_m_delta(n, d) + 1.0)
+
+    def full_decrement(self, dt):
+        return 2.0 * dt if self.half else dt
+
+    def done(self, dt, x, resid, t, J=None):
+        """Boolean per column (J: the column indices dt, x, resid belong to)."""
+        D = self.full_decrement(dt)
+        if self.D0 is None:
+            self.D0 = D.copy()
+        D0 = self.D0 if J is None else self.D0[J]
+        exact = (dt <= 0) | ~np.any(resid != 0, axis=0)
+        s = self.o.stop
+        if s == "xrel":
+            rule = self.sr * D <= self.scale * np.sum(x * x, axis=0)
+        elif s == "dtilde_rel":
+            rule = D <= (self.o.tol ** 2) * D0
+        elif s == "fixed":
+            rule = np.full(D.shape, t >= self.o.max_iter)
+        elif s == "remark":
+            rule = 0.5 * D <= self.remark_thr
+        else:
+            raise ValueError(f"unknown stop rule {s!r}")
+        return exact | rule
+
+
+def _as2d(b):
+    b = np.asarray(b, dtype=np.float64)
+    return (b[:, None], True) if b.ndim == 1 else (b, False)
+
+
+def _sketch_factor(A, m, o, k, nu, lam):
+    SA = sk.sketch(A, m, o.sketch, o.seed, k, o.problem)
+    return SketchedHessian(SA, nu, lam)
+
+
+def adaptive_pcg(A, b, nu, lam=None, opts=None):
+    """Adaptive PCG (Algorithm 2).  Returns (x, Info); x has the shape of b."""
+    o = opts or Options()
+    A = np.asarray(A, dtype=np.float64)
+    n, d = A.shape
+    B, squeeze = _as2d(b)
+    c = B.shape[1]
+    lam = np.ones(d) if lam is None else np.asarray(lam, dtype=np.float64)
+    _validate(A, B, nu, lam, o)
+    info = Info()
+    phi, cc = pcg_constants(o.rho)
+    log_phi, log_c = math.log(phi), math.log(cc)
+    m_cap = sk.max_sketch_size(n, o.sketch) if o.m_max <= 0 else min(o.m_max, sk.max_sketch_size(n, o.sketch))
+    m = min(o.m_init, m_cap)
+    k = 0
+    try:
+        P = _sketch_factor(A, m, o, k, nu, lam)
+    except NotSPDError:
+        info.status = "not_spd"
+        return (np.zeros(d) if squeeze else np.zeros((d, c))), info
+
+    X = np.zeros((d, c)) if o.x0 is None else np.array(o.x0, dtype=np.float64).reshape(d, c)
+    if np.any(X != 0):
+        R = B - hess_apply(A, nu, lam, X)
+        info.a_passes += 1
+    else:
+        R = B.copy()
+    Rt = P.apply(R)
+    Pd = Rt.copy()
+    Dt = np.sum(R * Rt, axis=0)
+    DI = Dt.copy()
+    I = t = 0
+    stopper = _Stopper(o, n, d, nu, lam, half=False)
+    active = ~stopper.done(Dt, X, R, t)
+    forced = set()
+
+    while active.any():
+        if t >= o.max_iter:
+            info.status = "max_iter"
+            break
+        J = np.flatnonzero(active)
+        pJ = Pd[:, J]
+        Q = hess_apply(A, nu, lam, pJ)
+        info.a_passes += 1
+        pHp = np.sum(pJ * Q, axis=0)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            alpha = Dt[J] / pHp
+        Xp = X[:, J] + alpha * pJ
+        Rp = R[:, J] - alpha * Q
+        Rtp = P.apply(Rp)
+        Dp = np.sum(Rp * Rtp, axis=0)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            Pp = Rtp + (Dp / Dt[J]) * pJ
+        info.attempts += 1
+        if not (np.all(np.isfinite(alpha)) and np.all(np.isfinite(Dp))):
+            info.status = "nonfinite"
+            break
+        thr = log_c + (t + 1 - I) * log_phi
+        with np.errstate(divide="ignore"):
+            lr = np.where(Dp > 0, np.log(np.maximum(Dp, 1e-300)) - np.log(DI[J]), -np.inf)
+        fail = bool(np.any(lr > thr))
+        if o.adaptive and t in o.force_reject_at and t not in forced:
+            forced.add(t)
+            fail = True
+        info.trace.append(dict(t=t, m=m, k=k, log_ratio=lr.copy(), threshold=thr, accept=not fail or not o.adaptive or m >= m_cap))
+        if fail and o.adaptive and m < m_cap:
+            I = t
+            m = min(2 * m, m_cap)
+            k += 1
+            info.resketches += 1
+            try:
+                P = _sketch_factor(A, m, o, k, nu, lam)
+            except NotSPDError:
+                info.status = "not_spd"
+                break
+            xJ = X[:, J]
+            if np.any(xJ != 0):
+                R[:, J] = B[:, J] - hess_apply(A, nu, lam, xJ)
+                info.a_passes += 1
+            else:
+                R[:, J] = B[:, J]
+            Rt[:, J] = P.apply(R[:, J])
+            Pd[:, J] = Rt[:, J]
+            Dt[J] = np.sum(R[:, J] * Rt[:, J], axis=0)
+            DI[J] = Dt[J]
+            continue
+        if fail and o.adaptive:
+            info.m_cap_reached = True
+        X[:, J], R[:, J], Rt[:, J], Pd[:, J], Dt[J] = Xp, Rp, Rtp, Pp, Dp
+        t += 1
+        if o.keep_iterates:
+            info.trace[-1]["x"] = X.copy()
+        active[J] = ~stopper.done(Dt[J], X[:, J], R[:, J], t, J)
+
+    info.iterations = t
+    info.final_m = m
+    info.dtilde_final = Dt.copy()
+    return (X[:, 0] if squeeze else X), info
+
+
+def adaptive_ihs(A, b, nu, lam=None, opts=None):
+    """Adaptive IHS (Algorithm 1 with psi = IHS, mu = 1 - rho).  Returns (x, Info)."""
+    o = opts or Options(method="ihs")
+    A = np.asarray(A, dtype=np.float64)
+    n, d = A.shape
+    B, squeeze = _as2d(b)
+    c = B.shape[1]
+    lam = np.ones(d) if lam is None else np.asarray(lam, dtype=np.float64)
+    _validate(A, B, nu, lam, o)
+    info = Info()
+    phi, cc, mu = ihs_constants(o.rho)
+    log_phi, log_c = math.log(phi), math.log(cc)
+    m_cap = sk.max_sketch_size(n, o.sketch) if o.m_max <= 0 else min(o.m_max, sk.max_sketch_size(n, o.sketch))
+    m = min(o.m_init, m_cap)
+    k = 0
+    try:
+        P = _sketch_factor(A, m, o, k, nu, lam)
+    except NotSPDError:
+        info.status = "not_spd"
+        return (np.zeros(d) if squeeze else np.zeros((d, c))), info
+
+    X = np.zeros((d, c)) if o.x0 is None else np.array(o.x0, dtype=np.float64).reshape(d, c)
+    if np.any(X != 0):
+        G = hess_apply(A, nu, lam, X) - B
+        info.a_passes += 1
+    else:
+        G = -B.copy()
+    Sd = P.apply(G)
+    Dt = 0.5 * np.sum(G * Sd, axis=0)
+    DI = Dt.copy()
+    I = t = 0
+    stopper = _Stopper(o, n, d, nu, lam, half=True)
+    active = ~stopper.done(Dt, X, G, t)
+    forced = set()
+
+    while active.any():
+        if t >= o.max_iter:
+            info.status = "max_iter"
+            break
+        J = np.flatnonzero(active)
+        Xp = X[:, J] - mu * Sd[:, J]
+        Gp = hess_apply(A, nu, lam, Xp) - B[:, J]
+        info.a_passes += 1
+        Sp = P.apply(Gp)
+        Dp = 0.5 * np.sum(Gp * Sp, axis=0)
+        info.attempts += 1
+        if not np.all(np.isfinite(Dp)):
+            info.status = "nonfinite"
+            break
+        thr = log_c + (t + 1 - I) * log_phi
+        with np.errstate(divide="ignore"):
+            lr = np.where(Dp > 0, np.log(np.maximum(Dp, 1e-300)) - np.log(DI[J]), -np.inf)
+        fail = bool(np.any(lr > thr))
+        if o.adaptive and t in o.force_reject_at and t not in forced:
+            forced.add(t)
+            fail = True
+        info.trace.append(dict(t=t, m=m, k=k, log_ratio=lr.copy(), threshold=thr, accept=not fail or not o.adaptive or m >= m_cap))
+        if fail and o.adaptive and m < m_cap:
+            I = t
+            m = min(2 * m, m_cap)
+            k += 1
+            info.resketches += 1
+            try:
+                P = _sketch_factor(A, m, o, k, nu, lam)
+            except NotSPDError:
+                info.status = "not_spd"
+                break
+            Sd[:, J] = P.apply(G[:, J])
+            Dt[J] = 0.5 * np.sum(G[:, J] * Sd[:, J], axis=0)
+            DI[J] = Dt[J]
+            continue
+        if fail and o.adaptive:
+            info.m_cap_reached = True
+        X[:, J], G[:, J], Sd[:, J], Dt[J] = Xp, Gp, Sp, Dp
+        t += 1
+        if o.keep_iterates:
+            info.trace[-1]["x"] = X.copy()
+        active[J] = ~stopper.done(Dt[J], X[:, J], G[:, J], t, J)
+
+    info.iterations = t
+    info.final_m = m
+    info.dtilde_final = Dt.copy()
+    return (X[:, 0] if squeeze else X), info
+
+
+def solve(A, b, nu, lam=None, opts=None):
+    o = opts or Options()
+    return adaptive_ihs(A, b, nu, lam, o) if o.method == "ihs" else adaptive_pcg(A, b, nu, lam, o)

@@ -1,0 +1,45 @@
+"""Pins of the reference solution, the direct baseline and the effective dimension."""
+import numpy as np
+
+import synth
+from oracle import reference
+
+
+def test_reference_equals_dense_solve_tiny():
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((30, 5))
+    lam = 1 + rng.random(5)
+    b = rng.standard_normal(5)
+    H = A.T @ A + 0.3 ** 2 * np.diag(lam)
+    np.testing.assert_allclose(reference.reference_solution(A, b, 0.3, lam), np.linalg.solve(H, b), rtol=1e-14)
+    np.testing.assert_allclose(reference.direct_solve(A, b, 0.3, lam), np.linalg.solve(H, b), rtol=1e-13)
+
+
+def test_refinement_beats_direct_on_ill_conditioned():
+    P = synth.make_problem(2048, 128, "geo:0.9", 1e-4, seed=3)
+    A, b, nu = P["A"], P["b"], P["nu"]
+    xr, hist = reference.reference_solution(A, b, nu, return_history=True)
+    xs = reference.reference_solution(A, b, nu, spectral=(P["V"], P["sigma"]))
+    assert np.max(reference.rel_error(xs, xr)) < 1e-13
+    r_ref = np.abs(reference.residual_extended(A, b, nu, None, xr)).max()
+    r_dir = np.abs(reference.residual_extended(A, b, nu, None, reference.direct_solve(A, b, nu))).max()
+    assert r_ref < r_dir
+    assert hist[-1] < 1e-13  # kappa(H) ~ 8e7: long-double residual limits the last digits
+
+
+def test_effective_dimension_closed_form():
+    for nu in (1e-1, 1e-2, 1e-3):
+        P = synth.make_problem(1024, 96, "geo:0.95", nu, seed=1)
+        de = reference.effective_dimension(P["A"], nu)
+        assert abs(de - reference.effective_dimension_closed(P["sigma"], nu)) < 1e-8 * de
+        assert reference.effective_dimension_sum(P["sigma"], nu) <= de <= 96
+
+
+def test_residual_extended_matches_float_residual():
+    rng = np.random.default_rng(2)
+    A = rng.standard_normal((500, 20))
+    x = rng.standard_normal((20, 2))
+    b = rng.standard_normal((20, 2))
+    lam = 1 + rng.random(20)
+    r = reference.residual_extended(A, b, 0.1, lam, x, chunk=64).astype(np.float64)
+    np.testing.assert_allclose(r, b - A.T @ (A @ x) - 0.01 * lam[:, None] * x, rtol=1e-10, atol=1e-10)

@@ -1,0 +1,113 @@
+"""Pins of the oracle's SRHT and Gaussian embeddings (Sec. 2.1)."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import philox
+from oracle import sketch as sk
+
+
+@pytest.mark.parametrize("n", [1, 2, 8, 64, 1024])
+def test_fwht_equals_sylvester_hadamard(n):
+    X = np.random.default_rng(n).standard_normal((n, 5))
+    np.testing.assert_allclose(sk.fwht_rows(X), sla.hadamard(n) @ X, rtol=0, atol=1e-12 * n)
+
+
+def test_fwht_orthogonality_and_symmetry():
+    n = 256
+    H = sk.fwht_rows(np.eye(n))
+    np.testing.assert_array_equal(H, H.T)
+    np.testing.assert_array_equal(H @ H, n * np.eye(n))
+
+
+def test_fwht_bit_exact_on_integers():
+    n = 512
+    X = np.random.default_rng(0).integers(-1000, 1000, size=(n, 7)).astype(np.float64)
+    np.testing.assert_array_equal(sk.fwht_rows(X), (sla.hadamard(n).astype(np.int64) @ X.astype(np.int64)).astype(np.float64))
+
+
+def test_padded_size():
+    assert [sk.padded_size(v) for v in (1, 2, 3, 4, 5, 4096, 4097)] == [1, 2, 4, 4, 8, 4096, 8192]
+
+
+def test_srht_full_size_is_isometry():
+    # m = n' => S^T S = I_n' (the normalised Hadamard is orthogonal), so (SA)^T SA = A^T A.
+    rng = np.random.default_rng(1)
+    A = rng.standard_normal((100, 6))  # n' = 128: padding exercised
+    SA = sk.srht(A, 128, seed=4, k=0)
+    np.testing.assert_allclose(SA.T @ SA, A.T @ A, rtol=1e-12, atol=1e-12)
+
+
+def test_srht_matrix_form_and_rows():
+    rng = np.random.default_rng(2)
+    n, d, m = 37, 4, 9
+    A = rng.standard_normal((n, d))
+    SA = sk.srht(A, m, seed=11, k=3)
+    R = sk.srht_rows(11, 3, n, m)
+    assert len(set(R.tolist())) == m and np.all(np.diff(R) > 0) and R.max() < 64
+    eps = philox.signs(11, 3, n)
+    Hn = sla.hadamard(64)[R][:, :n]
+    S = Hn * eps[None, :] / np.sqrt(m)
+    np.testing.assert_allclose(SA, S @ A, rtol=1e-13, atol=1e-13)
+    for j in (0, 4, 8):
+        np.testing.assert_allclose(sk.srht_row(A, m, 11, 3, j), SA[j], rtol=1e-13, atol=1e-13)
+
+
+def _sts(kind, n, m, seed, k):
+    return np.array(sk.sketch(np.eye(n), m, kind, seed, k)).T @ np.array(sk.sketch(np.eye(n), m, kind, seed, k))
+
+
+@pytest.mark.parametrize("kind", ["srht", "gauss"])
+def test_sketch_unbiased(kind):
+    # E[S^T S] = I: average over independent sketch indices (Monte Carlo).
+    n, m, reps = 16, 4, 600
+    acc = np.zeros((n, n))
+    for k in range(reps):
+        SA = sk.sketch(np.eye(n), m, kind, seed=5, k=k)
+        acc += SA.T @ SA
+    acc /= reps
+    assert np.max(np.abs(acc - np.eye(n))) < 0.25
+    assert abs(np.trace(acc) / n - 1) < 0.05
+
+
+def test_srht_row_sample_uniform():
+    npad, m, reps = 32, 8, 4000
+    counts = np.zeros(npad)
+    for k in range(reps):
+        counts[sk.srht_rows(7, k, npad, m)] += 1
+    expected = reps * m / npad
+    chi2 = np.sum((counts - expected) ** 2 / expected)
+    from scipy import stats
+    assert stats.chi2.sf(chi2, npad - 1) > 1e-4
+
+
+def test_gaussian_sketch_matches_definition():
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((50, 3))
+    SA = sk.gaussian(A, 6, seed=2, k=1, chunk=16)
+    G = philox.gaussian_rows(2, 1, np.arange(6), 0, 50)
+    np.testing.assert_allclose(SA, G @ A / np.sqrt(6), rtol=1e-13, atol=1e-13)
+
+
+def test_gaussian_embedding_theorem_statistical():
+    # Gaussian concentration theorem: with m >= (sqrt(d_e) + sqrt(8 log(16/delta)))^2 / rho,
+    # eig(C_S - I) lies in ||D||^2 (-2 sqrt(rho) + rho, 2 sqrt(rho) + rho) w.p. >= 1 - delta.
+    from oracle.factor import SketchedHessian
+    rng = np.random.default_rng(4)
+    n, d, nu, rho, delta = 256, 6, 0.3, 0.5, 0.5
+    U, _ = np.linalg.qr(rng.standard_normal((n, d)))
+    sig = 0.7 ** np.arange(1, d + 1)
+    A = U * sig
+    H = A.T @ A + nu ** 2 * np.eye(d)
+    D2 = sig ** 2 / (sig ** 2 + nu ** 2)
+    de = D2.sum() / D2.max()
+    m = int(np.ceil((np.sqrt(de) + np.sqrt(8 * np.log(16 / delta))) ** 2 / rho))
+    w, V = np.linalg.eigh(H)
+    Hm12 = V @ np.diag(w ** -0.5) @ V.T
+    ok = 0
+    reps = 40
+    for k in range(reps):
+        HS = SketchedHessian(sk.gaussian(A, m, seed=8, k=k), nu, np.ones(d)).matrix()
+        ev = np.linalg.eigvalsh(Hm12 @ HS @ Hm12 - np.eye(d))
+        ok += (ev.min() >= D2.max() * (-2 * np.sqrt(rho) + rho)) and (ev.max() <= D2.max() * (2 * np.sqrt(rho) + rho))
+    assert ok / reps >= 1 - delta

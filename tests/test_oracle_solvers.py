@@ -1,0 +1,244 @@
+"""Pins of the oracle's adaptive PCG (Algorithm 2) and adaptive IHS (Algorithm 1)."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import reference, solvers
+from oracle import sketch as sk
+from oracle.factor import SketchedHessian
+
+
+def _tiny(n=64, d=8, nu=0.1, seed=0, lam=None):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, d)) * (0.6 ** np.arange(d))[None, :]
+    b = A.T @ rng.standard_normal(n)
+    lam = np.ones(d) if lam is None else lam
+    return A, b, nu, lam
+
+
+def _H(A, nu, lam):
+    return A.T @ A + nu ** 2 * np.diag(lam)
+
+
+def test_constants_limits():
+    # PCG rate phi(rho) ~ rho/4 for small rho and is below the IHS rate rho (Sec. 3.2).
+    for rho in (1e-4, 0.01, 0.125, 0.5):
+        phi, c = solvers.pcg_constants(rho)
+        assert 0 < phi < rho
+        assert c > 4
+    phi, c = solvers.pcg_constants(1e-6)
+    assert abs(phi / 1e-6 - 0.25) < 1e-3
+    assert abs(c - 4) < 0.02  # c(alpha, rho) -> alpha = 4, the constant of the PCG rate bound
+    phi_i, c_i, mu = solvers.ihs_constants(1e-6)
+    assert phi_i == 1e-6 and abs(c_i - 1) < 0.005 and mu == 1 - 1e-6
+
+
+def test_pcg_one_step_when_sketch_is_full():
+    A, b, nu, lam = _tiny(n=60, d=7)
+    o = solvers.Options(m_init=64, adaptive=False, stop="fixed", max_iter=1, seed=3)
+    x, info = solvers.adaptive_pcg(A, b, nu, lam, o)
+    xs = np.linalg.solve(_H(A, nu, lam), b)
+    assert info.iterations == 1
+    assert reference.rel_error(x, xs) < 1e-12
+
+
+@pytest.mark.parametrize("t", [1, 2, 3, 4, 5])
+def test_pcg_krylov_optimality(t):
+    # Theorem "rate cg": PCG's x_t minimises ||x - x*||_H over x_0 + K_t(H_S^{-1} H, H_S^{-1} r_0).
+    A, b, nu, lam = _tiny(n=64, d=10, nu=0.05, seed=1, lam=1 + np.arange(10) / 5)
+    m, seed = 6, 9
+    o = solvers.Options(m_init=m, adaptive=False, stop="fixed", max_iter=t, seed=seed)
+    x, _ = solvers.adaptive_pcg(A, b, nu, lam, o)
+    H = _H(A, nu, lam)
+    HS = SketchedHessian(sk.srht(A, m, seed, 0), nu, lam).matrix()
+    xs = np.linalg.solve(H, b)
+    M = np.linalg.solve(HS, H)
+    v = np.linalg.solve(HS, b)  # x_0 = 0 -> r_0 = b
+    K = np.stack([np.linalg.matrix_power(M, j) @ v for j in range(t)], axis=1)
+    Q, _ = np.linalg.qr(K)
+    c = np.linalg.solve(Q.T @ H @ Q, Q.T @ H @ xs)
+    xbest = Q @ c
+    assert reference.rel_error(x, xbest) < 1e-7
+
+
+def test_ihs_error_recursion():
+    # Proof of Theorem "rate IHS": x_{t+1} - x* = (I - mu H_S^{-1} H)(x_t - x*), mu = 1 - rho.
+    A, b, nu, lam = _tiny(n=64, d=8, nu=0.2, seed=2)
+    rho, m, seed = 0.2, 16, 4
+    H = _H(A, nu, lam)
+    HS = SketchedHessian(sk.srht(A, m, seed, 0), nu, lam).matrix()
+    xs = np.linalg.solve(H, b)
+    T = np.eye(8) - (1 - rho) * np.linalg.solve(HS, H)
+    e = -xs
+    for t in range(1, 5):
+        o = solvers.Options(method="ihs", rho=rho, m_init=m, adaptive=False, stop="fixed", max_iter=t, seed=seed)
+        x, _ = solvers.adaptive_ihs(A, b, nu, lam, o)
+        e = T @ e
+        np.testing.assert_allclose(x - xs, e, rtol=1e-8, atol=1e-11)
+
+
+def test_ihs_one_step_full_sketch_contracts_by_rho():
+    # With H_S = H the IHS error after one step is exactly rho (x_0 - x*) (mu = 1 - rho).
+    A, b, nu, lam = _tiny(n=30, d=5)
+    rho = 0.3
+    o = solvers.Options(method="ihs", rho=rho, m_init=32, adaptive=False, stop="fixed", max_iter=1)
+    x, _ = solvers.adaptive_ihs(A, b, nu, lam, o)
+    xs = np.linalg.solve(_H(A, nu, lam), b)
+    np.testing.assert_allclose(x - xs, rho * (0 - xs), rtol=1e-10, atol=1e-13)
+
+
+def test_decrement_bracket():
+    # Proof of the decrement lemma: delta/lambda_max(C_S) <= delta~ <= delta/lambda_min(C_S).
+    A, b, nu, lam = _tiny(n=128, d=9, nu=0.05, seed=5)
+    H = _H(A, nu, lam)
+    xs = np.linalg.solve(H, b)
+    P = SketchedHessian(sk.srht(A, 12, 2, 0), nu, lam)
+    w, V = np.linalg.eigh(H)
+    Hh = V @ np.diag(w ** -0.5) @ V.T
+    cs = np.linalg.eigvalsh(Hh @ P.matrix() @ Hh)
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        x = rng.standard_normal(9)
+        g = H @ x - b
+        dt = 0.5 * g @ P.apply(g)
+        dl = 0.5 * (x - xs) @ H @ (x - xs)
+        assert dl / cs.max() * (1 - 1e-10) <= dt <= dl / cs.min() * (1 + 1e-10)
+
+
+@pytest.fixture(scope="module")
+def small():
+    P = synth.make_workload("pcg_n4096_d256", seed=0)
+    P["xref"] = reference.reference_solution(P["A"], P["b"], P["nu"], P["lam"])
+    return P
+
+
+@pytest.mark.parametrize("method", ["pcg", "ihs"])
+@pytest.mark.parametrize("kind", ["srht", "gauss"])
+def test_solution_accuracy(small, method, kind):
+    if kind == "gauss" and method == "ihs":
+        pytest.skip("covered by pcg/gauss; keeps the CPU suite short")
+    o = solvers.Options(method=method, sketch=kind, m_init=8, tol=1e-10, seed=1)
+    x, info = solvers.solve(small["A"], small["b"], small["nu"], small["lam"], o)
+    assert info.status == "ok"
+    assert reference.rel_error(x, small["xref"]) <= 1e-10
+    assert info.final_m <= sk.padded_size(4096)
+
+
+def test_adaptive_invariants(small):
+    o = solvers.Options(m_init=8, seed=2)
+    x, info = solvers.adaptive_pcg(small["A"], small["b"], small["nu"], small["lam"], o)
+    tr = info.trace
+    ms = [e["m"] for e in tr]
+    assert all(m2 >= m1 for m1, m2 in zip(ms, ms[1:]))
+    assert all(math.log2(m / 8).is_integer() for m in ms)
+    assert info.resketches <= math.ceil(math.log2(4096 / 8))
+    for a, b_ in zip(tr, tr[1:]):
+        if a["accept"]:
+            assert np.max(a["log_ratio"]) <= a["threshold"] or a["m"] == 4096
+            assert b_["t"] == a["t"] + 1 and b_["m"] == a["m"]
+        else:
+            assert np.max(a["log_ratio"]) > a["threshold"]
+            assert b_["t"] == a["t"] and b_["m"] == 2 * a["m"]
+    # one pass per candidate step plus one explicit residual per rejection at x_t != 0
+    rej_nonzero = sum(1 for e in tr if not e["accept"] and e["t"] > 0)
+    assert info.a_passes == info.attempts + rej_nonzero
+
+
+def test_forced_rejection_restarts(small):
+    A, b, nu, lam = small["A"], small["b"], small["nu"], small["lam"]
+    o = solvers.Options(m_init=1024, seed=2, force_reject_at=(3,))
+    x, info = solvers.adaptive_pcg(A, b, nu, lam, o)
+    t3 = [e for e in info.trace if e["t"] == 3]
+    assert not t3[0]["accept"] and t3[1]["m"] == 2048
+    assert info.a_passes == info.attempts + 1
+    assert reference.rel_error(x, small["xref"]) <= 1e-10
+
+
+def test_linear_decay_after_last_resize(small):
+    # Condition "linear convergence" for PCG (eq. "rate pcg"): once the sketch satisfies the
+    # embedding event, delta_t <= 4 phi^(t - T0) delta_T0.
+    A, b, nu, lam = small["A"], small["b"], small["nu"], small["lam"]
+    o = solvers.Options(m_init=8, seed=1, keep_iterates=True)
+    x, info = solvers.adaptive_pcg(A, b, nu, lam, o)
+    acc = [e for e in info.trace if e["accept"] and "x" in e]
+    mfin = info.final_m
+    it = [e for e in acc if e["m"] == mfin]
+    xs = small["xref"]
+    dl = [float(reference.h_norm_error(A, nu, lam, e["x"][:, 0], xs)) for e in it]
+    d0 = dl[0]
+    # embedding event of the final sketch
+    H = _H(A, nu, lam)
+    w, V = np.linalg.eigh(H)
+    Hh = V @ np.diag(w ** -0.5) @ V.T
+    k_last = it[0]["k"]
+    HS = SketchedHessian(sk.srht(A, mfin, 1, k_last), nu, lam).matrix()
+    dev = np.max(np.abs(np.linalg.eigvalsh(Hh @ HS @ Hh) - 1))
+    rho_eff = max(dev ** 2, 1e-6) if dev < 1 else None
+    assert rho_eff is not None
+    phi, _ = solvers.pcg_constants(rho_eff)
+    for j, dj in enumerate(dl):
+        if reference.rel_error(it[j]["x"][:, 0], xs) < 1e-12:
+            break
+        assert dj <= 4 * phi ** j * d0 * (1 + 1e-6)
+    # and the decay is geometric: at least 5x per step on average
+    n_use = max(2, min(len(dl), 6))
+    assert (dl[n_use - 1] / dl[0]) ** (1 / (n_use - 1)) < 0.2
+
+
+def test_m_tracks_effective_dimension():
+    # Adaptivity theorem / Sec. 5: the final sketch size follows d_e (not d) as nu varies.
+    res = []
+    for i, nu in enumerate((1e-1, 1e-2, 1e-3)):
+        P = synth.make_problem(8192, 256, "geo:0.98", nu, seed=40 + i)
+        de = reference.effective_dimension_closed(P["sigma"], nu)
+        o = solvers.Options(m_init=1, seed=7, tol=1e-8)
+        x, info = solvers.adaptive_pcg(P["A"], P["b"], nu, None, o)
+        assert info.status == "ok"
+        res.append((de, info.final_m))
+    des = [r[0] for r in res]
+    ms = [r[1] for r in res]
+    assert des == sorted(des)
+    assert ms == sorted(ms)
+    for de, m in res:
+        assert m < 8192
+        assert 1 <= m / de <= 64
+
+
+def test_multiple_rhs_and_equivalence(small):
+    A, nu, lam = small["A"], small["nu"], small["lam"]
+    rng = np.random.default_rng(5)
+    B = A.T @ rng.standard_normal((A.shape[0], 3))
+    o = solvers.Options(m_init=8, seed=4)
+    X, info = solvers.adaptive_pcg(A, B, nu, lam, o)
+    Xr = reference.reference_solution(A, B, nu, lam)
+    assert np.all(reference.rel_error(X, Xr) <= 1e-10)
+    x1, i1 = solvers.adaptive_pcg(A, B[:, 0], nu, lam, o)
+    x2, i2 = solvers.adaptive_pcg(A, B[:, :1], nu, lam, o)
+    np.testing.assert_array_equal(x1, x2[:, 0])
+    assert i1.iterations == i2.iterations and i1.final_m == i2.final_m
+
+
+def test_stop_rules_and_status(small):
+    A, b, nu, lam = small["A"], small["b"], small["nu"], small["lam"]
+    for stop in ("dtilde_rel", "remark"):
+        o = solvers.Options(m_init=8, seed=1, stop=stop, tol=1e-12 if stop == "remark" else 1e-9)
+        x, info = solvers.adaptive_pcg(A, b, nu, lam, o)
+        assert info.status == "ok" and info.iterations > 0
+    o = solvers.Options(m_init=8, seed=1, stop="fixed", max_iter=5)
+    x, info = solvers.adaptive_pcg(A, b, nu, lam, o)
+    assert info.status == "ok" and info.iterations == 5
+    o = solvers.Options(m_init=8, seed=1, max_iter=3)
+    x, info = solvers.adaptive_pcg(A, b, nu, lam, o)
+    assert info.status == "max_iter" and info.iterations == 3
+    x, info = solvers.adaptive_pcg(A, np.zeros(A.shape[1]), nu, lam, solvers.Options(m_init=8))
+    assert info.iterations == 0 and not np.any(x)
+
+
+def test_validation():
+    A, b, nu, lam = _tiny()
+    for kw, args in [({}, (A, b, 0.0, lam)), ({}, (A, b, nu, -lam)), ({"rho": 1.0}, (A, b, nu, lam)),
+                     ({"m_init": 0}, (A, b, nu, lam))]:
+        with pytest.raises(ValueError):
+            solvers.adaptive_pcg(*args, solvers.Options(**kw))
