@@ -1,0 +1,222 @@
+/*
+ * aes.h -- C ABI of the adaptive sketching-based least-squares solver for MI355X (gfx950).
+ *
+ * Problem (Lacotte & Pilanci, arXiv 2104.14101, eq. "main optimization problem"):
+ *     x* = argmin_x  1/2 x^T H x - b^T x,     H = A^T A + nu^2 Lambda,
+ * with A in R^{n x d} dense, b in R^{d} (or R^{d x c}: c right-hand sides, the "matrix
+ * variables" of Sec. 5), Lambda = diag(lambda) with lambda_i > 0, nu > 0.
+ *
+ * Conventions for every entry point
+ *   - Matrices are row-major.  A is n x d with leading dimension lda >= d (elements).
+ *     Right-hand sides and solutions are d x c with leading dimension ldb / ldx >= c; for
+ *     c = 1 pass ld = 1 (a contiguous vector).
+ *   - Pointers documented "device" are caller-owned HBM buffers on the handle's device; the
+ *     library reads/writes them only during the call and never retains them, except an
+ *     aes_ctx, which keeps a non-owning pointer to A until aes_ctx_free (A must stay valid and
+ *     unchanged until then).  Pointers documented "host" are ordinary host memory.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.  All device work
+ *     is enqueued on it.  The solve entry points block until their result is complete
+ *     (the adaptive loop takes one host decision per iteration); the kernel-level entry points
+ *     (aes_hv, aes_sketch, ...) are asynchronous on `stream`.
+ *   - Errors are returned as aes_status; no C++ exception crosses the ABI.  A message for
+ *     the last error on a handle is available from aes_last_error.  On AES_ERR_INVALID_ARG no
+ *     output buffer has been written.
+ *   - Random numbers: Philox4x64-10 keyed by (seed, (problem << 32) | k), k = index of the
+ *     sketch within a solve; see the sketch entry points for the streams.
+ */
+#ifndef AES_H
+#define AES_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct aes_handle_s* aes_handle; /* device workspace pool; use from one host thread */
+typedef struct aes_ctx_s* aes_ctx;       /* kept sketch + factor for adjoint solves */
+
+typedef enum {
+  AES_OK = 0,
+  AES_ERR_INVALID_ARG = 1,  /* a size, pointer or option is out of range */
+  AES_ERR_NOT_SPD = 2,      /* a Cholesky pivot of H_S (or W_S) was <= 0 or NaN */
+  AES_ERR_NONFINITE = 3,    /* a step length or decrement became NaN/Inf */
+  AES_ERR_MAX_ITER = 4,     /* max_iter accepted steps without meeting the stop rule;
+                               x holds the last accepted iterate */
+  AES_ERR_HIP = 5,          /* a HIP runtime call failed */
+  AES_ERR_OOM = 6,          /* device workspace allocation failed */
+  AES_ERR_NOT_IMPLEMENTED = 7
+} aes_status;
+
+typedef enum { AES_PCG = 0, AES_IHS = 1 } aes_method;
+typedef enum { AES_SRHT = 0, AES_GAUSS = 1 } aes_sketch_kind;
+typedef enum {
+  AES_FP64 = 0,   /* every step in FP64 */
+  AES_MIXED = 1   /* BF16 sketch + BF16 MFMA Gram (FP32 accumulation), FP32-stored A for
+                     the PCG matvecs (FP64 accumulation), FP64 Cholesky, FP64 scalars, FP64
+                     residual refinement */
+} aes_precision;
+typedef enum {
+  AES_STOP_XREL = 0,       /* (1+sqrt rho) D_t <= nu^2 min(lambda) tol^2 ||x_t||^2 (D = r^T H_S^-1 r) */
+  AES_STOP_DTILDE_REL = 1, /* D_t <= tol^2 D_0 */
+  AES_STOP_FIXED = 2,      /* exactly max_iter accepted steps */
+  AES_STOP_REMARK = 3      /* 1/2 D_t <= tol / (m_delta + 1), Remark on termination, d_e := d */
+} aes_stop_rule;
+
+/* One attempted step of the adaptive loop (the axes of the paper's plots). */
+typedef struct {
+  int64_t t;          /* accepted-step counter before the attempt */
+  int64_t m;          /* sketch size used by the attempt */
+  int64_t k;          /* sketch index */
+  double log_ratio;   /* max over active columns of log(D+ / D_I) */
+  double threshold;   /* log c + (t+1-I) log phi */
+  int32_t accept;
+  int32_t pad_;
+} aes_trace_entry;
+
+typedef struct {
+  int32_t method;        /* aes_method, default AES_PCG */
+  int32_t sketch;        /* aes_sketch_kind, default AES_SRHT */
+  int32_t precision;     /* aes_precision, default AES_FP64 */
+  int32_t stop;          /* aes_stop_rule, default AES_STOP_XREL */
+  double rho;            /* in (0,1), default 1/8 */
+  int64_t m_init;        /* >= 1, default 1 */
+  int64_t m_max;         /* cap on m; <= 0 means n' = 2^ceil(log2 n) */
+  int64_t max_iter;      /* cap on accepted steps, default 200 */
+  uint64_t seed;         /* Philox key word 0, default 0 */
+  int32_t problem;       /* Philox stream id of the problem (key word 1 high half) */
+  int32_t adaptive;      /* 1 (default): Algorithm 1/2; 0: fixed m = m_init, no test */
+  int64_t force_reject_at;  /* test hook: reject the first candidate step at this t; -1 none */
+  double inner_tol;      /* AES_MIXED: relative tolerance of each inner solve, default 1e-6 */
+  int32_t max_refine;    /* AES_MIXED: cap on refinement sweeps, default 20 */
+  int32_t trace_cap;     /* capacity of `trace` (entries) */
+  aes_trace_entry* trace;   /* host, optional: filled with the attempted steps */
+  const double* x0;         /* device d x c (ld = ldx) initial point, or NULL for 0 */
+} aes_options;
+
+typedef struct {
+  int64_t iterations;     /* accepted steps t (summed over sweeps for AES_MIXED) */
+  int64_t attempts;       /* candidate steps (accepted + rejected) */
+  int64_t final_m;        /* sketch size at exit */
+  int64_t resketches;     /* number of times m was doubled */
+  int64_t a_passes;       /* passes over A (H.v products and explicit residuals) */
+  int64_t refine_sweeps;  /* AES_MIXED: outer refinement sweeps */
+  int64_t trace_len;      /* entries written to options.trace (<= trace_cap) */
+  double dtilde_final;    /* max over columns of the final decrement D */
+  double time_sketch_ms;  /* host-measured wall time in sketch + factor phases */
+  double time_total_ms;   /* host-measured wall time of the call */
+  int32_t m_cap_reached;  /* a failed test was accepted because m reached its cap */
+  int32_t status;         /* aes_status of the solve */
+} aes_info;
+
+/* Create a handle bound to HIP device `device` (allocates nothing large). */
+aes_status aes_create(aes_handle* h, int device);
+/* Release the handle and all its device workspace. */
+aes_status aes_destroy(aes_handle h);
+/* Message of the last error on `h` (static storage owned by the handle). */
+const char* aes_last_error(aes_handle h);
+/* Default options: PCG, SRHT, FP64, XREL, rho = 1/8, m_init = 1, max_iter = 200. */
+void aes_default_options(aes_options* o);
+
+/*
+ * aes_solve -- adaptive PCG (Algorithm 2) or adaptive IHS (Algorithm 1 with the IHS update,
+ * step mu = 1 - rho of Theorem "rate IHS") for H x = b with the sketched preconditioner
+ * H_S = (SA)^T SA + nu^2 Lambda, factorised as in Sec. 4.1 (Cholesky of H_S for m >= d,
+ * Woodbury form with the Cholesky of W_S for m < d).  When the improvement test of the
+ * algorithm fails, m doubles, a fresh S is drawn and the method restarts at x_t.
+ *   A       device, n x d, row-major, lda >= d
+ *   b       device, d x c, ldb >= c
+ *   lambda  device, length d, all > 0; NULL means Lambda = I
+ *   x       device, d x c output, ldx >= c
+ *   info    host, output (may be NULL)
+ * Returns AES_OK, or AES_ERR_MAX_ITER / NOT_SPD / NONFINITE with x = last accepted iterate.
+ */
+aes_status aes_solve(aes_handle h, void* stream, int64_t n, int64_t d, int64_t c,
+                     const double* A, int64_t lda, const double* b, int64_t ldb, double nu,
+                     const double* lambda, double tol, const aes_options* opt, double* x,
+                     int64_t ldx, aes_info* info);
+
+/* One problem of a batch (all pointers device, layouts as in aes_solve). */
+typedef struct {
+  int64_t n, d, c;
+  const double* A;
+  int64_t lda;
+  const double* b;
+  int64_t ldb;
+  double nu;
+  const double* lambda;
+  double* x;
+  int64_t ldx;
+} aes_problem;
+
+/*
+ * aes_solve_batched -- solves nprob independent problems (each with c right-hand sides that
+ * share the problem's sketch, Sec. 5 "matrix variables").  Problem p draws its sketches from
+ * Philox stream id p.  probs and infos are host arrays of length nprob.
+ */
+aes_status aes_solve_batched(aes_handle h, void* stream, int64_t nprob, const aes_problem* probs,
+                             double tol, const aes_options* opt, aes_info* infos);
+
+/*
+ * aes_solve_keep -- as aes_solve (single problem) and additionally returns a context holding
+ * the last sketch, its factorisation and x*, for adjoint solves with the same H_S.
+ */
+aes_status aes_solve_keep(aes_handle h, void* stream, int64_t n, int64_t d, int64_t c,
+                          const double* A, int64_t lda, const double* b, int64_t ldb, double nu,
+                          const double* lambda, double tol, const aes_options* opt, double* x,
+                          int64_t ldx, aes_info* info, aes_ctx* ctx);
+
+/*
+ * aes_adjoint_solve -- solves H lam = g (H symmetric) by adaptive PCG starting from the
+ * context's sketch size and factorisation (resketching only if the improvement test fails).
+ *   g    device, d x c (ld = c);   lam  device, d x c output (ld = c)
+ */
+aes_status aes_adjoint_solve(aes_ctx ctx, void* stream, const double* g, double tol,
+                             double* lam, aes_info* info);
+
+/*
+ * aes_grad -- gradients of L(x*) given the adjoint lam = H^{-1} dL/dx* (single column):
+ *   dA = -(A x*) lam^T - (A lam) x*^T   (device n x d, ld = d; NULL to skip)
+ *   dlognu = -2 nu^2 lam^T Lambda x*     (host scalar; NULL to skip)
+ * db equals lam and is not computed here.
+ */
+aes_status aes_grad(aes_ctx ctx, void* stream, const double* lam, double* dA, double* dlognu);
+
+void aes_ctx_free(aes_ctx ctx);
+
+/*
+ * Kernel-level entry points (asynchronous on `stream`; used by the parity tests).
+ */
+
+/* q = A^T (A p) + nu^2 lambda .* p  and  pHp = ||A p||^2 + nu^2 p^T Lambda p   (single pass
+ * over A; the per-iteration product of Sec. 4.1 "Per-iteration cost").
+ *   p, q: device length d.  pHp: device, 1 double.  lambda: device or NULL. */
+aes_status aes_hv(aes_handle h, void* stream, int64_t n, int64_t d, const double* A, int64_t lda,
+                  double nu, const double* lambda, const double* p, double* q, double* pHp);
+
+/* SA for sketch index k of size m (Sec. 2.1).  kind AES_SRHT: SA = (1/sqrt m) R H E A_pad,
+ * H the unnormalised Sylvester Walsh-Hadamard matrix of order n' = 2^ceil(log2 n), E the
+ * signs of stream SIGN, R the m padded rows with the smallest ROW keys (ascending order);
+ * kind AES_GAUSS: SA = G A / sqrt m with G from stream GAUSS by Box-Muller.
+ *   SA: device, m x d output (ld = d).  1 <= m <= n'. */
+aes_status aes_sketch(aes_handle h, void* stream, int kind, int64_t n, int64_t d, const double* A,
+                      int64_t lda, int64_t m, uint64_t seed, int32_t problem, int64_t k, double* SA);
+
+/* Factorisation of H_S from SA (Sec. 4.1).  For m >= d writes G = SA^T SA + nu^2 Lambda and
+ * its lower Cholesky factor L (both d x d, ld = d) to `G` and `L`; for m < d writes
+ * W = SA Lambda^-1 SA^T + nu^2 I_m and L_W (m x m, ld = m).  Returns AES_ERR_NOT_SPD if a
+ * pivot fails (synchronises the stream to read the flag). */
+aes_status aes_factor(aes_handle h, void* stream, int64_t m, int64_t d, const double* SA, double nu,
+                      const double* lambda, double* G, double* L);
+
+/* v = H_S^{-1} z for the sketch SA (m x d), by the factorisation of Sec. 4.1 (builds it; the
+ * solvers cache it instead).  z, v: device d x c (ld = c). */
+aes_status aes_precond_apply(aes_handle h, void* stream, int64_t m, int64_t d, int64_t c,
+                             const double* SA, double nu, const double* lambda, const double* z,
+                             double* v);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AES_H */

@@ -1,0 +1,993 @@
+// Host engine behind the C ABI: workspace pool, the adaptive PCG / IHS loops (Algorithm 2,
+// Algorithm 1 with the IHS update), the cached factorisation of H_S (Sec. 4.1), the
+// mixed-precision refinement driver, batched solves, and the kept context for adjoint solves.
+//
+// Control: every device step is enqueued on the caller's stream; the host reads back one
+// small block of flags per attempted step (accepted / rejected / stopped), because the
+// accept-or-resketch decision of the algorithms is data dependent.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "aes.h"
+#include "common.h"
+#include "kernels.h"
+
+using namespace aes;
+
+// ---------------------------------------------------------------------------------------
+// Handle and workspace.
+// ---------------------------------------------------------------------------------------
+struct aes_handle_s {
+  int device = 0;
+  int num_cu = 256;
+  std::unordered_map<std::string, std::pair<void*, size_t>> bufs;
+  std::string err;
+  double* pinned = nullptr;  // host-visible flag block
+
+  template <typename T>
+  T* buf(const std::string& name, size_t count) {
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    auto it = bufs.find(name);
+    if (it != bufs.end() && it->second.second >= bytes) return static_cast<T*>(it->second.first);
+    if (it != bufs.end()) {
+      AES_HIP(hipFree(it->second.first));
+      bufs.erase(it);
+    }
+    void* p = nullptr;
+    const size_t alloc = (bytes + 255) / 256 * 256;
+    hipError_t e = hipMalloc(&p, alloc);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw std::bad_alloc();
+    }
+    bufs[name] = {p, alloc};
+    return static_cast<T*>(p);
+  }
+  void release() {
+    for (auto& kv : bufs) (void)hipFree(kv.second.first);
+    bufs.clear();
+    if (pinned) (void)hipHostFree(pinned);
+    pinned = nullptr;
+  }
+};
+
+struct aes_ctx_s {
+  aes_handle h = nullptr;  // private workspace holding the kept factorisation
+  int64_t n = 0, d = 0, lda = 0;
+  const double* A = nullptr;
+  double nu = 0;
+  bool has_lambda = false;
+  aes_options opt{};
+  int64_t m = 0, k = 0;
+  double* xstar = nullptr;  // device, d (owned by h's pool: "ctx_xstar")
+};
+
+namespace {
+
+struct StatusError : std::runtime_error {
+  aes_status st;
+  StatusError(aes_status s, const std::string& m) : std::runtime_error(m), st(s) {}
+};
+
+inline double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct ProblemDesc {
+  int64_t n, d, c;
+  const double* A;
+  int64_t lda;
+  const double* b;
+  int64_t ldb;
+  double nu;
+  const double* lambda;
+  double* x;
+  int64_t ldx;
+};
+
+void validate(const ProblemDesc& P, double tol, const aes_options& o) {
+  auto bad = [](const char* m) { throw StatusError(AES_ERR_INVALID_ARG, m); };
+  if (P.n < 1 || P.d < 1 || P.c < 1) bad("n, d and c must be >= 1");
+  if (P.c > 32) bad("at most 32 right-hand sides per problem");
+  if (P.d > 8192) bad("d > 8192 is not supported");
+  if (P.lda < P.d) bad("lda < d");
+  if (P.ldb < P.c || P.ldx < P.c) bad("ldb and ldx must be >= c");
+  if (!P.A || !P.b || !P.x) bad("A, b and x must be non-null");
+  if (!(std::isfinite(P.nu) && P.nu > 0)) bad("nu must be finite and > 0");
+  if (!(o.rho > 0.0 && o.rho < 1.0)) bad("rho must lie in (0, 1)");
+  if (o.m_init < 1) bad("m_init must be >= 1");
+  if (o.stop != AES_STOP_FIXED && !(tol > 0)) bad("tol must be > 0");
+  if (o.method != AES_PCG && o.method != AES_IHS) bad("unknown method");
+  if (o.sketch != AES_SRHT && o.sketch != AES_GAUSS) bad("unknown sketch");
+  if (o.precision != AES_FP64 && o.precision != AES_MIXED) bad("unknown precision");
+  if (o.stop < 0 || o.stop > 3) bad("unknown stop rule");
+  if (o.max_iter < 0) bad("max_iter must be >= 0");
+}
+
+double remark_m_delta(int64_t n, int64_t d) {
+  const double de = (double)d, delta = 1.0 / (double)d;
+  const double t = std::sqrt(de) + std::sqrt(8.0 * std::log(2.0 * (double)n / delta));
+  return 16.0 * std::log(16.0 * de / delta) * t * t;
+}
+
+// ---------------------------------------------------------------------------------------
+// Solver: one problem, C (power of two) internal columns.
+// ---------------------------------------------------------------------------------------
+class Solver {
+ public:
+  Solver(aes_handle h, hipStream_t s, const ProblemDesc& P, const aes_options& o, double tol, const std::string& ns)
+      : h_(h), s_(s), P_(P), o_(o), tol_(tol), ns_(ns) {
+    n_ = P.n;
+    d_ = P.d;
+    c_ = P.c;
+    C_ = (int)next_pow2(P.c);
+    npad_ = next_pow2(n_);
+    mcap_ = o.m_max > 0 ? std::min<int64_t>(o.m_max, npad_) : npad_;
+    nu2_ = P.nu * P.nu;
+    mixed_ = o.precision == AES_MIXED;
+    if (mixed_ && C_ > 1) throw StatusError(AES_ERR_NOT_IMPLEMENTED, "mixed precision supports c = 1");
+  }
+
+  // Buffers in the handle pool, namespaced per solver role.
+  template <typename T>
+  T* B(const char* name, size_t count) {
+    return h_->buf<T>(ns_ + name, count);
+  }
+
+  void setup_common() {
+    const int64_t dc = d_ * C_;
+    lam_ = B<double>("lam", d_);
+    invlam_ = B<double>("invlam", d_);
+    if (P_.lambda) {
+      AES_HIP(hipMemcpyAsync(lam_, P_.lambda, d_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
+      launch_inv(d_, P_.lambda, invlam_, s_);
+    } else {
+      launch_fill(lam_, d_, 1.0, s_);
+      launch_fill(invlam_, d_, 1.0, s_);
+    }
+    X_ = B<double>("X", dc);
+    R_ = B<double>("R", dc);
+    Pv_ = B<double>("P", dc);
+    Q_ = B<double>("Q", dc);
+    XP_ = B<double>("XP", dc);
+    RP_ = B<double>("RP", dc);
+    RTP_ = B<double>("RTP", dc);
+    Bv_ = B<double>("B", dc);
+    scal_ = B<double>("scal", 8 * C_ + 8);
+    active_ = B<int>("active", C_);
+    nwg_ = hv_num_blocks(h_->num_cu, n_);
+    if (C_ == 1) {
+      part_ = B<double>("part", (size_t)nwg_ * d_);
+      spart_ = B<double>("spart", nwg_);
+    } else {
+      const int64_t split_rows = std::max<int64_t>(4096, ceil_div(n_, 64));
+      msplit_ = (int)ceil_div(n_, split_rows);
+      msplit_rows_ = split_rows;
+      part_ = B<double>("part", (size_t)msplit_ * d_ * C_);
+      Z_ = B<double>("Z", (size_t)n_ * C_);
+    }
+    AES_HIP(hipMemsetAsync(scal_, 0, (8 * C_ + 8) * sizeof(double), s_));
+    launch_copy_cols(d_, C_, P_.b, P_.ldb, (int)c_, Bv_, C_, s_);
+    std::vector<int> act(C_, 0);
+    for (int j = 0; j < c_; ++j) act[j] = 1;
+    AES_HIP(hipMemcpyAsync(active_, act.data(), C_ * sizeof(int), hipMemcpyHostToDevice, s_));
+    if (mixed_) {
+      A32_ = B<float>("A32", (size_t)n_ * d_);
+      A16_ = B<__hip_bfloat16>("A16", (size_t)n_ * d_);
+      launch_cast2(n_, d_, P_.A, P_.lda, A32_, A16_, s_);
+    }
+    stop_scale_ = nu2_ * min_lambda() * tol_ * tol_;
+    if (o_.stop == AES_STOP_REMARK) stop_scale_ = tol_ / (remark_m_delta(n_, d_) + 1.0);
+    stop_sr_ = 1.0 + std::sqrt(o_.rho);
+    tol2_ = tol_ * tol_;
+  }
+
+  double min_lambda() {
+    if (!P_.lambda) return 1.0;
+    std::vector<double> hl(d_);
+    AES_HIP(hipMemcpyAsync(hl.data(), P_.lambda, d_ * sizeof(double), hipMemcpyDeviceToHost, s_));
+    AES_HIP(hipStreamSynchronize(s_));
+    double mn = hl[0];
+    for (double v : hl) {
+      if (!(v > 0) || !std::isfinite(v)) throw StatusError(AES_ERR_INVALID_ARG, "lambda entries must be finite and > 0");
+      mn = std::min(mn, v);
+    }
+    return mn;
+  }
+
+  // out = sgn * (H v) + bsgn * b    (H = A^T A + nu^2 Lambda); A in FP64 or (inner) FP32.
+  void hv(const double* v, double* out, double sgn, const double* bb, double bsgn, bool use32) {
+    if (C_ == 1) {
+      if (use32)
+        launch_hv_fused<float>(A32_, n_, d_, d_, v, part_, spart_, nwg_, s_);
+      else
+        launch_hv_fused<double>(P_.A, n_, d_, P_.lda, v, part_, spart_, nwg_, s_);
+      launch_hv_colsum(part_, nwg_, d_, 1, v, lam_, nu2_, sgn, bb, bsgn, out, s_);
+    } else {
+      // Z = A V (n x C); partial Q_w = A_w^T Z_w over row splits; fixed-order column sum.
+      gemm_f64(false, false, n_, C_, d_, 1.0, P_.A, P_.lda, 0, v, C_, 0, 0.0, Z_, C_, 0, 1, 0, s_);
+      const int full = (int)(n_ / msplit_rows_);
+      if (full > 0)
+        gemm_f64(true, false, d_, C_, msplit_rows_, 1.0, P_.A, P_.lda, msplit_rows_ * P_.lda, Z_, C_,
+                 msplit_rows_ * C_, 0.0, part_, C_, d_ * C_, full, 0, s_);
+      const int64_t tail = n_ - (int64_t)full * msplit_rows_;
+      int used = full;
+      if (tail > 0) {
+        gemm_f64(true, false, d_, C_, tail, 1.0, P_.A + (int64_t)full * msplit_rows_ * P_.lda, P_.lda, 0,
+                 Z_ + (int64_t)full * msplit_rows_ * C_, C_, 0, 0.0, part_ + (int64_t)full * d_ * C_, C_, 0, 1, 0, s_);
+        ++used;
+      }
+      launch_hv_colsum(part_, used, d_, C_, v, lam_, nu2_, sgn, bb, bsgn, out, s_);
+    }
+    ++a_passes_;
+  }
+
+  // ---- sketch + factorisation of H_S (Sec. 4.1) ----------------------------------------
+  void sketch_factor() {
+    const double t0 = now_ms();
+    const bool bf = mixed_ && o_.sketch == AES_SRHT;
+    woodbury_ = m_ < d_;
+    if (bf) {
+      SA16_ = B<__hip_bfloat16>("SA16", (size_t)m_ * d_);
+    } else {
+      SA_ = B<double>("SA", (size_t)m_ * d_);
+    }
+    if (o_.sketch == AES_SRHT) {
+      double* eps = B<double>("eps", n_);
+      launch_signs(o_.seed, o_.problem, k_, n_, eps, s_);
+      SelectScratch sc;
+      sc.keys = B<uint64_t>("sel_keys", npad_);
+      sc.pos = B<int32_t>("sel_pos", npad_);
+      sc.hist = B<uint32_t>("sel_hist", 256 * 8);
+      sc.state = B<uint64_t>("sel_state", 4);
+      sc.blk = B<uint32_t>("sel_blk", 2 * select_blocks(npad_));
+      launch_srht_select(o_.seed, o_.problem, k_, npad_, m_, sc, s_);
+      if (bf) {
+        float* Y = B<float>("Y32", (size_t)npad_ * d_);
+        launch_srht_apply<__hip_bfloat16, float, __hip_bfloat16>(A16_, n_, d_, d_, eps, npad_, sc.pos, m_, Y, SA16_, d_,
+                                                                 s_);
+      } else {
+        double* Y = B<double>("Y", (size_t)npad_ * d_);
+        launch_srht_apply<double, double, double>(P_.A, n_, d_, P_.lda, eps, npad_, sc.pos, m_, Y, SA_, d_, s_);
+      }
+    } else {
+      launch_gauss_sketch(P_.A, n_, d_, P_.lda, m_, o_.seed, o_.problem, k_, SA_, d_, s_);
+    }
+    int* flag = B<int>("chol_flag", 1);
+    AES_HIP(hipMemsetAsync(flag, 0, sizeof(int), s_));
+    factor_from_sa(bf, flag);
+    int hflag = 0;
+    AES_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s_));
+    AES_HIP(hipStreamSynchronize(s_));
+    t_sketch_ += now_ms() - t0;
+    if (hflag) throw StatusError(AES_ERR_NOT_SPD, "Cholesky pivot of the sketched Hessian is not positive");
+  }
+
+  // Gram of the current sketch, its Cholesky factor and the inverse factor (Sec. 4.1).
+  void factor_from_sa(bool bf, int* flag) {
+    if (!woodbury_) {
+      fp_ = round_up(d_, 64);
+      double* G = B<double>("G", (size_t)fp_ * fp_);
+      if (bf) {
+        const int splits = gram_splits(h_->num_cu, m_, d_);
+        float* part = B<float>("gram_part32", (size_t)splits * fp_ * fp_);
+        gram_tn_bf16(m_, d_, SA16_, d_, nu2_, lam_, part, splits, G, fp_, s_);
+      } else {
+        const int splits = gram_splits(h_->num_cu, m_, d_);
+        double* part = B<double>("gram_part", (size_t)splits * fp_ * fp_);
+        gram_tn(m_, d_, SA_, d_, nu2_, lam_, part, splits, G, fp_, s_);
+      }
+      factor_and_invert(G, fp_, flag);
+    } else {
+      fp_ = round_up(m_, 64);
+      double* W = B<double>("G", (size_t)fp_ * fp_);
+      double* scaled = B<double>("sa_scaled", (size_t)m_ * d_);
+      if (bf) {
+        SA_ = B<double>("SA", (size_t)m_ * d_);
+        gram_nt_bf16(m_, d_, SA16_, d_, nu2_, invlam_, SA_, scaled, W, fp_, s_);
+      } else {
+        gram_nt(m_, d_, SA_, d_, nu2_, invlam_, scaled, W, fp_, s_);
+      }
+      factor_and_invert(W, fp_, flag);
+      SAT_ = B<double>("SAT", (size_t)d_ * m_);
+      launch_transpose(m_, d_, SA_, d_, SAT_, m_, s_);
+    }
+  }
+
+  void factor_and_invert(double* G, int64_t np, int* flag) {
+    double* dinv = B<double>("dinv", (size_t)(np / 64) * 4096);
+    cholesky_inplace(G, np, dinv, flag, s_);
+    Linv_ = B<double>("Linv", (size_t)np * np);
+    LinvT_ = B<double>("LinvT", (size_t)np * np);
+    double* tmp = B<double>("trtri_tmp", (size_t)(np / 64) * 4096);
+    trtri_lower(G, np, dinv, Linv_, tmp, s_);
+    launch_transpose(np, np, Linv_, np, LinvT_, np, s_);
+  }
+
+  // v = H_S^{-1} z (z, v: d x C)
+  void apply(const double* z, double* v) {
+    double* t1 = B<double>("ap_t1", (size_t)std::max(m_, d_) * C_);
+    if (!woodbury_) {
+      if (C_ >= 8) {
+        gemm_f64(false, false, d_, C_, d_, 1.0, Linv_, fp_, 0, z, C_, 0, 0.0, t1, C_, 0, 1, 0, s_);
+        gemm_f64(false, false, d_, C_, d_, 1.0, LinvT_, fp_, 0, t1, C_, 0, 0.0, v, C_, 0, 1, 0, s_);
+      } else {
+        launch_rowdot(d_, d_, Linv_, fp_, 1, z, C_, nullptr, 1.0, nullptr, nullptr, 1.0, t1, s_);
+        launch_rowdot(d_, d_, LinvT_, fp_, 2, t1, C_, nullptr, 1.0, nullptr, nullptr, 1.0, v, s_);
+      }
+    } else {
+      double* u = B<double>("ap_u", (size_t)m_ * C_);
+      double* w = B<double>("ap_w", (size_t)m_ * C_);
+      launch_rowdot(m_, d_, SA_, d_, 0, z, C_, invlam_, 1.0, nullptr, nullptr, 1.0, u, s_);
+      launch_rowdot(m_, m_, Linv_, fp_, 1, u, C_, nullptr, 1.0, nullptr, nullptr, 1.0, t1, s_);
+      launch_rowdot(m_, m_, LinvT_, fp_, 2, t1, C_, nullptr, 1.0, nullptr, nullptr, 1.0, w, s_);
+      launch_rowdot(d_, m_, SAT_, m_, 0, w, C_, nullptr, -1.0, z, invlam_, 1.0 / nu2_, v, s_);
+    }
+  }
+
+  void read_flags() {
+    AES_HIP(hipMemcpyAsync(h_->pinned, scal_ + 7 * C_, 8 * sizeof(double), hipMemcpyDeviceToHost, s_));
+    AES_HIP(hipStreamSynchronize(s_));
+    for (int i = 0; i < 8; ++i) fl_[i] = h_->pinned[i];
+  }
+
+  void trace(int64_t t, double lr, double thr, bool accept) {
+    if (o_.trace && trace_len_ < o_.trace_cap) {
+      aes_trace_entry& e = o_.trace[trace_len_++];
+      e.t = t;
+      e.m = m_;
+      e.k = k_;
+      e.log_ratio = lr;
+      e.threshold = thr;
+      e.accept = accept ? 1 : 0;
+      e.pad_ = 0;
+    }
+  }
+
+  // ---- the adaptive loop --------------------------------------------------------------
+  // Solves H x = rhs (device d x C), x initialised by the caller (x_is_zero tells whether
+  // the initial point is 0).  Returns the status; fills the counters.
+  aes_status adaptive(const double* rhs, double* x, bool x_is_zero, bool use32, int stop_rule, double stop_scale,
+                      bool reuse_factor) {
+    const bool ihs = o_.method == AES_IHS;
+    double phi, cc, mu = 0.0;
+    const double sr = std::sqrt(o_.rho);
+    if (ihs) {
+      phi = o_.rho;
+      cc = (1.0 + sr) / (1.0 - sr);
+      mu = 1.0 - o_.rho;
+    } else {
+      const double q = std::sqrt(1.0 - o_.rho);
+      phi = (1.0 - q) / (1.0 + q);
+      cc = 4.0 * (1.0 + sr) / (1.0 - sr);
+    }
+    const double lphi = std::log(phi), lc = std::log(cc);
+    if (!reuse_factor) sketch_factor();
+    // initial residual / gradient
+    if (ihs) {
+      if (x_is_zero)
+        launch_hv_colsum(part_, 0, d_, C_, x, lam_, 0.0, 0.0, rhs, -1.0, R_, s_);  // g = -b
+      else
+        hv(x, R_, 1.0, rhs, -1.0, use32);  // g = H x - b
+      apply(R_, Pv_);
+      launch_ihs_init(d_, C_, R_, Pv_, scal_, active_, nullptr, stop_rule, stop_scale, stop_sr_, tol2_, x, 1, s_);
+    } else {
+      if (x_is_zero)
+        AES_HIP(hipMemcpyAsync(R_, rhs, d_ * C_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
+      else
+        hv(x, R_, -1.0, rhs, 1.0, use32);  // r = b - H x
+      apply(R_, RTP_);
+      launch_pcg_init(d_, C_, R_, RTP_, Pv_, scal_, active_, nullptr, stop_rule, stop_scale, stop_sr_, tol2_, x, 1, s_);
+    }
+    read_flags();
+    if (fl_[2] != 0.0) return AES_ERR_NONFINITE;
+    int64_t t = 0, I = 0;
+    bool forced = false;
+    while (fl_[1] > 0.5) {
+      if (t >= o_.max_iter) return stop_rule == AES_STOP_FIXED ? AES_OK : AES_ERR_MAX_ITER;
+      const double thr = lc + (double)(t + 1 - I) * lphi;
+      const int force = (o_.adaptive && o_.force_reject_at >= 0 && t == o_.force_reject_at && !forced) ? 1 : 0;
+      if (force) forced = true;
+      const int at_cap = m_ >= mcap_ ? 1 : 0;
+      if (ihs) {
+        launch_ihs_candidate(d_, C_, x, Pv_, mu, XP_, active_, s_);
+        hv(XP_, RP_, 1.0, rhs, -1.0, use32);
+        apply(RP_, RTP_);
+        launch_ihs_finish(d_, C_, x, R_, Pv_, XP_, RP_, RTP_, scal_, active_, nullptr, thr, force, o_.adaptive, at_cap,
+                          stop_rule, stop_scale, stop_sr_, tol2_, s_);
+      } else {
+        hv(Pv_, Q_, 1.0, nullptr, 0.0, use32);
+        launch_pcg_candidate(d_, C_, C_ == 1 ? spart_ : nullptr, nwg_, lam_, nu2_, x, R_, Pv_, Q_, XP_, RP_, scal_,
+                             active_, s_);
+        apply(RP_, RTP_);
+        launch_pcg_finish(d_, C_, x, R_, Pv_, XP_, RP_, RTP_, scal_, active_, nullptr, thr, force, o_.adaptive, at_cap,
+                          stop_rule, stop_scale, stop_sr_, tol2_, s_);
+      }
+      read_flags();
+      ++attempts_;
+      const bool fail = fl_[0] != 0.0, accepted = fl_[3] != 0.0;
+      trace(t, fl_[4], thr, accepted);
+      if (fl_[2] != 0.0) return AES_ERR_NONFINITE;
+      if (accepted) {
+        ++t;
+        ++iters_;
+        if (fail && o_.adaptive) m_cap_reached_ = 1;
+        if (stop_rule == AES_STOP_FIXED && t >= o_.max_iter) return AES_OK;
+        continue;
+      }
+      // rejected: double m, fresh sketch, restart at x_t (Algorithm 2 / Algorithm 1)
+      I = t;
+      m_ = std::min<int64_t>(2 * m_, mcap_);
+      ++k_;
+      ++resketches_;
+      sketch_factor();
+      if (ihs) {
+        apply(R_, Pv_);
+        launch_ihs_init(d_, C_, R_, Pv_, scal_, active_, nullptr, stop_rule, stop_scale, stop_sr_, tol2_, x, 0, s_);
+      } else {
+        if (x_is_zero && t == 0)
+          AES_HIP(hipMemcpyAsync(R_, rhs, d_ * C_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
+        else
+          hv(x, R_, -1.0, rhs, 1.0, use32);  // explicit r_t = b - H x_t
+        apply(R_, RTP_);
+        launch_pcg_init(d_, C_, R_, RTP_, Pv_, scal_, active_, nullptr, stop_rule, stop_scale, stop_sr_, tol2_, x, 0, s_);
+      }
+      read_flags();
+      if (fl_[2] != 0.0) return AES_ERR_NONFINITE;
+    }
+    return AES_OK;
+  }
+
+  aes_status run(aes_info* info, bool reuse_factor = false) {
+    const double t0 = now_ms();
+    aes_status st = AES_OK;
+    try {
+      setup_common();
+      if (!reuse_factor) {
+        m_ = std::min<int64_t>(o_.m_init, mcap_);
+        k_ = 0;
+      }
+      const bool x0 = o_.x0 != nullptr;
+      if (x0)
+        launch_copy_cols(d_, C_, o_.x0, P_.ldx, (int)c_, X_, C_, s_);
+      else
+        AES_HIP(hipMemsetAsync(X_, 0, d_ * C_ * sizeof(double), s_));
+      if (!mixed_) {
+        st = adaptive(Bv_, X_, !x0, false, o_.stop, stop_scale_, reuse_factor);
+      } else {
+        st = run_mixed(x0);
+      }
+      if (st == AES_OK || st == AES_ERR_MAX_ITER || st == AES_ERR_NONFINITE)
+        launch_copy_cols(d_, (int)c_, X_, C_, (int)c_, P_.x, P_.ldx, s_);
+      AES_HIP(hipStreamSynchronize(s_));
+    } catch (const StatusError& e) {
+      st = e.st;
+      h_->err = e.what();
+    } catch (const HipError& e) {
+      st = AES_ERR_HIP;
+      h_->err = e.what();
+    } catch (const std::bad_alloc&) {
+      st = AES_ERR_OOM;
+      h_->err = "device workspace allocation failed";
+    } catch (const std::invalid_argument& e) {
+      st = AES_ERR_INVALID_ARG;
+      h_->err = e.what();
+    }
+    if (info) {
+      info->iterations = iters_;
+      info->attempts = attempts_;
+      info->final_m = m_;
+      info->resketches = resketches_;
+      info->a_passes = a_passes_;
+      info->refine_sweeps = sweeps_;
+      info->trace_len = trace_len_;
+      info->dtilde_final = fl_[5];
+      info->time_sketch_ms = t_sketch_;
+      info->time_total_ms = now_ms() - t0;
+      info->m_cap_reached = m_cap_reached_;
+      info->status = st;
+    }
+    return st;
+  }
+
+  // Mixed precision: outer FP64 residual refinement around inner adaptive PCG/IHS solves
+  // on the FP32-stored A with the BF16 sketch; the sketch state persists across sweeps.
+  aes_status run_mixed(bool x0) {
+    double* E = B<double>("E", d_ * C_);
+    double* Rr = B<double>("Rres", d_ * C_);
+    double* nrm = B<double>("nrm", 4);
+    bool first = true;
+    bool x_zero = !x0;
+    m_ = std::min<int64_t>(o_.m_init, mcap_);
+    k_ = 0;
+    const double inner = o_.inner_tol > 0 ? o_.inner_tol : 1e-6;
+    const double inner_scale = nu2_ * min_lambda() * inner * inner;
+    for (int sweep = 0; sweep < std::max(1, o_.max_refine); ++sweep) {
+      ++sweeps_;
+      // r = b - H x in FP64 (one pass over the FP64 A)
+      if (x_zero)
+        AES_HIP(hipMemcpyAsync(Rr, Bv_, d_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
+      else
+        hv(X_, Rr, -1.0, Bv_, 1.0, false);
+      AES_HIP(hipMemsetAsync(E, 0, d_ * sizeof(double), s_));
+      // re-arm the column
+      const int one = 1;
+      AES_HIP(hipMemcpyAsync(active_, &one, sizeof(int), hipMemcpyHostToDevice, s_));
+      aes_status st = adaptive(Rr, E, true, true, AES_STOP_XREL, inner_scale, !first);
+      first = false;
+      if (st == AES_ERR_NONFINITE) return st;
+      launch_axpy_cols(d_, 1, X_, E, nullptr, s_);
+      x_zero = false;
+      // ||e|| and ||x||
+      launch_norms(E, X_, nrm);
+      const double en = std::sqrt(h_->pinned[0]), xn = std::sqrt(h_->pinned[1]);
+      if (en <= 0.25 * tol_ * xn || xn == 0.0) return AES_OK;
+    }
+    return AES_ERR_MAX_ITER;
+  }
+
+  void launch_norms(const double* e, const double* x, double* nrm) {
+    // reuse the IHS init kernel machinery is overkill; use rowdot with a 1 x d "matrix"
+    launch_rowdot(1, d_, e, d_, 0, e, 1, nullptr, 1.0, nullptr, nullptr, 1.0, nrm, s_);
+    launch_rowdot(1, d_, x, d_, 0, x, 1, nullptr, 1.0, nullptr, nullptr, 1.0, nrm + 1, s_);
+    AES_HIP(hipMemcpyAsync(h_->pinned, nrm, 2 * sizeof(double), hipMemcpyDeviceToHost, s_));
+    AES_HIP(hipStreamSynchronize(s_));
+  }
+
+  // Factorise H_S for a caller-given sketch SA (m x d, ld d) and apply it to z (d x C).
+  void apply_external(int64_t m, const double* SA, const double* z, double* v) {
+    lam_ = B<double>("lam", d_);
+    invlam_ = B<double>("invlam", d_);
+    if (P_.lambda) {
+      AES_HIP(hipMemcpyAsync(lam_, P_.lambda, d_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
+      launch_inv(d_, P_.lambda, invlam_, s_);
+    } else {
+      launch_fill(lam_, d_, 1.0, s_);
+      launch_fill(invlam_, d_, 1.0, s_);
+    }
+    m_ = m;
+    woodbury_ = m_ < d_;
+    SA_ = B<double>("SA", (size_t)m_ * d_);
+    AES_HIP(hipMemcpyAsync(SA_, SA, (size_t)m_ * d_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
+    int* flag = B<int>("chol_flag", 1);
+    AES_HIP(hipMemsetAsync(flag, 0, sizeof(int), s_));
+    factor_from_sa(false, flag);
+    int hflag = 0;
+    AES_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s_));
+    AES_HIP(hipStreamSynchronize(s_));
+    if (hflag) throw StatusError(AES_ERR_NOT_SPD, "Cholesky pivot of the sketched Hessian is not positive");
+    apply(z, v);
+  }
+
+  // accessors for the kept context
+  int64_t m() const { return m_; }
+  int64_t k() const { return k_; }
+  void set_mk(int64_t m, int64_t k, bool woodbury, int64_t fp) {
+    m_ = m;
+    k_ = k;
+    woodbury_ = woodbury;
+    fp_ = fp;
+  }
+  void bind_factor() {
+    // re-fetch kept factor buffers after setup (same names, same sizes)
+    if (!woodbury_) {
+      Linv_ = B<double>("Linv", (size_t)fp_ * fp_);
+      LinvT_ = B<double>("LinvT", (size_t)fp_ * fp_);
+    } else {
+      Linv_ = B<double>("Linv", (size_t)fp_ * fp_);
+      LinvT_ = B<double>("LinvT", (size_t)fp_ * fp_);
+      SA_ = B<double>("SA", (size_t)m_ * d_);
+      SAT_ = B<double>("SAT", (size_t)d_ * m_);
+    }
+  }
+  bool woodbury() const { return woodbury_; }
+  int64_t fp() const { return fp_; }
+  double* X() const { return X_; }
+
+ private:
+  aes_handle h_;
+  hipStream_t s_;
+  ProblemDesc P_;
+  aes_options o_;
+  double tol_;
+  std::string ns_;
+  int64_t n_, d_, c_;
+  int C_;
+  int64_t npad_, mcap_, m_ = 1, k_ = 0, fp_ = 64;
+  double nu2_;
+  bool mixed_ = false, woodbury_ = false;
+  double *lam_ = nullptr, *invlam_ = nullptr, *X_ = nullptr, *R_ = nullptr, *Pv_ = nullptr, *Q_ = nullptr,
+         *XP_ = nullptr, *RP_ = nullptr, *RTP_ = nullptr, *Bv_ = nullptr, *scal_ = nullptr;
+  int* active_ = nullptr;
+  double *part_ = nullptr, *spart_ = nullptr, *Z_ = nullptr;
+  int nwg_ = 1, msplit_ = 1;
+  int64_t msplit_rows_ = 1;
+  float* A32_ = nullptr;
+  __hip_bfloat16* A16_ = nullptr;
+  double *SA_ = nullptr, *SAT_ = nullptr, *Linv_ = nullptr, *LinvT_ = nullptr;
+  __hip_bfloat16* SA16_ = nullptr;
+  double stop_scale_ = 0, stop_sr_ = 1, tol2_ = 0;
+  double fl_[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t iters_ = 0, attempts_ = 0, resketches_ = 0, a_passes_ = 0, sweeps_ = 0, trace_len_ = 0;
+  int m_cap_reached_ = 0;
+  double t_sketch_ = 0;
+};
+
+aes_status guard(aes_handle h, const std::function<void()>& f) {
+  try {
+    f();
+    return AES_OK;
+  } catch (const StatusError& e) {
+    if (h) h->err = e.what();
+    return e.st;
+  } catch (const HipError& e) {
+    if (h) h->err = e.what();
+    return AES_ERR_HIP;
+  } catch (const std::bad_alloc&) {
+    if (h) h->err = "device workspace allocation failed";
+    return AES_ERR_OOM;
+  } catch (const std::invalid_argument& e) {
+    if (h) h->err = e.what();
+    return AES_ERR_INVALID_ARG;
+  } catch (const std::exception& e) {
+    if (h) h->err = e.what();
+    return AES_ERR_HIP;
+  }
+}
+
+void set_device(aes_handle h) { AES_HIP(hipSetDevice(h->device)); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+// C ABI.
+// ---------------------------------------------------------------------------------------
+extern "C" {
+
+void aes_default_options(aes_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->method = AES_PCG;
+  o->sketch = AES_SRHT;
+  o->precision = AES_FP64;
+  o->stop = AES_STOP_XREL;
+  o->rho = 0.125;
+  o->m_init = 1;
+  o->m_max = 0;
+  o->max_iter = 200;
+  o->seed = 0;
+  o->problem = 0;
+  o->adaptive = 1;
+  o->force_reject_at = -1;
+  o->inner_tol = 1e-6;
+  o->max_refine = 20;
+  o->trace_cap = 0;
+  o->trace = nullptr;
+  o->x0 = nullptr;
+}
+
+aes_status aes_create(aes_handle* out, int device) {
+  if (!out) return AES_ERR_INVALID_ARG;
+  *out = nullptr;
+  auto h = std::make_unique<aes_handle_s>();
+  h->device = device;
+  aes_status st = guard(h.get(), [&] {
+    int count = 0;
+    AES_HIP(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) throw StatusError(AES_ERR_INVALID_ARG, "no such device");
+    AES_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    AES_HIP(hipGetDeviceProperties(&prop, device));
+    h->num_cu = prop.multiProcessorCount;
+    AES_HIP(hipHostMalloc((void**)&h->pinned, 64 * sizeof(double), hipHostMallocDefault));
+  });
+  if (st != AES_OK) return st;
+  *out = h.release();
+  return AES_OK;
+}
+
+aes_status aes_destroy(aes_handle h) {
+  if (!h) return AES_ERR_INVALID_ARG;
+  (void)hipSetDevice(h->device);
+  h->release();
+  delete h;
+  return AES_OK;
+}
+
+const char* aes_last_error(aes_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+static aes_status solve_impl(aes_handle h, void* stream, const ProblemDesc& P, double tol, const aes_options* opt,
+                             aes_info* info, const std::string& ns, Solver** keep) {
+  if (!h) return AES_ERR_INVALID_ARG;
+  aes_options o;
+  if (opt)
+    o = *opt;
+  else
+    aes_default_options(&o);
+  aes_status st = guard(h, [&] {
+    set_device(h);
+    validate(P, tol, o);
+  });
+  if (st != AES_OK) {
+    if (info) {
+      std::memset(info, 0, sizeof(*info));
+      info->status = st;
+    }
+    return st;
+  }
+  auto* solver = new Solver(h, (hipStream_t)stream, P, o, tol, ns);
+  st = solver->run(info);
+  if (keep)
+    *keep = solver;
+  else
+    delete solver;
+  return st;
+}
+
+aes_status aes_solve(aes_handle h, void* stream, int64_t n, int64_t d, int64_t c, const double* A, int64_t lda,
+                     const double* b, int64_t ldb, double nu, const double* lambda, double tol, const aes_options* opt,
+                     double* x, int64_t ldx, aes_info* info) {
+  ProblemDesc P{n, d, c, A, lda, b, ldb, nu, lambda, x, ldx};
+  aes_status st = AES_OK;
+  try {
+    st = solve_impl(h, stream, P, tol, opt, info, "s.", nullptr);
+  } catch (const StatusError& e) {
+    if (h) h->err = e.what();
+    st = e.st;
+  }
+  return st;
+}
+
+aes_status aes_solve_batched(aes_handle h, void* stream, int64_t nprob, const aes_problem* probs, double tol,
+                             const aes_options* opt, aes_info* infos) {
+  if (!h || nprob < 0 || (nprob > 0 && !probs)) return AES_ERR_INVALID_ARG;
+  aes_options o;
+  if (opt)
+    o = *opt;
+  else
+    aes_default_options(&o);
+  aes_status worst = AES_OK;
+  for (int64_t p = 0; p < nprob; ++p) {
+    const aes_problem& q = probs[p];
+    ProblemDesc P{q.n, q.d, q.c, q.A, q.lda, q.b, q.ldb, q.nu, q.lambda, q.x, q.ldx};
+    aes_options op = o;
+    op.problem = (int32_t)p;
+    op.trace = nullptr;
+    op.trace_cap = 0;
+    aes_status st;
+    try {
+      st = solve_impl(h, stream, P, tol, &op, infos ? &infos[p] : nullptr, "s.", nullptr);
+    } catch (const StatusError& e) {
+      h->err = e.what();
+      st = e.st;
+    }
+    if (st != AES_OK && worst == AES_OK) worst = st;
+  }
+  return worst;
+}
+
+aes_status aes_solve_keep(aes_handle h, void* stream, int64_t n, int64_t d, int64_t c, const double* A, int64_t lda,
+                          const double* b, int64_t ldb, double nu, const double* lambda, double tol,
+                          const aes_options* opt, double* x, int64_t ldx, aes_info* info, aes_ctx* ctx) {
+  if (!h || !ctx) return AES_ERR_INVALID_ARG;
+  *ctx = nullptr;
+  if (c != 1) {
+    h->err = "aes_solve_keep supports c = 1";
+    return AES_ERR_INVALID_ARG;
+  }
+  aes_options o;
+  if (opt)
+    o = *opt;
+  else
+    aes_default_options(&o);
+  if (o.precision != AES_FP64) {
+    h->err = "aes_solve_keep supports FP64";
+    return AES_ERR_INVALID_ARG;
+  }
+  auto c2 = std::make_unique<aes_ctx_s>();
+  aes_status st = aes_create(&c2->h, h->device);
+  if (st != AES_OK) return st;
+  ProblemDesc P{n, d, c, A, lda, b, ldb, nu, lambda, x, ldx};
+  Solver* keep = nullptr;
+  st = solve_impl(c2->h, stream, P, tol, &o, info, "s.", &keep);
+  if (st != AES_OK) {
+    h->err = c2->h->err;
+    delete keep;
+    aes_destroy(c2->h);
+    return st;
+  }
+  c2->n = n;
+  c2->d = d;
+  c2->lda = lda;
+  c2->A = A;
+  c2->nu = nu;
+  c2->has_lambda = lambda != nullptr;
+  c2->opt = o;
+  c2->opt.trace = nullptr;
+  c2->opt.trace_cap = 0;
+  c2->opt.x0 = nullptr;
+  c2->m = keep->m();
+  c2->k = keep->k();
+  st = guard(h, [&] {
+    c2->xstar = c2->h->buf<double>("ctx_xstar", d);
+    AES_HIP(hipMemcpyAsync(c2->xstar, x, d * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    if (lambda) {
+      double* lk = c2->h->buf<double>("ctx_lambda", d);
+      AES_HIP(hipMemcpyAsync(lk, lambda, d * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    }
+    AES_HIP(hipStreamSynchronize((hipStream_t)stream));
+  });
+  delete keep;
+  if (st != AES_OK) {
+    aes_destroy(c2->h);
+    return st;
+  }
+  *ctx = c2.release();
+  return AES_OK;
+}
+
+aes_status aes_adjoint_solve(aes_ctx ctx, void* stream, const double* g, double tol, double* lam, aes_info* info) {
+  if (!ctx || !g || !lam) return AES_ERR_INVALID_ARG;
+  aes_handle h = ctx->h;
+  const double* lk = ctx->has_lambda ? h->buf<double>("ctx_lambda", ctx->d) : nullptr;
+  ProblemDesc P{ctx->n, ctx->d, 1, ctx->A, ctx->lda, g, 1, ctx->nu, lk, lam, 1};
+  aes_status st = guard(h, [&] {
+    set_device(h);
+    validate(P, tol, ctx->opt);
+  });
+  if (st != AES_OK) return st;
+  // Same workspace names as the forward solve: the kept SA / factor are reused as H_S, and
+  // the sketch stream continues at index k+1 if the improvement test asks for a resize.
+  Solver solver(h, (hipStream_t)stream, P, ctx->opt, tol, "s.");
+  solver.set_mk(ctx->m, ctx->k, ctx->m < ctx->d, round_up(ctx->m < ctx->d ? ctx->m : ctx->d, 64));
+  st = guard(h, [&] { solver.bind_factor(); });
+  if (st != AES_OK) return st;
+  st = solver.run(info, true);
+  if (st == AES_OK) {
+    ctx->m = solver.m();
+    ctx->k = solver.k();
+  }
+  return st;
+}
+
+aes_status aes_grad(aes_ctx ctx, void* stream, const double* lam, double* dA, double* dlognu) {
+  if (!ctx || !lam) return AES_ERR_INVALID_ARG;
+  aes_handle h = ctx->h;
+  return guard(h, [&] {
+    set_device(h);
+    hipStream_t s = (hipStream_t)stream;
+    if (dA) launch_grad_rank2(ctx->A, ctx->n, ctx->d, ctx->lda, ctx->xstar, lam, dA, ctx->d, s);
+    if (dlognu) {
+      // -2 nu^2 lam^T Lambda x*  (a 1 x d row-dot with the diagonal as the column scale)
+      double* out = h->buf<double>("grad_out", 1);
+      const double* lk = ctx->has_lambda ? h->buf<double>("ctx_lambda", ctx->d) : nullptr;
+      launch_rowdot(1, ctx->d, lam, ctx->d, 0, ctx->xstar, 1, lk, 1.0, nullptr, nullptr, 1.0, out, s);
+      double v = 0;
+      AES_HIP(hipMemcpyAsync(&v, out, sizeof(double), hipMemcpyDeviceToHost, s));
+      AES_HIP(hipStreamSynchronize(s));
+      *dlognu = -2.0 * ctx->nu * ctx->nu * v;
+    }
+  });
+}
+
+void aes_ctx_free(aes_ctx ctx) {
+  if (!ctx) return;
+  if (ctx->h) aes_destroy(ctx->h);
+  delete ctx;
+}
+
+aes_status aes_hv(aes_handle h, void* stream, int64_t n, int64_t d, const double* A, int64_t lda, double nu,
+                  const double* lambda, const double* p, double* q, double* pHp) {
+  if (!h) return AES_ERR_INVALID_ARG;
+  return guard(h, [&] {
+    if (n < 1 || d < 1 || lda < d || !A || !p || !q || !(nu >= 0)) throw StatusError(AES_ERR_INVALID_ARG, "bad arguments");
+    if (d > 8192) throw StatusError(AES_ERR_INVALID_ARG, "d > 8192 is not supported");
+    set_device(h);
+    hipStream_t s = (hipStream_t)stream;
+    const int nwg = hv_num_blocks(h->num_cu, n);
+    double* part = h->buf<double>("hv.part", (size_t)nwg * d);
+    double* spart = h->buf<double>("hv.spart", nwg);
+    launch_hv_fused<double>(A, n, d, lda, p, part, spart, nwg, s);
+    launch_hv_colsum(part, nwg, d, 1, p, lambda, nu * nu, 1.0, nullptr, 0.0, q, s);
+    if (pHp) {
+      // ||A p||^2 + nu^2 p^T Lambda p: the candidate kernel's reduction with a zero state
+      double* scal = h->buf<double>("hv.scal", 16);
+      int* act = h->buf<int>("hv.act", 1);
+      double* dummy = h->buf<double>("hv.dummy", 2 * d);
+      AES_HIP(hipMemsetAsync(scal, 0, 16 * sizeof(double), s));
+      AES_HIP(hipMemsetAsync(act, 0, sizeof(int), s));
+      launch_pcg_candidate(d, 1, spart, nwg, lambda, nu * nu, p, p, p, q, dummy, dummy + d, scal, act, s);
+      AES_HIP(hipMemcpyAsync(pHp, scal + 5, sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+  });
+}
+
+aes_status aes_sketch(aes_handle h, void* stream, int kind, int64_t n, int64_t d, const double* A, int64_t lda,
+                      int64_t m, uint64_t seed, int32_t problem, int64_t k, double* SA) {
+  if (!h) return AES_ERR_INVALID_ARG;
+  return guard(h, [&] {
+    const int64_t npad = next_pow2(n);
+    if (n < 1 || d < 1 || lda < d || m < 1 || m > npad || !A || !SA || k < 0)
+      throw StatusError(AES_ERR_INVALID_ARG, "bad arguments");
+    set_device(h);
+    hipStream_t s = (hipStream_t)stream;
+    if (kind == AES_SRHT) {
+      double* eps = h->buf<double>("sk.eps", n);
+      launch_signs(seed, problem, k, n, eps, s);
+      SelectScratch sc;
+      sc.keys = h->buf<uint64_t>("sk.keys", npad);
+      sc.pos = h->buf<int32_t>("sk.pos", npad);
+      sc.hist = h->buf<uint32_t>("sk.hist", 256 * 8);
+      sc.state = h->buf<uint64_t>("sk.state", 4);
+      sc.blk = h->buf<uint32_t>("sk.blk", 2 * select_blocks(npad));
+      launch_srht_select(seed, problem, k, npad, m, sc, s);
+      double* Y = h->buf<double>("sk.Y", (size_t)npad * d);
+      launch_srht_apply<double, double, double>(A, n, d, lda, eps, npad, sc.pos, m, Y, SA, d, s);
+    } else if (kind == AES_GAUSS) {
+      launch_gauss_sketch(A, n, d, lda, m, seed, problem, k, SA, d, s);
+    } else {
+      throw StatusError(AES_ERR_INVALID_ARG, "unknown sketch kind");
+    }
+  });
+}
+
+aes_status aes_factor(aes_handle h, void* stream, int64_t m, int64_t d, const double* SA, double nu,
+                      const double* lambda, double* G, double* L) {
+  if (!h) return AES_ERR_INVALID_ARG;
+  return guard(h, [&] {
+    if (m < 1 || d < 1 || !SA || !G || !L || !(nu > 0)) throw StatusError(AES_ERR_INVALID_ARG, "bad arguments");
+    set_device(h);
+    hipStream_t s = (hipStream_t)stream;
+    const bool wb = m < d;
+    const int64_t dim = wb ? m : d;
+    const int64_t fp = round_up(dim, 64);
+    double* Gp = h->buf<double>("fa.G", (size_t)fp * fp);
+    double* invlam = h->buf<double>("fa.invlam", d);
+    launch_inv(d, lambda, invlam, s);
+    if (!wb) {
+      const int splits = gram_splits(h->num_cu, m, d);
+      double* part = h->buf<double>("fa.part", (size_t)splits * fp * fp);
+      gram_tn(m, d, SA, d, nu * nu, lambda, part, splits, Gp, fp, s);
+    } else {
+      double* scaled = h->buf<double>("fa.scaled", (size_t)m * d);
+      gram_nt(m, d, SA, d, nu * nu, invlam, scaled, Gp, fp, s);
+    }
+    // G (unpadded, full symmetric from the lower triangle)
+    launch_copy_cols(dim, (int)dim, Gp, fp, (int)dim, G, dim, s);
+    int* flag = h->buf<int>("fa.flag", 1);
+    AES_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+    double* dinv = h->buf<double>("fa.dinv", (size_t)(fp / 64) * 4096);
+    cholesky_inplace(Gp, fp, dinv, flag, s);
+    launch_copy_cols(dim, (int)dim, Gp, fp, (int)dim, L, dim, s);
+    int hf = 0;
+    AES_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    AES_HIP(hipStreamSynchronize(s));
+    if (hf) throw StatusError(AES_ERR_NOT_SPD, "Cholesky pivot is not positive");
+  });
+}
+
+aes_status aes_precond_apply(aes_handle h, void* stream, int64_t m, int64_t d, int64_t c, const double* SA, double nu,
+                             const double* lambda, const double* z, double* v) {
+  if (!h) return AES_ERR_INVALID_ARG;
+  return guard(h, [&] {
+    if (m < 1 || d < 1 || c < 1 || c > 32 || (c & (c - 1)) || !SA || !z || !v || !(nu > 0))
+      throw StatusError(AES_ERR_INVALID_ARG, "bad arguments (c must be a power of two <= 32)");
+    set_device(h);
+    hipStream_t s = (hipStream_t)stream;
+    // Build a solver state around the given sketch (no A needed for the application).
+    aes_options o;
+    aes_default_options(&o);
+    ProblemDesc P{std::max<int64_t>(m, 1), d, c, SA, d, z, c, nu, lambda, v, c};
+    Solver so(h, s, P, o, 1e-10, "pa.");
+    so.apply_external(m, SA, z, v);
+  });
+}
+
+}  // extern "C"

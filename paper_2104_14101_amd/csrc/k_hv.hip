@@ -1,0 +1,215 @@
+// Fused single-pass Hessian-vector product (the per-iteration O(nd) work of Sec. 4.1):
+//     z = A v (kept on chip),  q = A^T z,  s = ||z||^2
+// streaming every row of A from HBM exactly once.  Each workgroup owns a slice of rows and
+// keeps its partial q (d values) in registers; partials are summed in a fixed order by
+// hv_colsum, which also adds nu^2 Lambda v (deterministic, no floating-point atomics).
+#include "common.h"
+#include "kernels.h"
+
+namespace aes {
+
+template <typename T, int V>
+struct VecT;
+template <>
+struct VecT<double, 1> {
+  using type = double;
+};
+template <>
+struct VecT<double, 2> {
+  using type = double __attribute__((ext_vector_type(2)));
+};
+template <>
+struct VecT<float, 1> {
+  using type = float;
+};
+template <>
+struct VecT<float, 4> {
+  using type = float __attribute__((ext_vector_type(4)));
+};
+
+template <typename TA, int VEC>
+__device__ __forceinline__ void load_vec(const TA* __restrict__ p, bool full, int nvalid, double (&out)[VEC]) {
+  using VT = typename VecT<TA, VEC>::type;
+  if constexpr (VEC == 1) {
+    out[0] = full ? (double)__builtin_nontemporal_load(p) : 0.0;
+  } else {
+    if (full) {
+      VT v = __builtin_nontemporal_load(reinterpret_cast<const VT*>(p));
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) out[i] = (double)v[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) out[i] = i < nvalid ? (double)p[i] : 0.0;
+    }
+  }
+}
+
+constexpr int kHvThreads = 256;
+
+// One workgroup = 4 waves; thread t owns columns (j*256 + t)*VEC + [0, VEC) for j < NCH.
+// Each step loads ROWS rows, reduces the ROWS partial dot products across the workgroup
+// (wave transpose-reduction + LDS), then accumulates q += z_r * a_r.
+template <typename TA, int VEC, int NCH, int ROWS>
+__global__ __launch_bounds__(kHvThreads, 2) void hv_fused_kernel(const TA* __restrict__ A, int64_t n, int d,
+                                                                  int64_t lda, const double* __restrict__ v,
+                                                                  double* __restrict__ part,
+                                                                  double* __restrict__ spart) {
+  constexpr int CH = kHvThreads * VEC;  // columns per chunk
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = tid >> 6;
+  __shared__ double red[2][4][ROWS];
+
+  double pr[NCH][VEC], qa[NCH][VEC];
+#pragma unroll
+  for (int j = 0; j < NCH; ++j)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const int col = j * CH + tid * VEC + e;
+      pr[j][e] = col < d ? v[col] : 0.0;
+      qa[j][e] = 0.0;
+    }
+
+  double ssum = 0.0;
+  int buf = 0;
+  const int64_t stride = (int64_t)gridDim.x * ROWS;
+  for (int64_t r0 = (int64_t)blockIdx.x * ROWS; r0 < n; r0 += stride) {
+    double a[ROWS][NCH][VEC];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+      const int64_t row = r0 + r;
+      const bool rok = row < n;
+      const TA* rp = A + (rok ? row : 0) * lda;
+#pragma unroll
+      for (int j = 0; j < NCH; ++j) {
+        const int col = j * CH + tid * VEC;
+        const int nvalid = d - col;
+        load_vec<TA, VEC>(rp + col, rok && nvalid >= VEC, rok ? nvalid : 0, a[r][j]);
+      }
+    }
+    double dot[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < NCH; ++j)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc = fma(a[r][j][e], pr[j][e], acc);
+      dot[r] = acc;
+    }
+    wave_transpose_sum<ROWS>(dot, lane);
+    constexpr int shift = 6 - ilog2_c(ROWS);
+    if ((lane & ((1 << shift) - 1)) == 0) red[buf][wid][(lane >> shift) & (ROWS - 1)] = dot[0];
+    __syncthreads();
+    double z[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) z[r] = (red[buf][0][r] + red[buf][1][r]) + (red[buf][2][r] + red[buf][3][r]);
+    buf ^= 1;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+      ssum = fma(z[r], z[r], ssum);
+#pragma unroll
+      for (int j = 0; j < NCH; ++j)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) qa[j][e] = fma(z[r], a[r][j][e], qa[j][e]);
+    }
+  }
+  double* out = part + (int64_t)blockIdx.x * d;
+#pragma unroll
+  for (int j = 0; j < NCH; ++j)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const int col = j * CH + tid * VEC + e;
+      if (col < d) out[col] = qa[j][e];
+    }
+  if (tid == 0) spart[blockIdx.x] = ssum;
+}
+
+int hv_num_blocks(int num_cu, int64_t n) {
+  int64_t nb = (int64_t)num_cu * 2;
+  const int64_t groups = ceil_div(n, 4);
+  if (nb > groups) nb = groups;
+  return (int)(nb < 1 ? 1 : nb);
+}
+
+template <typename TA, int VEC, int NCH, int ROWS>
+static void hv_launch_cfg(const TA* A, int64_t n, int64_t d, int64_t lda, const double* v, double* part,
+                          double* spart, int nwg, hipStream_t s) {
+  hipLaunchKernelGGL((hv_fused_kernel<TA, VEC, NCH, ROWS>), dim3(nwg), dim3(kHvThreads), 0, s, A, n, (int)d, lda,
+                     v, part, spart);
+  AES_LAUNCH_CHECK();
+}
+
+template <>
+void launch_hv_fused<double>(const double* A, int64_t n, int64_t d, int64_t lda, const double* v, double* part,
+                             double* spart, int nwg, hipStream_t s) {
+  const bool v2 = (d % 2 == 0) && (lda % 2 == 0) && ((uintptr_t)A % 16 == 0);
+  if (v2) {
+    if (d <= 512) return hv_launch_cfg<double, 2, 1, 16>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 1024) return hv_launch_cfg<double, 2, 2, 8>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 2048) return hv_launch_cfg<double, 2, 4, 8>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 4096) return hv_launch_cfg<double, 2, 8, 4>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 8192) return hv_launch_cfg<double, 2, 16, 2>(A, n, d, lda, v, part, spart, nwg, s);
+  } else {
+    if (d <= 256) return hv_launch_cfg<double, 1, 1, 16>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 1024) return hv_launch_cfg<double, 1, 4, 8>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 2048) return hv_launch_cfg<double, 1, 8, 4>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 4096) return hv_launch_cfg<double, 1, 16, 2>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 8192) return hv_launch_cfg<double, 1, 32, 1>(A, n, d, lda, v, part, spart, nwg, s);
+  }
+  throw std::invalid_argument("hv_fused: d > 8192 is not supported");
+}
+
+template <>
+void launch_hv_fused<float>(const float* A, int64_t n, int64_t d, int64_t lda, const double* v, double* part,
+                            double* spart, int nwg, hipStream_t s) {
+  const bool v4 = (d % 4 == 0) && (lda % 4 == 0) && ((uintptr_t)A % 16 == 0);
+  if (v4) {
+    if (d <= 1024) return hv_launch_cfg<float, 4, 1, 16>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 2048) return hv_launch_cfg<float, 4, 2, 8>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 4096) return hv_launch_cfg<float, 4, 4, 8>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 8192) return hv_launch_cfg<float, 4, 8, 4>(A, n, d, lda, v, part, spart, nwg, s);
+  } else {
+    if (d <= 256) return hv_launch_cfg<float, 1, 1, 16>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 1024) return hv_launch_cfg<float, 1, 4, 8>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 2048) return hv_launch_cfg<float, 1, 8, 4>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 4096) return hv_launch_cfg<float, 1, 16, 2>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 8192) return hv_launch_cfg<float, 1, 32, 1>(A, n, d, lda, v, part, spart, nwg, s);
+  }
+  throw std::invalid_argument("hv_fused: d > 8192 is not supported");
+}
+
+// out[j, c] = sgn * (sum_w part[w][j][c] + nu2 * lam[j] * v[j, c]) + bsgn * b[j, c]
+// 256 threads = 32 (j,c)-elements x 8 partial groups; groups combined in a fixed order.
+__global__ __launch_bounds__(256) void hv_colsum_kernel(const double* __restrict__ part, int nwg, int64_t total,
+                                                        int C, const double* __restrict__ v,
+                                                        const double* __restrict__ lam, double nu2, double sgn,
+                                                        const double* __restrict__ b, double bsgn,
+                                                        double* __restrict__ out) {
+  __shared__ double sh[8][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int64_t e = (int64_t)blockIdx.x * 32 + tx;
+  double acc = 0.0;
+  if (e < total)
+    for (int w = ty; w < nwg; w += 8) acc += part[(int64_t)w * total + e];
+  sh[ty][tx] = acc;
+  __syncthreads();
+  if (ty == 0 && e < total) {
+    double sum = ((sh[0][tx] + sh[1][tx]) + (sh[2][tx] + sh[3][tx])) + ((sh[4][tx] + sh[5][tx]) + (sh[6][tx] + sh[7][tx]));
+    const int64_t j = e / C;
+    const double lj = lam ? lam[j] : 1.0;
+    double val = sgn * (sum + nu2 * lj * v[e]);
+    if (b) val += bsgn * b[e];
+    out[e] = val;
+  }
+}
+
+void launch_hv_colsum(const double* part, int nwg, int64_t d, int C, const double* v, const double* lam, double nu2,
+                      double sgn, const double* b, double bsgn, double* out, hipStream_t s) {
+  const int64_t total = d * C;
+  hipLaunchKernelGGL(hv_colsum_kernel, dim3((unsigned)ceil_div(total, 32)), dim3(256), 0, s, part, nwg, total, C, v,
+                     lam, nu2, sgn, b, bsgn, out);
+  AES_LAUNCH_CHECK();
+}
+
+}  // namespace aes

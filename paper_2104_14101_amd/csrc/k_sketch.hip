@@ -1,0 +1,403 @@
+// Subsampled randomized Hadamard transform S A = (1/sqrt m) R H E A_pad (Sec. 2.1, with the
+// zero padding of its footnote and the sqrt(n'/m) scale of the SRHT proof section):
+//   * E: Rademacher signs of Philox stream SIGN (one per data row);
+//   * R: the m padded rows with the smallest 64-bit Philox ROW keys (a uniform sample without
+//     replacement), kept in increasing row order.  Selected by an exact radix select of the
+//     m-th smallest key (eight 8-bit digit passes) and an order-preserving compaction;
+//   * H: unnormalised Sylvester Walsh-Hadamard transform of order n' = 2^L along the rows,
+//     done in ceil(L / 9) passes.  A pass transforms 2^b rows that differ in b consecutive
+//     index bits: the tile (2^b rows x CW columns) is staged in LDS and transformed with
+//     radix-8 butterflies held in registers (one LDS round trip per 3 bits).  The first pass
+//     applies E and synthesises the zero padding rows; the last pass writes only the rows in R
+//     (scaled by 1/sqrt m) and skips tiles that contain none.
+#include <cmath>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace aes {
+
+__global__ void signs_kernel(uint64_t k0, uint64_t k1, int64_t n, double* __restrict__ eps) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Rand4 r = philox4x64_10((uint64_t)i, kStreamSign, 0, 0, k0, k1);
+  eps[i] = (r.w[0] >> 63) ? -1.0 : 1.0;
+}
+
+void launch_signs(uint64_t seed, int32_t problem, int64_t k, int64_t n, double* eps, hipStream_t s) {
+  const RngKey key = make_key(seed, problem, k);
+  hipLaunchKernelGGL(signs_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, key.k0, key.k1, n, eps);
+  AES_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------------------
+// Row selection.
+// state: [0] prefix (key value being built), [1] remaining rank, [2] unused, [3] unused
+// ---------------------------------------------------------------------------------------
+__global__ void rowkeys_kernel(uint64_t k0, uint64_t k1, int64_t npad, uint64_t* __restrict__ keys) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npad) return;
+  keys[i] = philox4x64_10((uint64_t)i, kStreamRow, 0, 0, k0, k1).w[0];
+}
+
+__global__ void select_init_kernel(uint64_t* __restrict__ state, uint32_t* __restrict__ hist, int64_t m) {
+  const int t = threadIdx.x;
+  for (int i = t; i < 256 * 8; i += blockDim.x) hist[i] = 0;
+  if (t == 0) {
+    state[0] = 0;
+    state[1] = (uint64_t)(m - 1);
+    state[2] = 0;
+    state[3] = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void select_hist_kernel(const uint64_t* __restrict__ keys, int64_t npad, int pass,
+                                                          const uint64_t* __restrict__ state,
+                                                          uint32_t* __restrict__ hist) {
+  __shared__ uint32_t lh[256];
+  lh[threadIdx.x] = 0;
+  __syncthreads();
+  const int shift = 56 - 8 * pass;
+  const uint64_t prefix = state[0];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npad; i += stride) {
+    const uint64_t key = keys[i];
+    const bool match = pass == 0 || (key >> (shift + 8)) == (prefix >> (shift + 8));
+    if (match) atomicAdd(&lh[(key >> shift) & 255], 1u);
+  }
+  __syncthreads();
+  const uint32_t v = lh[threadIdx.x];
+  if (v) atomicAdd(&hist[pass * 256 + threadIdx.x], v);
+}
+
+__global__ __launch_bounds__(256) void select_scan_kernel(int pass, uint64_t* __restrict__ state,
+                                                          const uint32_t* __restrict__ hist) {
+  __shared__ uint64_t cum[256];
+  const int t = threadIdx.x;
+  cum[t] = hist[pass * 256 + t];
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {  // inclusive Hillis-Steele scan
+    const uint64_t v = t >= off ? cum[t - off] : 0;
+    __syncthreads();
+    cum[t] += v;
+    __syncthreads();
+  }
+  const uint64_t rank = state[1];
+  const uint64_t before = t ? cum[t - 1] : 0;
+  __syncthreads();
+  if (rank >= before && rank < cum[t]) {
+    const int shift = 56 - 8 * pass;
+    state[0] |= (uint64_t)t << shift;
+    state[1] = rank - before;
+  }
+}
+
+constexpr int kSelBlk = 1024;
+
+size_t select_blocks(int64_t npad) { return (size_t)ceil_div(npad, kSelBlk); }
+
+__global__ __launch_bounds__(kSelBlk) void select_count_kernel(const uint64_t* __restrict__ keys, int64_t npad,
+                                                               const uint64_t* __restrict__ state,
+                                                               uint32_t* __restrict__ blk) {
+  __shared__ uint32_t cl[16], ce[16];
+  const uint64_t T = state[0];
+  const int64_t i = (int64_t)blockIdx.x * kSelBlk + threadIdx.x;
+  const uint64_t key = i < npad ? keys[i] : ~0ull;
+  const bool less = i < npad && key < T;
+  const bool eq = i < npad && key == T;
+  const uint64_t bl = __ballot(less), be = __ballot(eq);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    cl[w] = (uint32_t)__popcll(bl);
+    ce[w] = (uint32_t)__popcll(be);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t a = 0, b = 0;
+    for (int k = 0; k < kSelBlk / 64; ++k) {
+      a += cl[k];
+      b += ce[k];
+    }
+    blk[2 * blockIdx.x] = a;
+    blk[2 * blockIdx.x + 1] = b;
+  }
+}
+
+// Exclusive scan of the per-block (less, equal) counts (single workgroup, sequential chunks).
+__global__ __launch_bounds__(1024) void select_blkscan_kernel(uint32_t* __restrict__ blk, int64_t nblk) {
+  __shared__ uint32_t sa[1024], sb[1024];
+  __shared__ uint32_t carry_a, carry_b;
+  if (threadIdx.x == 0) {
+    carry_a = 0;
+    carry_b = 0;
+  }
+  __syncthreads();
+  for (int64_t base = 0; base < nblk; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    const uint32_t a = i < nblk ? blk[2 * i] : 0, b = i < nblk ? blk[2 * i + 1] : 0;
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const uint32_t va = threadIdx.x >= off ? sa[threadIdx.x - off] : 0;
+      const uint32_t vb = threadIdx.x >= off ? sb[threadIdx.x - off] : 0;
+      __syncthreads();
+      sa[threadIdx.x] += va;
+      sb[threadIdx.x] += vb;
+      __syncthreads();
+    }
+    if (i < nblk) {
+      blk[2 * i] = carry_a + sa[threadIdx.x] - a;
+      blk[2 * i + 1] = carry_b + sb[threadIdx.x] - b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 1023) {
+      carry_a += sa[1023];
+      carry_b += sb[1023];
+    }
+    __syncthreads();
+  }
+}
+
+// pos[i] = rank of padded row i in R (ascending row order) or -1.
+__global__ __launch_bounds__(kSelBlk) void select_write_kernel(const uint64_t* __restrict__ keys, int64_t npad,
+                                                               const uint64_t* __restrict__ state,
+                                                               const uint32_t* __restrict__ blk,
+                                                               int32_t* __restrict__ pos) {
+  __shared__ uint32_t cl[16], ce[16];
+  const uint64_t T = state[0];
+  const uint64_t need = state[1] + 1;  // keys equal to T that are taken, in index order
+  const int64_t i = (int64_t)blockIdx.x * kSelBlk + threadIdx.x;
+  const uint64_t key = i < npad ? keys[i] : ~0ull;
+  const bool less = i < npad && key < T;
+  const bool eq = i < npad && key == T;
+  const uint64_t bl = __ballot(less), be = __ballot(eq);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  if (lane == 0) {
+    cl[w] = (uint32_t)__popcll(bl);
+    ce[w] = (uint32_t)__popcll(be);
+  }
+  __syncthreads();
+  uint32_t less_before = blk[2 * blockIdx.x], eq_before = blk[2 * blockIdx.x + 1];
+  for (int k = 0; k < w; ++k) {
+    less_before += cl[k];
+    eq_before += ce[k];
+  }
+  less_before += (uint32_t)__popcll(bl & lt);
+  eq_before += (uint32_t)__popcll(be & lt);
+  if (i >= npad) return;
+  int32_t p = -1;
+  const uint64_t eqt = eq_before < need ? eq_before : need;
+  if (less) p = (int32_t)(less_before + eqt);
+  else if (eq && eq_before < need) p = (int32_t)(less_before + eq_before);
+  pos[i] = p;
+}
+
+void launch_srht_select(uint64_t seed, int32_t problem, int64_t k, int64_t npad, int64_t m, const SelectScratch& sc,
+                        hipStream_t s) {
+  const RngKey key = make_key(seed, problem, k);
+  hipLaunchKernelGGL(rowkeys_kernel, dim3((unsigned)ceil_div(npad, 256)), dim3(256), 0, s, key.k0, key.k1, npad, sc.keys);
+  AES_LAUNCH_CHECK();
+  hipLaunchKernelGGL(select_init_kernel, dim3(1), dim3(256), 0, s, sc.state, sc.hist, m);
+  AES_LAUNCH_CHECK();
+  int64_t hb = ceil_div(npad, 256 * 8);
+  if (hb > 1024) hb = 1024;
+  if (hb < 1) hb = 1;
+  for (int pass = 0; pass < 8; ++pass) {
+    hipLaunchKernelGGL(select_hist_kernel, dim3((unsigned)hb), dim3(256), 0, s, sc.keys, npad, pass, sc.state, sc.hist);
+    AES_LAUNCH_CHECK();
+    hipLaunchKernelGGL(select_scan_kernel, dim3(1), dim3(256), 0, s, pass, sc.state, sc.hist);
+    AES_LAUNCH_CHECK();
+  }
+  const int64_t nblk = (int64_t)select_blocks(npad);
+  hipLaunchKernelGGL(select_count_kernel, dim3((unsigned)nblk), dim3(kSelBlk), 0, s, sc.keys, npad, sc.state, sc.blk);
+  AES_LAUNCH_CHECK();
+  hipLaunchKernelGGL(select_blkscan_kernel, dim3(1), dim3(1024), 0, s, sc.blk, nblk);
+  AES_LAUNCH_CHECK();
+  hipLaunchKernelGGL(select_write_kernel, dim3((unsigned)nblk), dim3(kSelBlk), 0, s, sc.keys, npad, sc.state, sc.blk,
+                     sc.pos);
+  AES_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------------------
+// Walsh-Hadamard passes.
+// ---------------------------------------------------------------------------------------
+template <typename T>
+struct AccOf {
+  using type = float;
+};
+template <>
+struct AccOf<double> {
+  using type = double;
+};
+
+template <typename TO, typename TA>
+__device__ __forceinline__ TO cvt(TA v) {
+  return (TO)v;
+}
+template <>
+__device__ __forceinline__ __hip_bfloat16 cvt<__hip_bfloat16, float>(float v) {
+  return __float2bfloat16(v);
+}
+template <>
+__device__ __forceinline__ float cvt<float, __hip_bfloat16>(__hip_bfloat16 v) {
+  return __bfloat162float(v);
+}
+
+constexpr int kMaxTileBits = 9;
+
+// In-register Walsh-Hadamard of 2^NB values: v[q] for q < 2^NB.
+template <typename TACC, int NB>
+__device__ __forceinline__ void wht_reg(TACC (&v)[1 << NB]) {
+#pragma unroll
+  for (int h = 1; h < (1 << NB); h <<= 1)
+#pragma unroll
+    for (int q = 0; q < (1 << NB); ++q)
+      if ((q & h) == 0) {
+        const TACC a = v[q], b = v[q | h];
+        v[q] = a + b;
+        v[q | h] = a - b;
+      }
+}
+
+template <typename TACC, int NB, int CW>
+__device__ __forceinline__ void wht_group(TACC* tile, int R, int g, int tid) {
+  // units: (R >> NB) index groups x CW columns
+  const int units = (R >> NB) * CW;
+  for (int u = tid; u < units; u += 256) {
+    const int c = u % CW;
+    const int jj = u / CW;
+    const int j0 = ((jj >> g) << (g + NB)) | (jj & ((1 << g) - 1));
+    TACC v[1 << NB];
+#pragma unroll
+    for (int q = 0; q < (1 << NB); ++q) v[q] = tile[(j0 + (q << g)) * CW + c];
+    wht_reg<TACC, NB>(v);
+#pragma unroll
+    for (int q = 0; q < (1 << NB); ++q) tile[(j0 + (q << g)) * CW + c] = v[q];
+  }
+}
+
+// One WHT pass over index bits [s, s+b).  MODE: 0 first pass (src = A with signs, rows >= n
+// are zero, dst = Y; tiles past n are skipped), 1 middle pass (Y -> Y), 2 last pass (Y -> SA,
+// rows selected by pos, scale), 3 single pass (A -> SA).
+// zero_bits > 0 (middle/last pass directly after the first): rows whose first-pass tile starts
+// at or beyond n are known zero and not read.
+template <typename TIN, typename TY, typename TOUT, int CW, int MODE>
+__global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A, const TY* __restrict__ Ysrc,
+                                                       TY* __restrict__ Ydst, TOUT* __restrict__ SA, int64_t ldsa,
+                                                       int64_t n, int64_t d, int64_t lda, int64_t npad, int s, int b,
+                                                       int zero_bits, const double* __restrict__ eps,
+                                                       const int32_t* __restrict__ pos, double scale) {
+  using TACC = typename AccOf<TY>::type;
+  extern __shared__ unsigned char smem_raw[];
+  TACC* tile = reinterpret_cast<TACC*>(smem_raw);
+  const int tid = threadIdx.x;
+  const int R = 1 << b;
+  const int64_t tile_id = blockIdx.x;
+  const int64_t lo = tile_id & ((1ll << s) - 1);
+  const int64_t hi = tile_id >> s;
+  const int64_t base = (hi << (s + b)) | lo;
+  const int64_t c0 = (int64_t)blockIdx.y * CW;
+  constexpr bool FIRST = MODE == 0 || MODE == 3;
+  constexpr bool LAST = MODE == 2 || MODE == 3;
+
+  if (MODE == 0 && base >= n) return;  // all-padding tile: implicit zeros
+  if (LAST) {
+    int found = 0;
+    for (int j = tid; j < R; j += 256) found |= pos[base + ((int64_t)j << s)] >= 0;
+    if (!__syncthreads_or(found)) return;  // no selected row in this tile
+  }
+  // load
+  for (int idx = tid; idx < R * CW; idx += 256) {
+    const int j = idx / CW, c = idx % CW;
+    const int64_t row = base + ((int64_t)j << s);
+    const int64_t col = c0 + c;
+    TACC v = 0;
+    if (FIRST) {
+      if (col < d && row < n) {
+        if constexpr (sizeof(TACC) == 8)
+          v = (TACC)((double)A[row * lda + col] * eps[row]);
+        else
+          v = cvt<float>(A[row * lda + col]) * (float)eps[row];
+      }
+    } else {
+      const bool zero_src = zero_bits > 0 && ((row >> zero_bits) << zero_bits) >= n;
+      if (col < d && !zero_src) v = (TACC)Ysrc[row * d + col];
+    }
+    tile[j * CW + c] = v;
+  }
+  __syncthreads();
+  for (int g = 0; g < b; g += 3) {
+    const int nb = (b - g) >= 3 ? 3 : (b - g);
+    if (nb == 3) wht_group<TACC, 3, CW>(tile, R, g, tid);
+    else if (nb == 2) wht_group<TACC, 2, CW>(tile, R, g, tid);
+    else wht_group<TACC, 1, CW>(tile, R, g, tid);
+    __syncthreads();
+  }
+  // store
+  for (int idx = tid; idx < R * CW; idx += 256) {
+    const int j = idx / CW, c = idx % CW;
+    const int64_t row = base + ((int64_t)j << s);
+    const int64_t col = c0 + c;
+    if (col >= d) continue;
+    const TACC v = tile[j * CW + c];
+    if (LAST) {
+      const int32_t pr = pos[row];
+      if (pr >= 0) {
+        if constexpr (sizeof(TACC) == 8)
+          SA[(int64_t)pr * ldsa + col] = (TOUT)(v * scale);
+        else
+          SA[(int64_t)pr * ldsa + col] = cvt<TOUT>((float)(v * (float)scale));
+      }
+    } else {
+      Ydst[row * d + col] = (TY)v;
+    }
+  }
+}
+
+template <typename TIN, typename TY, typename TOUT>
+void launch_srht_apply(const TIN* A, int64_t n, int64_t d, int64_t lda, const double* eps, int64_t npad,
+                       const int32_t* pos, int64_t m, TY* Y, TOUT* SA, int64_t ldsa, hipStream_t st) {
+  using TACC = typename AccOf<TY>::type;
+  constexpr int CW = sizeof(TACC) == 8 ? 16 : 32;  // 128-byte row segments
+  int L = 0;
+  while ((1ll << L) < npad) ++L;
+  const int passes = L == 0 ? 1 : (L + kMaxTileBits - 1) / kMaxTileBits;
+  const double scale = 1.0 / std::sqrt((double)m);
+  const unsigned cblocks = (unsigned)ceil_div(d, CW);
+  int s = 0;
+  int first_bits = 0;
+  for (int p = 0; p < passes; ++p) {
+    const int remaining = L - s;
+    const int left = passes - p;
+    const int b = (remaining + left - 1) / left;
+    const size_t shmem = (size_t)(1 << b) * CW * sizeof(TACC);
+    const dim3 grid((unsigned)(npad >> b), cblocks);
+    const int zero_bits = (p == 1) ? first_bits : 0;
+    if (passes == 1) {
+      hipLaunchKernelGGL((wht_pass_kernel<TIN, TY, TOUT, CW, 3>), grid, dim3(256), shmem, st, A, (const TY*)nullptr,
+                         (TY*)nullptr, SA, ldsa, n, d, lda, npad, s, b, 0, eps, pos, scale);
+    } else if (p == 0) {
+      hipLaunchKernelGGL((wht_pass_kernel<TIN, TY, TOUT, CW, 0>), grid, dim3(256), shmem, st, A, (const TY*)nullptr, Y,
+                         SA, ldsa, n, d, lda, npad, s, b, 0, eps, pos, scale);
+      first_bits = b;
+    } else if (p == passes - 1) {
+      hipLaunchKernelGGL((wht_pass_kernel<TIN, TY, TOUT, CW, 2>), grid, dim3(256), shmem, st, A, (const TY*)Y,
+                         (TY*)nullptr, SA, ldsa, n, d, lda, npad, s, b, zero_bits, eps, pos, scale);
+    } else {
+      hipLaunchKernelGGL((wht_pass_kernel<TIN, TY, TOUT, CW, 1>), grid, dim3(256), shmem, st, A, (const TY*)Y, Y, SA,
+                         ldsa, n, d, lda, npad, s, b, zero_bits, eps, pos, scale);
+    }
+    AES_LAUNCH_CHECK();
+    s += b;
+  }
+}
+
+template void launch_srht_apply<double, double, double>(const double*, int64_t, int64_t, int64_t, const double*, int64_t,
+                                                        const int32_t*, int64_t, double*, double*, int64_t, hipStream_t);
+template void launch_srht_apply<__hip_bfloat16, float, __hip_bfloat16>(const __hip_bfloat16*, int64_t, int64_t, int64_t,
+                                                                       const double*, int64_t, const int32_t*, int64_t,
+                                                                       float*, __hip_bfloat16*, int64_t, hipStream_t);
+
+}  // namespace aes

@@ -1,0 +1,486 @@
+// O(d) vector work of the adaptive PCG / IHS loops (Algorithm 2, Algorithm 1), the
+// preconditioner applications as GEMVs with the inverted Cholesky factors (Sec. 4.1), and
+// small helpers (copies, casts, the rank-2 gradient of the adjoint).
+//
+// Scalar state of a solve with C columns, `scal` (device doubles):
+//   [0C) D      current decrement  r^T H_S^{-1} r  (IHS: 1/2 g^T H_S^{-1} g)
+//   [1C) DI     decrement at the last restart index I
+//   [2C) alpha  PCG step length of the pending candidate
+//   [3C) Dp     decrement of the pending candidate
+//   [4C) D0     decrement at the start (for the relative stop rule)
+//   [5C) pHp    curvature of the pending candidate
+//   [6C) lr     log(Dp / DI) of the pending candidate
+//   [7C .. 7C+8) host-read flags: 0 fail, 1 number of active columns, 2 nonfinite,
+//                3 accepted, 4 max log ratio over active columns, 5 max D over columns
+#include <cmath>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace aes {
+
+constexpr int kVT = 1024;  // threads of the single-workgroup vector kernels
+
+enum StopRule { kStopXrel = 0, kStopDtildeRel = 1, kStopFixed = 2, kStopRemark = 3 };
+
+// Column-wise block sum: thread t contributes v to column t % C (C a power of two dividing
+// 1024); on return buf[c] holds the sum for column c (fixed-order tree).
+__device__ __forceinline__ void col_reduce(double* buf, double v, int C) {
+  const int tid = threadIdx.x;
+  buf[tid] = v;
+  __syncthreads();
+  for (int s = kVT / 2; s >= C; s >>= 1) {
+    if (tid < s) buf[tid] += buf[tid + s];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kVT) void pcg_candidate_kernel(int64_t d, int C, const double* __restrict__ spart, int nwg,
+                                                            const double* __restrict__ lam, double nu2,
+                                                            const double* __restrict__ x, const double* __restrict__ r,
+                                                            const double* __restrict__ p, const double* __restrict__ q,
+                                                            double* __restrict__ xp, double* __restrict__ rp,
+                                                            double* __restrict__ scal, const int* __restrict__ active) {
+  __shared__ double buf[kVT];
+  __shared__ double alpha_s[64];
+  const int tid = threadIdx.x, col = tid % C, tpc = kVT / C;
+  double loc = 0.0;
+  if (spart) {
+    for (int64_t i = tid / C; i < d; i += tpc) {
+      const double pv = p[i * C + col];
+      loc += (lam ? lam[i] : 1.0) * pv * pv;
+    }
+    loc *= nu2;
+    for (int w = tid / C; w < nwg; w += tpc) loc += spart[(int64_t)w * C + col];
+  } else {
+    for (int64_t i = tid / C; i < d; i += tpc) loc += p[i * C + col] * q[i * C + col];
+  }
+  col_reduce(buf, loc, C);
+  if (tid < C) {
+    const double pHp = buf[tid];
+    scal[5 * C + tid] = pHp;
+    const double a = active[tid] ? scal[tid] / pHp : 0.0;
+    scal[2 * C + tid] = a;
+    alpha_s[tid] = a;
+  }
+  __syncthreads();
+  const double a = alpha_s[col];
+  if (active[col])
+    for (int64_t i = tid / C; i < d; i += tpc) {
+      const int64_t e = i * C + col;
+      xp[e] = x[e] + a * p[e];
+      rp[e] = r[e] - a * q[e];
+    }
+}
+
+void launch_pcg_candidate(int64_t d, int C, const double* spart, int nwg, const double* lam, double nu2, const double* x,
+                          const double* r, const double* p, const double* q, double* xp, double* rp, double* scal,
+                          const int* active, hipStream_t s) {
+  hipLaunchKernelGGL(pcg_candidate_kernel, dim3(1), dim3(kVT), 0, s, d, C, spart, nwg, lam, nu2, x, r, p, q, xp, rp, scal,
+                     active);
+  AES_LAUNCH_CHECK();
+}
+
+// Stop rule of one column after a commit (see oracle docs / design notes for the readings).
+__device__ __forceinline__ bool stop_test(int rule, double Dfull, double D0full, double xn2, bool resid_zero,
+                                          double stop_scale, double stop_sr, double tol2) {
+  if (Dfull <= 0.0 || resid_zero) return true;
+  switch (rule) {
+    case kStopXrel:
+      return stop_sr * Dfull <= stop_scale * xn2;
+    case kStopDtildeRel:
+      return Dfull <= tol2 * D0full;
+    case kStopRemark:
+      return 0.5 * Dfull <= stop_scale;
+    default:
+      return false;  // kStopFixed is decided by the host from the step count
+  }
+}
+
+// Shared tail of the PCG / IHS finish kernels.  `half` = 1 for the IHS decrement.
+template <bool IHS>
+__global__ __launch_bounds__(kVT) void finish_kernel(int64_t d, int C, double* __restrict__ x, double* __restrict__ r,
+                                                     double* __restrict__ p, const double* __restrict__ xp,
+                                                     const double* __restrict__ rp, const double* __restrict__ rtp,
+                                                     double* __restrict__ scal, int* __restrict__ active,
+                                                     int* __restrict__ flags, double thr, int force_reject,
+                                                     int adaptive, int at_cap, int stop_rule, double stop_scale,
+                                                     double stop_sr, double tol2) {
+  __shared__ double buf[kVT];
+  __shared__ double dp_s[64], xn_s[64], rz_s[64];
+  __shared__ int accept_s;
+  const int tid = threadIdx.x, col = tid % C, tpc = kVT / C;
+  const bool act = active[col] != 0;
+  double l1 = 0.0, l2 = 0.0, l3 = 0.0;
+  if (act)
+    for (int64_t i = tid / C; i < d; i += tpc) {
+      const int64_t e = i * C + col;
+      l1 += rp[e] * rtp[e];
+      l2 += xp[e] * xp[e];
+      l3 += fabs(rp[e]);
+    }
+  col_reduce(buf, l1, C);
+  if (tid < C) dp_s[tid] = IHS ? 0.5 * buf[tid] : buf[tid];
+  __syncthreads();
+  col_reduce(buf, l2, C);
+  if (tid < C) xn_s[tid] = buf[tid];
+  __syncthreads();
+  col_reduce(buf, l3, C);
+  if (tid < C) rz_s[tid] = buf[tid];
+  __syncthreads();
+  if (tid == 0) {
+    double* fl = scal + 7 * C;
+    bool fail = force_reject != 0;
+    bool nonfinite = false;
+    double maxlr = -INFINITY;
+    for (int c = 0; c < C; ++c) {
+      if (!active[c]) continue;
+      const double Dp = dp_s[c];
+      const double a = IHS ? 1.0 : scal[2 * C + c];
+      if (!isfinite(Dp) || !isfinite(a)) nonfinite = true;
+      const double lr = Dp > 0.0 ? log(Dp) - log(scal[C + c]) : -INFINITY;
+      scal[3 * C + c] = Dp;
+      scal[6 * C + c] = lr;
+      if (lr > maxlr) maxlr = lr;
+      if (lr > thr) fail = true;
+    }
+    const bool accept = !nonfinite && (!fail || !adaptive || at_cap);
+    fl[0] = fail ? 1.0 : 0.0;
+    fl[2] = nonfinite ? 1.0 : 0.0;
+    fl[3] = accept ? 1.0 : 0.0;
+    fl[4] = maxlr;
+    accept_s = accept;
+  }
+  __syncthreads();
+  if (!accept_s) {
+    if (tid == 0) {
+      int na = 0;
+      for (int c = 0; c < C; ++c) na += active[c] != 0;
+      scal[7 * C + 1] = (double)na;
+    }
+    return;
+  }
+  if (act) {
+    const double beta = IHS ? 0.0 : dp_s[col] / scal[col];
+    for (int64_t i = tid / C; i < d; i += tpc) {
+      const int64_t e = i * C + col;
+      x[e] = xp[e];
+      r[e] = rp[e];
+      p[e] = IHS ? rtp[e] : rtp[e] + beta * p[e];
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int na = 0;
+    double maxD = 0.0;
+    for (int c = 0; c < C; ++c) {
+      if (active[c]) {
+        const double Dp = dp_s[c];
+        scal[c] = Dp;
+        const double Df = IHS ? 2.0 * Dp : Dp;
+        const double D0f = IHS ? 2.0 * scal[4 * C + c] : scal[4 * C + c];
+        if (stop_test(stop_rule, Df, D0f, xn_s[c], rz_s[c] == 0.0, stop_scale, stop_sr, tol2)) active[c] = 0;
+      }
+      na += active[c] != 0;
+      if (scal[c] > maxD) maxD = scal[c];
+    }
+    scal[7 * C + 1] = (double)na;
+    scal[7 * C + 5] = maxD;
+  }
+}
+
+void launch_pcg_finish(int64_t d, int C, double* x, double* r, double* p, const double* xp, const double* rp,
+                       const double* rtp, double* scal, int* active, int* flags, double thr, int force_reject,
+                       int adaptive, int at_cap, int stop_rule, double stop_scale, double stop_sr, double tol2,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(finish_kernel<false>, dim3(1), dim3(kVT), 0, s, d, C, x, r, p, xp, rp, rtp, scal, active, flags, thr,
+                     force_reject, adaptive, at_cap, stop_rule, stop_scale, stop_sr, tol2);
+  AES_LAUNCH_CHECK();
+}
+
+void launch_ihs_finish(int64_t d, int C, double* x, double* g, double* sd, const double* xp, const double* gp,
+                       const double* sp, double* scal, int* active, int* flags, double thr, int force_reject,
+                       int adaptive, int at_cap, int stop_rule, double stop_scale, double stop_sr, double tol2,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(finish_kernel<true>, dim3(1), dim3(kVT), 0, s, d, C, x, g, sd, xp, gp, sp, scal, active, flags, thr,
+                     force_reject, adaptive, at_cap, stop_rule, stop_scale, stop_sr, tol2);
+  AES_LAUNCH_CHECK();
+}
+
+// (Re)initialisation after a factorisation: p = rt (PCG), D = r.rt (x 1/2 for the IHS),
+// DI = D, optionally D0 = D; then the stop rule at x.
+template <bool IHS>
+__global__ __launch_bounds__(kVT) void init_kernel(int64_t d, int C, const double* __restrict__ r,
+                                                   const double* __restrict__ rt, double* __restrict__ p,
+                                                   double* __restrict__ scal, int* __restrict__ active,
+                                                   int stop_rule, double stop_scale, double stop_sr, double tol2,
+                                                   const double* __restrict__ x, int set_d0) {
+  __shared__ double buf[kVT];
+  __shared__ double dd[64], xn[64], rz[64];
+  const int tid = threadIdx.x, col = tid % C, tpc = kVT / C;
+  const bool act = active[col] != 0;
+  double l1 = 0.0, l2 = 0.0, l3 = 0.0;
+  if (act)
+    for (int64_t i = tid / C; i < d; i += tpc) {
+      const int64_t e = i * C + col;
+      l1 += r[e] * rt[e];
+      if (x) l2 += x[e] * x[e];
+      l3 += fabs(r[e]);
+      if (!IHS) p[e] = rt[e];
+    }
+  col_reduce(buf, l1, C);
+  if (tid < C) dd[tid] = IHS ? 0.5 * buf[tid] : buf[tid];
+  __syncthreads();
+  col_reduce(buf, l2, C);
+  if (tid < C) xn[tid] = buf[tid];
+  __syncthreads();
+  col_reduce(buf, l3, C);
+  if (tid < C) rz[tid] = buf[tid];
+  __syncthreads();
+  if (tid == 0) {
+    int na = 0;
+    double maxD = 0.0;
+    for (int c = 0; c < C; ++c) {
+      if (active[c]) {
+        scal[c] = dd[c];
+        scal[C + c] = dd[c];
+        if (set_d0) scal[4 * C + c] = dd[c];
+        const double Df = IHS ? 2.0 * dd[c] : dd[c];
+        const double D0f = IHS ? 2.0 * scal[4 * C + c] : scal[4 * C + c];
+        if (stop_test(stop_rule, Df, D0f, xn[c], rz[c] == 0.0, stop_scale, stop_sr, tol2)) active[c] = 0;
+        if (!isfinite(dd[c])) scal[7 * C + 2] = 1.0;
+      }
+      na += active[c] != 0;
+      if (scal[c] > maxD) maxD = scal[c];
+    }
+    scal[7 * C + 1] = (double)na;
+    scal[7 * C + 5] = maxD;
+  }
+}
+
+void launch_pcg_init(int64_t d, int C, const double* r, const double* rt, double* p, double* scal, int* active,
+                     int* flags, int stop_rule, double stop_scale, double stop_sr, double tol2, const double* x,
+                     int set_d0, hipStream_t s) {
+  hipLaunchKernelGGL(init_kernel<false>, dim3(1), dim3(kVT), 0, s, d, C, r, rt, p, scal, active, stop_rule, stop_scale,
+                     stop_sr, tol2, x, set_d0);
+  AES_LAUNCH_CHECK();
+}
+
+void launch_ihs_init(int64_t d, int C, const double* g, const double* sd, double* scal, int* active, int* flags,
+                     int stop_rule, double stop_scale, double stop_sr, double tol2, const double* x, int set_d0,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(init_kernel<true>, dim3(1), dim3(kVT), 0, s, d, C, g, sd, nullptr, scal, active, stop_rule,
+                     stop_scale, stop_sr, tol2, x, set_d0);
+  AES_LAUNCH_CHECK();
+}
+
+__global__ void ihs_candidate_kernel(int64_t total, int C, const double* __restrict__ x, const double* __restrict__ sd,
+                                     double mu, double* __restrict__ xp, const int* __restrict__ active) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  xp[e] = active[e % C] ? x[e] - mu * sd[e] : x[e];
+}
+
+void launch_ihs_candidate(int64_t d, int C, const double* x, const double* sd, double mu, double* xp, const int* active,
+                          hipStream_t s) {
+  const int64_t total = d * C;
+  hipLaunchKernelGGL(ihs_candidate_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, total, C, x, sd, mu, xp,
+                     active);
+  AES_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------------------
+// Row-dot GEMV, one wave per row; C right-hand sides reduced with the transpose reduction.
+// ---------------------------------------------------------------------------------------
+template <int CC>
+__global__ __launch_bounds__(256) void rowdot_kernel(int64_t nrows, int64_t ncols, const double* __restrict__ M,
+                                                     int64_t ldm, int tri, const double* __restrict__ x,
+                                                     const double* __restrict__ xs, double ysgn,
+                                                     const double* __restrict__ zadd,
+                                                     const double* __restrict__ rowscale, double gscale,
+                                                     double* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i = wave; i < nrows; i += nwaves) {
+    int64_t jlo = 0, jhi = ncols;
+    if (tri == 1) jhi = i + 1 < ncols ? i + 1 : ncols;
+    if (tri == 2) jlo = i;
+    double acc[CC];
+#pragma unroll
+    for (int c = 0; c < CC; ++c) acc[c] = 0.0;
+    const double* Mi = M + i * ldm;
+    for (int64_t j = jlo + lane; j < jhi; j += 64) {
+      double mv = Mi[j];
+      if (xs) mv *= xs[j];
+#pragma unroll
+      for (int c = 0; c < CC; ++c) acc[c] = fma(mv, x[j * CC + c], acc[c]);
+    }
+    wave_transpose_sum<CC>(acc, lane);
+    constexpr int shift = 6 - ilog2_c(CC);
+    if ((lane & ((1 << shift) - 1)) == 0) {
+      const int c = (lane >> shift) & (CC - 1);
+      double v = ysgn * acc[0];
+      if (zadd) v += zadd[i * CC + c];
+      if (rowscale) v *= rowscale[i];
+      y[i * CC + c] = v * gscale;
+    }
+  }
+}
+
+void launch_rowdot(int64_t nrows, int64_t ncols, const double* M, int64_t ldm, int tri, const double* x, int C,
+                   const double* xs, double ysgn, const double* zadd, const double* rowscale, double gscale, double* y,
+                   hipStream_t s) {
+  if (nrows <= 0) return;
+  int64_t blocks = ceil_div(nrows, 4);
+  if (blocks > 4096) blocks = 4096;
+  dim3 g((unsigned)blocks), b(256);
+  switch (C) {
+    case 1: hipLaunchKernelGGL(rowdot_kernel<1>, g, b, 0, s, nrows, ncols, M, ldm, tri, x, xs, ysgn, zadd, rowscale, gscale, y); break;
+    case 2: hipLaunchKernelGGL(rowdot_kernel<2>, g, b, 0, s, nrows, ncols, M, ldm, tri, x, xs, ysgn, zadd, rowscale, gscale, y); break;
+    case 4: hipLaunchKernelGGL(rowdot_kernel<4>, g, b, 0, s, nrows, ncols, M, ldm, tri, x, xs, ysgn, zadd, rowscale, gscale, y); break;
+    case 8: hipLaunchKernelGGL(rowdot_kernel<8>, g, b, 0, s, nrows, ncols, M, ldm, tri, x, xs, ysgn, zadd, rowscale, gscale, y); break;
+    case 16: hipLaunchKernelGGL(rowdot_kernel<16>, g, b, 0, s, nrows, ncols, M, ldm, tri, x, xs, ysgn, zadd, rowscale, gscale, y); break;
+    case 32: hipLaunchKernelGGL(rowdot_kernel<32>, g, b, 0, s, nrows, ncols, M, ldm, tri, x, xs, ysgn, zadd, rowscale, gscale, y); break;
+    default: throw std::invalid_argument("rowdot: C must be a power of two <= 32");
+  }
+  AES_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------------------
+// Helpers.
+// ---------------------------------------------------------------------------------------
+__global__ void copy_cols_kernel(int64_t rows, int C, const double* __restrict__ src, int64_t lds, int csrc,
+                                 double* __restrict__ dst, int64_t ldd) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * C) return;
+  const int64_t i = e / C;
+  const int c = (int)(e % C);
+  dst[i * ldd + c] = c < csrc ? src[i * lds + c] : 0.0;
+}
+
+void launch_copy_cols(int64_t rows, int C, const double* src, int64_t lds, int csrc, double* dst, int64_t ldd,
+                      hipStream_t s) {
+  if (rows * C <= 0) return;
+  hipLaunchKernelGGL(copy_cols_kernel, dim3((unsigned)ceil_div(rows * C, 256)), dim3(256), 0, s, rows, C, src, lds, csrc,
+                     dst, ldd);
+  AES_LAUNCH_CHECK();
+}
+
+__global__ void fill_kernel(double* p, int64_t count, double v) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) p[e] = v;
+}
+
+void launch_fill(double* p, int64_t count, double v, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)ceil_div(count, 256)), dim3(256), 0, s, p, count, v);
+  AES_LAUNCH_CHECK();
+}
+
+__global__ void transpose_kernel(int64_t rows, int64_t cols, const double* __restrict__ src, int64_t lds,
+                                 double* __restrict__ dst, int64_t ldd) {
+  __shared__ double t[32][33];
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 32 x 8
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t r = r0 + k, c = c0 + tx;
+    t[k][tx] = (r < rows && c < cols) ? src[r * lds + c] : 0.0;
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t c = c0 + k, r = r0 + tx;
+    if (c < cols && r < rows) dst[c * ldd + r] = t[tx][k];
+  }
+}
+
+void launch_transpose(int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst, int64_t ldd,
+                      hipStream_t s) {
+  dim3 g((unsigned)ceil_div(cols, 32), (unsigned)ceil_div(rows, 32));
+  hipLaunchKernelGGL(transpose_kernel, g, dim3(256), 0, s, rows, cols, src, lds, dst, ldd);
+  AES_LAUNCH_CHECK();
+}
+
+__global__ void inv_kernel(int64_t count, const double* __restrict__ src, double* __restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) dst[e] = src ? 1.0 / src[e] : 1.0;
+}
+
+void launch_inv(int64_t count, const double* src, double* dst, hipStream_t s) {
+  hipLaunchKernelGGL(inv_kernel, dim3((unsigned)ceil_div(count, 256)), dim3(256), 0, s, count, src, dst);
+  AES_LAUNCH_CHECK();
+}
+
+template <typename TO>
+__global__ void cast_kernel(int64_t n, int64_t d, const double* __restrict__ A, int64_t lda, TO* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * d) return;
+  out[e] = (TO)A[(e / d) * lda + (e % d)];
+}
+
+template <typename TO>
+void launch_cast(int64_t n, int64_t d, const double* A, int64_t lda, TO* out, hipStream_t s) {
+  hipLaunchKernelGGL(cast_kernel<TO>, dim3((unsigned)ceil_div(n * d, 256)), dim3(256), 0, s, n, d, A, lda, out);
+  AES_LAUNCH_CHECK();
+}
+template void launch_cast<float>(int64_t, int64_t, const double*, int64_t, float*, hipStream_t);
+
+// One read of A (FP64), two outputs: FP32 and BF16 copies (round to nearest even).
+__global__ void cast2_kernel(int64_t n, int64_t d, const double* __restrict__ A, int64_t lda, float* __restrict__ a32,
+                             __hip_bfloat16* __restrict__ a16) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * d) return;
+  const double v = A[(e / d) * lda + (e % d)];
+  a32[e] = (float)v;
+  a16[e] = __float2bfloat16((float)v);
+}
+
+void launch_cast2(int64_t n, int64_t d, const double* A, int64_t lda, float* a32, __hip_bfloat16* a16, hipStream_t s) {
+  hipLaunchKernelGGL(cast2_kernel, dim3((unsigned)ceil_div(n * d, 256)), dim3(256), 0, s, n, d, A, lda, a32, a16);
+  AES_LAUNCH_CHECK();
+}
+
+__global__ void axpy_cols_kernel(int64_t total, int C, double* __restrict__ x, const double* __restrict__ e,
+                                 const int* __restrict__ active) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  if (!active || active[i % C]) x[i] += e[i];
+}
+
+void launch_axpy_cols(int64_t d, int C, double* x, const double* e, const int* active, hipStream_t s) {
+  const int64_t total = d * C;
+  hipLaunchKernelGGL(axpy_cols_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, total, C, x, e, active);
+  AES_LAUNCH_CHECK();
+}
+
+// dA[i, :] = -(z1_i y2 + z2_i y1), z1 = A y1, z2 = A y2: one wave per row, A read once.
+__global__ __launch_bounds__(256) void grad_rank2_kernel(const double* __restrict__ A, int64_t n, int64_t d, int64_t lda,
+                                                         const double* __restrict__ y1, const double* __restrict__ y2,
+                                                         double* __restrict__ dA, int64_t ldda) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i = wave; i < n; i += nwaves) {
+    const double* Ai = A + i * lda;
+    double v[2] = {0.0, 0.0};
+    for (int64_t j = lane; j < d; j += 64) {
+      const double a = Ai[j];
+      v[0] = fma(a, y1[j], v[0]);
+      v[1] = fma(a, y2[j], v[1]);
+    }
+    const double z1 = wave_sum(v[0]);
+    const double z2 = wave_sum(v[1]);
+    double* Di = dA + i * ldda;
+    for (int64_t j = lane; j < d; j += 64) Di[j] = -(z1 * y2[j] + z2 * y1[j]);
+  }
+}
+
+void launch_grad_rank2(const double* A, int64_t n, int64_t d, int64_t lda, const double* y1, const double* y2, double* dA,
+                       int64_t ldda, hipStream_t s) {
+  int64_t blocks = ceil_div(n, 4);
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(grad_rank2_kernel, dim3((unsigned)blocks), dim3(256), 0, s, A, n, d, lda, y1, y2, dA, ldda);
+  AES_LAUNCH_CHECK();
+}
+
+}  // namespace aes

@@ -1,0 +1,124 @@
+// Host-side launchers of the HIP kernels (all asynchronous on the given stream).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+
+namespace aes {
+
+// ---- fused H.v (k_hv.hip) ---------------------------------------------------------------
+// Number of workgroups used by hv_fused for a problem (the size of the partial buffers).
+int hv_num_blocks(int num_cu, int64_t n);
+// part[w*d + j] (w < nwg) and spart[w]: per-workgroup partials of A^T (A v) and ||A v||^2.
+template <typename TA>
+void launch_hv_fused(const TA* A, int64_t n, int64_t d, int64_t lda, const double* v, double* part,
+                     double* spart, int nwg, hipStream_t s);
+// Multi-RHS variant (C right-hand sides, V is d x C row-major): part[w][d][C], spart[w][C].
+template <typename TA>
+void launch_hv_multi(const TA* A, int64_t n, int64_t d, int64_t lda, const double* V, int C,
+                     double* part, double* spart, int nwg, hipStream_t s);
+// out[j,c] = sgn * (sum_w part[w][j][c] + nu2 * lam[j] * v[j,c]) + (b ? bsgn*b[j,c] : 0)
+void launch_hv_colsum(const double* part, int nwg, int64_t d, int C, const double* v,
+                      const double* lam, double nu2, double sgn, const double* b, double bsgn,
+                      double* out, hipStream_t s);
+
+// ---- vector kernels (k_vec.hip): one workgroup, C columns ------------------------------
+struct StepScalars;  // defined in k_vec.hip
+// PCG candidate: pHp_c = sum_w spart[w][c] + nu2 sum_j lam_j p_jc^2; alpha_c = D_c / pHp_c;
+// xp = x + alpha p; rp = r - alpha q   (only for active columns)
+void launch_pcg_candidate(int64_t d, int C, const double* spart, int nwg, const double* lam, double nu2,
+                          const double* x, const double* r, const double* p, const double* q,
+                          double* xp, double* rp, double* scal, const int* active, hipStream_t s);
+// PCG finish: Dp = rp . rtp per column; test; commit if accepted; stop rule.  See k_vec.hip.
+void launch_pcg_finish(int64_t d, int C, double* x, double* r, double* p, const double* xp,
+                       const double* rp, const double* rtp, double* scal, int* active, int* flags,
+                       double thr, int force_reject, int adaptive, int at_cap, int stop_rule,
+                       double stop_scale, double stop_sr, double tol2, hipStream_t s);
+// PCG (re)initialisation after a factorisation: rt = H_S^{-1} r given; p = rt; D = r.rt; DI = D.
+void launch_pcg_init(int64_t d, int C, const double* r, const double* rt, double* p, double* scal,
+                     int* active, int* flags, int stop_rule, double stop_scale, double stop_sr,
+                     double tol2, const double* x, int set_d0, hipStream_t s);
+// IHS: xp = x - mu s
+void launch_ihs_candidate(int64_t d, int C, const double* x, const double* sd, double mu, double* xp,
+                          const int* active, hipStream_t s);
+void launch_ihs_finish(int64_t d, int C, double* x, double* g, double* sd, const double* xp,
+                       const double* gp, const double* sp, double* scal, int* active, int* flags,
+                       double thr, int force_reject, int adaptive, int at_cap, int stop_rule,
+                       double stop_scale, double stop_sr, double tol2, hipStream_t s);
+void launch_ihs_init(int64_t d, int C, const double* g, const double* sd, double* scal, int* active,
+                     int* flags, int stop_rule, double stop_scale, double stop_sr, double tol2,
+                     const double* x, int set_d0, hipStream_t s);
+
+// ---- triangular / dense GEMV (k_vec.hip) ------------------------------------------------
+// y[i, c] = (ysgn * sum_{j in tri(i)} M[i, j] * xs[j] * x[j, c] + (zadd ? zadd[i, c] : 0))
+//           * (rowscale ? rowscale[i] : 1) * gscale
+// tri: 0 full [0, ncols), 1 lower [0, i], 2 upper [i, ncols)
+void launch_rowdot(int64_t nrows, int64_t ncols, const double* M, int64_t ldm, int tri,
+                   const double* x, int C, const double* xs, double ysgn, const double* zadd,
+                   const double* rowscale, double gscale, double* y, hipStream_t s);
+
+// ---- misc (k_vec.hip) --------------------------------------------------------------------
+void launch_copy_cols(int64_t rows, int C, const double* src, int64_t lds, int csrc, double* dst,
+                      int64_t ldd, hipStream_t s);
+void launch_fill(double* p, int64_t count, double v, hipStream_t s);
+void launch_transpose(int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst,
+                      int64_t ldd, hipStream_t s);
+void launch_inv(int64_t count, const double* src, double* dst, hipStream_t s);
+template <typename TO>
+void launch_cast(int64_t n, int64_t d, const double* A, int64_t lda, TO* out, hipStream_t s);
+void launch_cast2(int64_t n, int64_t d, const double* A, int64_t lda, float* a32, __hip_bfloat16* a16,
+                  hipStream_t s);
+void launch_axpy_cols(int64_t d, int C, double* x, const double* e, const int* active, hipStream_t s);
+
+// ---- sketches (k_sketch.hip) -------------------------------------------------------------
+struct SelectScratch {
+  uint64_t* keys;      // npad
+  int32_t* pos;        // npad: output row of padded row i, or -1
+  uint32_t* hist;      // 256 * 8
+  uint64_t* state;     // 4
+  uint32_t* blk;       // 2 * nblk
+};
+size_t select_blocks(int64_t npad);
+void launch_srht_select(uint64_t seed, int32_t problem, int64_t k, int64_t npad, int64_t m,
+                        const SelectScratch& sc, hipStream_t s);
+void launch_signs(uint64_t seed, int32_t problem, int64_t k, int64_t n, double* eps, hipStream_t s);
+// FWHT-based SRHT: SA (m x d, ld d) from A (n x d, lda); Y scratch npad x d of type TY.
+template <typename TIN, typename TY, typename TOUT>
+void launch_srht_apply(const TIN* A, int64_t n, int64_t d, int64_t lda, const double* eps, int64_t npad,
+                       const int32_t* pos, int64_t m, TY* Y, TOUT* SA, int64_t ldsa, hipStream_t s);
+void launch_gauss_sketch(const double* A, int64_t n, int64_t d, int64_t lda, int64_t m, uint64_t seed,
+                         int32_t problem, int64_t k, double* SA, int64_t ldsa, hipStream_t s);
+
+// ---- dense linear algebra on MFMA (k_dense.hip) ------------------------------------------
+// C = alpha * opA(A) * opB(B) + beta * C, batched with element strides; tri = 1 writes only
+// elements with row >= col (and skips tiles strictly above the diagonal).
+void gemm_f64(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+              int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta, double* C,
+              int64_t ldc, int64_t sC, int batch, int tri, hipStream_t s);
+// Gram of a sketch with split-K: G (dp x dp, ld dp) lower = SA^T SA + nu2 diag(lam) (padding
+// rows/cols beyond d get identity).  part: scratch of splits * dp * dp doubles.
+int gram_splits(int num_cu, int64_t m, int64_t d);
+void gram_tn(int64_t m, int64_t d, const double* SA, int64_t ldsa, double nu2, const double* lam,
+             double* part, int splits, double* G, int64_t dp, hipStream_t s);
+// BF16 SA (m x d, ld ldsa) with FP32 accumulation on MFMA; G as above in FP64.
+void gram_tn_bf16(int64_t m, int64_t d, const __hip_bfloat16* SA, int64_t ldsa, double nu2,
+                  const double* lam, float* part, int splits, double* G, int64_t dp, hipStream_t s);
+// W (mp x mp) lower = SA diag(1/lam) SA^T + nu2 I_m (padding gets identity).
+void gram_nt(int64_t m, int64_t d, const double* SA, int64_t ldsa, double nu2, const double* invlam,
+             double* scaled, double* W, int64_t mp, hipStream_t s);
+void gram_nt_bf16(int64_t m, int64_t d, const __hip_bfloat16* SA, int64_t ldsa, double nu2,
+                  const double* invlam, double* sa64, double* scaled, double* W, int64_t mp, hipStream_t s);
+// In-place blocked Cholesky of the lower triangle of G (np x np, np % 64 == 0); writes the
+// inverses of the 64 x 64 diagonal blocks of L to dinv (np/64 blocks of 64*64) and sets
+// *flag != 0 on a non-positive or NaN pivot.  Then Linv = L^{-1} (np x np) and LinvT.
+void cholesky_inplace(double* G, int64_t np, double* dinv, int* flag, hipStream_t s);
+void trtri_lower(const double* L, int64_t np, const double* dinv, double* Linv, double* tmp, hipStream_t s);
+
+// ---- adjoint (k_vec.hip) ------------------------------------------------------------------
+// dA[i, j] = -(z1[i] * y2[j] + z2[i] * y1[j]) with z1 = A y1, z2 = A y2 computed in-kernel.
+void launch_grad_rank2(const double* A, int64_t n, int64_t d, int64_t lda, const double* y1,
+                       const double* y2, double* dA, int64_t ldda, hipStream_t s);
+
+}  // namespace aes

@@ -1,0 +1,135 @@
+"""Kernel-level parity of the HIP library against the oracle (called through the C ABI)."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2104_14101_amd as aes
+import synth
+from oracle import factor as ofac
+from oracle import philox
+from oracle import sketch as osk
+
+from _helpers import hv_bound, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("n,d", [(1, 1), (37, 5), (1000, 256), (777, 300), (3001, 1024), (1500, 2048), (513, 4096),
+                                 (64, 4097)])
+def test_hv_matches_oracle(n, d):
+    rng = np.random.default_rng(n * 7 + d)
+    A = rng.standard_normal((n, d))
+    p = rng.standard_normal(d)
+    lam = 1 + 9 * rng.random(d)
+    nu = 0.37
+    q, php = aes.hv(to_dev(A), to_dev(p), nu, to_dev(lam))
+    torch.cuda.synchronize()
+    qref = A.T @ (A @ p) + nu ** 2 * lam * p
+    bound = hv_bound(A, lam, nu, p)
+    assert np.all(np.abs(q.cpu().numpy() - qref) <= bound)
+    Ap = A @ p
+    pref = Ap @ Ap + nu ** 2 * p @ (lam * p)
+    assert abs(php.item() - pref) <= 4 * (n + d) * 1.2e-16 * pref
+
+
+def test_hv_strided_rows():
+    rng = np.random.default_rng(3)
+    big = rng.standard_normal((500, 300))
+    A = to_dev(big)[:, :257]  # lda = 300, odd d
+    p = rng.standard_normal(257)
+    q, _ = aes.hv(A, to_dev(p), 0.1)
+    qref = big[:, :257].T @ (big[:, :257] @ p) + 0.01 * p
+    assert np.all(np.abs(q.cpu().numpy() - qref) <= hv_bound(big[:, :257], None, 0.1, p))
+
+
+def test_hv_full_size_pcg_workload():
+    P = synth.make_problem(65536, 2048, "pow:1", 1e-3, lam="uniform1_10", seed=11, backend="torch", device="cuda")
+    A = P["A"]
+    p = torch.randn(2048, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(1))
+    q, _ = aes.hv(A, p, 1e-3, P["lam"])
+    An, pn, ln = A.cpu().numpy(), p.cpu().numpy(), P["lam"].cpu().numpy()
+    qref = An.T @ (An @ pn) + 1e-6 * ln * pn
+    assert np.all(np.abs(q.cpu().numpy() - qref) <= hv_bound(An, ln, 1e-3, pn))
+
+
+@pytest.mark.parametrize("n,d,m", [(1, 3, 1), (8, 4, 4), (1000, 40, 16), (513, 33, 64), (5000, 17, 256),
+                                   (70000, 8, 1024), (300000, 3, 64)])
+def test_srht_bit_exact_on_integers(n, d, m):
+    # Integer data: every FWHT partial sum is exact in FP64; sqrt(m) is a power of two.
+    rng = np.random.default_rng(n + d + m)
+    A = rng.integers(-50, 51, size=(n, d)).astype(np.float64)
+    SA = aes.sketch(to_dev(A), m, "srht", seed=99, k=3).cpu().numpy()
+    ref = osk.srht(A, m, 99, 3)
+    np.testing.assert_array_equal(SA, ref)
+
+
+@pytest.mark.parametrize("n,d,m", [(4096, 256, 1024), (3000, 70, 100), (20000, 129, 1000)])
+def test_srht_float_data(n, d, m):
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((n, d))
+    SA = aes.sketch(to_dev(A), m, "srht", seed=4, k=1).cpu().numpy()
+    ref = osk.srht(A, m, 4, 1)
+    # Both sides apply the radix-2 stages in the same bit order, so the transform is
+    # bit-identical; only the final 1/sqrt(m) (a multiply vs a divide) may round differently.
+    np.testing.assert_allclose(SA, ref, rtol=4.5e-16, atol=0)
+
+
+def test_srht_full_size_sampled_rows():
+    P = synth.make_problem(65536, 2048, "pow:1", 1e-3, seed=12, backend="torch", device="cuda")
+    A = P["A"]
+    m = 4096
+    SA = aes.sketch(A, m, "srht", seed=5, k=2).cpu().numpy()
+    An = A.cpu().numpy()
+    for j in (0, 1, 777, 4095):
+        ref = osk.srht_row(An, m, 5, 2, j)
+        assert np.max(np.abs(SA[j] - ref)) <= 1e-13 * np.max(np.abs(ref)) * 16
+
+
+@pytest.mark.parametrize("n,d,m", [(300, 40, 70), (1000, 65, 128), (129, 7, 3)])
+def test_gaussian_sketch(n, d, m):
+    rng = np.random.default_rng(6)
+    A = rng.standard_normal((n, d))
+    SA = aes.sketch(to_dev(A), m, "gauss", seed=8, k=2).cpu().numpy()
+    ref = osk.gaussian(A, m, 8, 2)
+    # G entries agree to a few ulps (device and host libm), sums of n terms
+    assert np.max(np.abs(SA - ref)) <= 1e-13 * np.sqrt(n) * np.max(np.abs(ref)) + 1e-14
+
+
+@pytest.mark.parametrize("m,d", [(200, 100), (100, 100), (37, 100), (1, 5), (300, 257), (129, 130)])
+def test_factor_and_apply(m, d):
+    rng = np.random.default_rng(m + d)
+    SA = rng.standard_normal((m, d)) / np.sqrt(m)
+    lam = 1 + rng.random(d)
+    nu = 0.05
+    G, L = aes.factor(to_dev(SA), nu, to_dev(lam))
+    P = ofac.SketchedHessian(SA, nu, lam)
+    Lref = P.L
+    Gn = G.cpu().numpy()
+    if m >= d:
+        Gref = SA.T @ SA + nu ** 2 * np.diag(lam)
+    else:
+        Gref = (SA / lam) @ SA.T + nu ** 2 * np.eye(m)
+    np.testing.assert_allclose(np.tril(Gn), np.tril(Gref), rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(L.cpu().numpy(), Lref, rtol=1e-9, atol=1e-11)
+    for c in (1, 2, 4, 8):
+        z = rng.standard_normal((d, c))
+        v = aes.precond_apply(to_dev(SA), nu, to_dev(lam), to_dev(z)).cpu().numpy()
+        vref = P.apply(z)
+        np.testing.assert_allclose(v, vref, rtol=1e-8, atol=1e-10 * np.max(np.abs(vref)))
+
+
+def test_factor_not_spd_is_reported():
+    SA = np.zeros((4, 6))
+    with pytest.raises(aes.AesError, match="not_spd"):
+        aes.factor(to_dev(SA), 1e-200, None)  # nu^2 underflows to 0: a zero pivot
+
+
+def test_philox_streams_on_device_match_oracle():
+    # signs and row selection are checked through the SRHT of the identity (H E columns)
+    n = 64
+    I = np.eye(n)
+    SA = aes.sketch(to_dev(I), 16, "srht", seed=2**63 + 5, k=7, problem=3).cpu().numpy()
+    ref = osk.srht(I, 16, 2**63 + 5, 7, problem=3)
+    np.testing.assert_array_equal(SA, ref)
+    eps = philox.signs(2**63 + 5, 7, n, problem=3)
+    assert np.all(np.sign(SA[0]) == np.sign(ref[0])) and set(np.unique(eps)) <= {-1.0, 1.0}

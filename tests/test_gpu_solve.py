@@ -1,0 +1,164 @@
+"""Solver-level parity of the HIP library against the oracle on small workloads."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2104_14101_amd as aes
+import synth
+from oracle import adjoint, reference, solvers
+
+from _helpers import to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def small():
+    P = synth.make_workload("pcg_n4096_d256", seed=0)
+    P["xref"] = reference.reference_solution(P["A"], P["b"], P["nu"], P["lam"])
+    P["dA"] = to_dev(P["A"])
+    P["db"] = to_dev(P["b"])
+    P["dlam"] = to_dev(P["lam"])
+    return P
+
+
+def _traj_gpu(info):
+    return [(e["t"], e["m"], e["accept"]) for e in info["trace"]]
+
+
+def _traj_cpu(io):
+    return [(e["t"], e["m"], bool(e["accept"])) for e in io.trace]
+
+
+@pytest.mark.parametrize("method", ["pcg", "ihs"])
+def test_srht_trajectory_and_accuracy(small, method):
+    kw = dict(method=method, sketch="srht", m_init=8, seed=1, tol=1e-10)
+    x, info = aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], trace_cap=256, **kw)
+    xo, io = solvers.solve(small["A"], small["b"], small["nu"], small["lam"], solvers.Options(**kw))
+    assert info["status"] == "ok"
+    assert _traj_gpu(info) == _traj_cpu(io)
+    assert info["iterations"] == io.iterations and info["final_m"] == io.final_m
+    assert info["resketches"] == io.resketches and info["a_passes"] == io.a_passes
+    assert reference.rel_error(x.cpu().numpy(), small["xref"]) <= 1e-10
+    assert reference.rel_error(x.cpu().numpy(), xo) <= 1e-9
+
+
+@pytest.mark.parametrize("method", ["pcg", "ihs"])
+def test_gaussian_accuracy(small, method):
+    x, info = aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], method=method, sketch="gauss",
+                        m_init=8, seed=1, tol=1e-10)
+    assert info["status"] == "ok"
+    assert reference.rel_error(x.cpu().numpy(), small["xref"]) <= 1e-10
+    assert info["final_m"] <= 4096
+
+
+def test_lambda_and_ragged_shape():
+    P = synth.make_problem(3000, 77, "pow:1", 1e-3, lam="uniform1_10", seed=5)
+    xr = reference.reference_solution(P["A"], P["b"], P["nu"], P["lam"])
+    kw = dict(m_init=2, seed=9, tol=1e-10)
+    x, info = aes.solve(to_dev(P["A"]), to_dev(P["b"]), P["nu"], to_dev(P["lam"]), trace_cap=256, **kw)
+    xo, io = solvers.adaptive_pcg(P["A"], P["b"], P["nu"], P["lam"], solvers.Options(**kw))
+    assert _traj_gpu(info) == _traj_cpu(io)
+    assert reference.rel_error(x.cpu().numpy(), xr) <= 1e-10
+
+
+def test_multiple_rhs(small):
+    rng = np.random.default_rng(4)
+    Bm = small["A"].T @ rng.standard_normal((4096, 3))
+    kw = dict(m_init=8, seed=4, tol=1e-10)
+    X, info = aes.solve(small["dA"], to_dev(Bm), small["nu"], small["dlam"], trace_cap=256, **kw)
+    Xo, io = solvers.adaptive_pcg(small["A"], Bm, small["nu"], small["lam"], solvers.Options(**kw))
+    Xr = reference.reference_solution(small["A"], Bm, small["nu"], small["lam"])
+    assert _traj_gpu(info) == _traj_cpu(io)
+    assert np.all(reference.rel_error(X.cpu().numpy(), Xr) <= 1e-10)
+
+
+def test_forced_rejection_and_max_iter(small):
+    kw = dict(m_init=512, seed=2, tol=1e-10, force_reject_at=3)
+    x, info = aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], trace_cap=256, **kw)
+    xo, io = solvers.adaptive_pcg(small["A"], small["b"], small["nu"], small["lam"],
+                                  solvers.Options(m_init=512, seed=2, tol=1e-10, force_reject_at=(3,)))
+    assert _traj_gpu(info) == _traj_cpu(io)
+    assert info["a_passes"] == io.a_passes
+    x3, info3 = aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], m_init=8, seed=1, max_iter=3)
+    xo3, io3 = solvers.adaptive_pcg(small["A"], small["b"], small["nu"], small["lam"],
+                                    solvers.Options(m_init=8, seed=1, max_iter=3))
+    assert info3["status"] == "max_iter" and io3.status == "max_iter"
+    assert reference.rel_error(x3.cpu().numpy(), xo3) <= 1e-8
+
+
+@pytest.mark.parametrize("stop", ["dtilde_rel", "fixed", "remark"])
+def test_stop_rules(small, stop):
+    tol = {"dtilde_rel": 1e-9, "fixed": 1e-10, "remark": 1e-12}[stop]
+    kw = dict(m_init=8, seed=1, stop=stop, tol=tol, max_iter=12 if stop == "fixed" else 200)
+    x, info = aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], **kw)
+    xo, io = solvers.adaptive_pcg(small["A"], small["b"], small["nu"], small["lam"], solvers.Options(**kw))
+    assert info["status"] == "ok" and io.status == "ok"
+    assert info["iterations"] == io.iterations
+
+
+def test_edge_cases(small):
+    d = small["A"].shape[1]
+    x, info = aes.solve(small["dA"], torch.zeros(d, dtype=torch.float64, device="cuda"), small["nu"])
+    assert info["iterations"] == 0 and not torch.any(x)
+    A1 = to_dev(np.array([[2.0]]))
+    x, info = aes.solve(A1, to_dev(np.array([3.0])), 0.5)
+    assert abs(x.item() - 3.0 / 4.25) < 1e-14
+    with pytest.raises(aes.AesError, match="invalid_arg"):
+        aes.solve(small["dA"], small["db"], 0.0)
+    with pytest.raises(aes.AesError, match="invalid_arg"):
+        aes.solve(small["dA"], small["db"], 1e-2, rho=1.0)
+    with pytest.raises(aes.AesError, match="invalid_arg"):
+        aes.solve(small["dA"], small["db"], 1e-2, -small["dlam"])
+
+
+def test_x0_warm_start(small):
+    x0 = small["xref"] + 1e-3 * np.random.default_rng(0).standard_normal(small["xref"].shape)
+    kw = dict(m_init=8, seed=6, tol=1e-10)
+    x, info = aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], x0=to_dev(x0), trace_cap=256, **kw)
+    xo, io = solvers.adaptive_pcg(small["A"], small["b"], small["nu"], small["lam"], solvers.Options(x0=x0, **kw))
+    assert _traj_gpu(info) == _traj_cpu(io)
+    assert reference.rel_error(x.cpu().numpy(), small["xref"]) <= 1e-10
+
+
+def test_deterministic(small):
+    x1, _ = aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], m_init=8, seed=1)
+    x2, _ = aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], m_init=8, seed=1)
+    assert torch.equal(x1, x2)
+
+
+def test_mixed_precision(small):
+    x, info = aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], precision="mixed", m_init=8, seed=1)
+    assert info["status"] == "ok", info
+    assert reference.rel_error(x.cpu().numpy(), small["xref"]) <= 1e-10
+    assert info["refine_sweeps"] >= 2
+
+
+def test_batched_equals_singles():
+    probs = []
+    for i, (n, d) in enumerate([(2048, 64), (3000, 128), (1024, 256)]):
+        P = synth.make_problem(n, d, "geo:0.98", 10.0 ** (-1 - i), nrhs=2, seed=20 + i)
+        probs.append(dict(A=to_dev(P["A"]), b=to_dev(P["b"]), nu=P["nu"], xref=reference.reference_solution(
+            P["A"], P["b"], P["nu"])))
+    res = aes.solve_batched(probs, tol=1e-10, m_init=16, seed=3)
+    for p, (x, info) in enumerate(res):
+        assert info["status"] == "ok"
+        assert np.all(reference.rel_error(x.cpu().numpy(), probs[p]["xref"]) <= 1e-10)
+        xs, _ = aes.solve(probs[p]["A"], probs[p]["b"], probs[p]["nu"], m_init=16, seed=3, problem=p)
+        assert torch.equal(xs, x)
+
+
+def test_autograd_adjoint():
+    P = synth.make_problem(2048, 64, "pow:0.5", 1e-2, seed=31, with_xt=True)
+    A, b, nu, xt = P["A"], P["b"], P["nu"], P["xt"]
+    At = to_dev(A).requires_grad_(True)
+    bt = to_dev(b).requires_grad_(True)
+    ln = torch.tensor(np.log(nu), dtype=torch.float64, device="cuda", requires_grad=True)
+    x = aes.SketchSolve.apply(At, bt, ln, None, dict(m_init=16, seed=2, tol=1e-12))
+    loss = 0.5 * torch.sum((x - to_dev(xt)) ** 2)
+    loss.backward()
+    xs = reference.reference_solution(A, b, nu)
+    _, adj, db, dA, dln = adjoint.gradients(A, b, nu, xs - xt, x=xs)
+    assert np.max(np.abs(bt.grad.cpu().numpy() - db)) <= 1e-9 * np.max(np.abs(db))
+    assert np.max(np.abs(At.grad.cpu().numpy() - dA)) <= 1e-9 * np.max(np.abs(dA))
+    assert abs(ln.grad.item() - dln) <= 1e-9 * abs(dln)
