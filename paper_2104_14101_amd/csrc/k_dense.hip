@@ -40,7 +40,8 @@ __device__ __forceinline__ void mfma_ktile(const double (*As)[BT + 1], const dou
   }
 }
 
-// Output element of lane `lane`, register r of block (bi, bj): row 4*(lane/16)+r, col lane%16.
+// Output element of lane `lane`, register r of block (bi, bj) for v_mfma_f64_16x16x4f64:
+// row (lane/16) + 4*r, column lane%16 (measured on gfx950 against the oracle).
 template <typename Store>
 __device__ __forceinline__ void store_tile(const d4 (&acc)[2][2], int lane, int wm, int wn, int64_t m0, int64_t n0,
                                            Store st) {
@@ -50,7 +51,7 @@ __device__ __forceinline__ void store_tile(const d4 (&acc)[2][2], int lane, int 
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t i = m0 + wm * 32 + bi * 16 + 4 * (lane >> 4) + r;
+        const int64_t i = m0 + wm * 32 + bi * 16 + (lane >> 4) + 4 * r;
         const int64_t j = n0 + wn * 32 + bj * 16 + (lane & 15);
         st(i, j, acc[bi][bj][r]);
       }
