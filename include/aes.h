@@ -92,6 +92,8 @@ typedef struct {
   int32_t trace_cap;     /* capacity of `trace` (entries) */
   aes_trace_entry* trace;   /* host, optional: filled with the attempted steps */
   const double* x0;         /* device d x c (ld = ldx) initial point, or NULL for 0 */
+  int32_t profile;          /* 1: time every fused H.v launch with HIP events on `stream` */
+  int32_t pad_;
 } aes_options;
 
 typedef struct {
@@ -107,6 +109,8 @@ typedef struct {
   double time_total_ms;   /* host-measured wall time of the call */
   int32_t m_cap_reached;  /* a failed test was accepted because m reached its cap */
   int32_t status;         /* aes_status of the solve */
+  double time_hv_ms;      /* options.profile: summed event time of the fused H.v kernels */
+  int64_t hv_launches;    /* options.profile: number of fused H.v launches timed */
 } aes_info;
 
 /* Create a handle bound to HIP device `device` (allocates nothing large). */

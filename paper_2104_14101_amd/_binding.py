@@ -30,14 +30,14 @@ class Options(ctypes.Structure):
                 ("rho", c_double), ("m_init", c_int64), ("m_max", c_int64), ("max_iter", c_int64),
                 ("seed", c_uint64), ("problem", c_int32), ("adaptive", c_int32), ("force_reject_at", c_int64),
                 ("inner_tol", c_double), ("max_refine", c_int32), ("trace_cap", c_int32),
-                ("trace", POINTER(TraceEntry)), ("x0", c_void_p)]
+                ("trace", POINTER(TraceEntry)), ("x0", c_void_p), ("profile", c_int32), ("pad_", c_int32)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("iterations", c_int64), ("attempts", c_int64), ("final_m", c_int64), ("resketches", c_int64),
                 ("a_passes", c_int64), ("refine_sweeps", c_int64), ("trace_len", c_int64),
                 ("dtilde_final", c_double), ("time_sketch_ms", c_double), ("time_total_ms", c_double),
-                ("m_cap_reached", c_int32), ("status", c_int32)]
+                ("m_cap_reached", c_int32), ("status", c_int32), ("time_hv_ms", c_double), ("hv_launches", c_int64)]
 
     def as_dict(self):
         out = {f[0]: getattr(self, f[0]) for f in self._fields_}

@@ -29,6 +29,16 @@ struct aes_handle_s {
   std::unordered_map<std::string, std::pair<void*, size_t>> bufs;
   std::string err;
   double* pinned = nullptr;  // host-visible flag block
+  std::vector<hipEvent_t> events;  // pairs for timing the fused H.v launches
+
+  hipEvent_t event(size_t i) {
+    while (events.size() <= i) {
+      hipEvent_t e;
+      AES_HIP(hipEventCreate(&e));
+      events.push_back(e);
+    }
+    return events[i];
+  }
 
   template <typename T>
   T* buf(const std::string& name, size_t count) {
@@ -52,6 +62,8 @@ struct aes_handle_s {
   void release() {
     for (auto& kv : bufs) (void)hipFree(kv.second.first);
     bufs.clear();
+    for (auto e : events) (void)hipEventDestroy(e);
+    events.clear();
     if (pinned) (void)hipHostFree(pinned);
     pinned = nullptr;
   }
@@ -205,10 +217,16 @@ class Solver {
   // out = sgn * (H v) + bsgn * b    (H = A^T A + nu^2 Lambda); A in FP64 or (inner) FP32.
   void hv(const double* v, double* out, double sgn, const double* bb, double bsgn, bool use32) {
     if (C_ == 1) {
+      const bool prof = o_.profile && !use32;
+      if (prof) AES_HIP(hipEventRecord(h_->event(2 * n_events_), s_));
       if (use32)
         launch_hv_fused<float>(A32_, n_, d_, d_, v, part_, spart_, nwg_, s_);
       else
         launch_hv_fused<double>(P_.A, n_, d_, P_.lda, v, part_, spart_, nwg_, s_);
+      if (prof) {
+        AES_HIP(hipEventRecord(h_->event(2 * n_events_ + 1), s_));
+        ++n_events_;
+      }
       launch_hv_colsum(part_, nwg_, d_, 1, v, lam_, nu2_, sgn, bb, bsgn, out, s_);
     } else {
       // Z = A V (n x C); partial Q_w = A_w^T Z_w over row splits; fixed-order column sum.
@@ -480,7 +498,16 @@ class Solver {
       st = AES_ERR_INVALID_ARG;
       h_->err = e.what();
     }
+    double hv_ms = 0.0;
+    if (o_.profile && st != AES_ERR_HIP) {
+      for (int64_t i = 0; i < n_events_; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, h_->events[2 * i], h_->events[2 * i + 1]) == hipSuccess) hv_ms += ms;
+      }
+    }
     if (info) {
+      info->time_hv_ms = hv_ms;
+      info->hv_launches = n_events_;
       info->iterations = iters_;
       info->attempts = attempts_;
       info->final_m = m_;
@@ -618,6 +645,7 @@ class Solver {
   int64_t iters_ = 0, attempts_ = 0, resketches_ = 0, a_passes_ = 0, sweeps_ = 0, trace_len_ = 0;
   int m_cap_reached_ = 0;
   double t_sketch_ = 0;
+  int64_t n_events_ = 0;
 };
 
 aes_status guard(aes_handle h, const std::function<void()>& f) {
