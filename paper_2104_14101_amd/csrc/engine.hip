@@ -320,12 +320,10 @@ class Solver {
   }
 
   void factor_and_invert(double* G, int64_t np, int* flag) {
-    double* dinv = B<double>("dinv", (size_t)(np / 64) * 4096);
-    cholesky_inplace(G, np, dinv, flag, s_);
     Linv_ = B<double>("Linv", (size_t)np * np);
     LinvT_ = B<double>("LinvT", (size_t)np * np);
-    double* tmp = B<double>("trtri_tmp", (size_t)(np / 64) * 4096);
-    trtri_lower(G, np, dinv, Linv_, tmp, s_);
+    double* tmp = B<double>("cholinv_tmp", cholinv_tmp_size(np));
+    cholinv(G, np, Linv_, tmp, flag, s_);
     launch_transpose(np, np, Linv_, np, LinvT_, np, s_);
   }
 
@@ -991,8 +989,9 @@ aes_status aes_factor(aes_handle h, void* stream, int64_t m, int64_t d, const do
     launch_copy_cols(dim, (int)dim, Gp, fp, (int)dim, G, dim, s);
     int* flag = h->buf<int>("fa.flag", 1);
     AES_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
-    double* dinv = h->buf<double>("fa.dinv", (size_t)(fp / 64) * 4096);
-    cholesky_inplace(Gp, fp, dinv, flag, s);
+    double* linv = h->buf<double>("fa.linv", (size_t)fp * fp);
+    double* tmp = h->buf<double>("fa.tmp", cholinv_tmp_size(fp));
+    cholinv(Gp, fp, linv, tmp, flag, s);
     launch_copy_cols(dim, (int)dim, Gp, fp, (int)dim, L, dim, s);
     int hf = 0;
     AES_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));

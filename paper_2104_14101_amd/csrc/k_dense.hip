@@ -57,85 +57,131 @@ __device__ __forceinline__ void store_tile(const d4 (&acc)[2][2], int lane, int 
       }
 }
 
-template <bool TA, bool TB>
+// Tiled GEMM, 256 threads = 2 x 2 waves, wave tile (BM/2) x (BN/2) of 16 x 16 MFMA blocks.
+// The next K-step is prefetched into registers while the current one is multiplied from LDS
+// (double-buffered LDS, one barrier per K-step).
+template <bool TA, bool TB, int BM, int BN, int BK>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int64_t K, double alpha,
                                                        const double* __restrict__ A, int64_t lda, int64_t sA,
                                                        const double* __restrict__ B, int64_t ldb, int64_t sB,
                                                        double beta, double* C, int64_t ldc, int64_t sC, int tri) {
+  constexpr int LA = BM * BK / 256, LB = BK * BN / 256;
+  constexpr int WI = BM / 32, WJ = BN / 32;  // 16 x 16 blocks per wave
   const int64_t bz = blockIdx.z;
   A += bz * sA;
   B += bz * sB;
   C += bz * sC;
-  const int64_t m0 = (int64_t)blockIdx.y * BT, n0 = (int64_t)blockIdx.x * BT;
-  if (tri && n0 > m0 + BT - 1) return;
-  __shared__ double As[BKT][BT + 1], Bs[BKT][BT + 1];
+  const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+  if (tri && n0 > m0 + BM - 1) return;
+  __shared__ double As[2][BK][BM + 1], Bs[2][BK][BN + 1];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wm = w >> 1, wn = w & 1;
-  d4 acc[2][2];
+  d4 acc[WI][WJ];
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int bi = 0; bi < WI; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
-
-  for (int64_t k0 = 0; k0 < K; k0 += BKT) {
+    for (int bj = 0; bj < WJ; ++bj) acc[bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
+  double ra[LA], rb[LB];
+  auto load = [&](int64_t k0) {
 #pragma unroll
-    for (int rep = 0; rep < 4; ++rep) {
-      const int idx = tid + rep * 256;
-      int i, k;
-      if (!TA) {
-        k = idx & 15;
-        i = idx >> 4;
-      } else {
-        i = idx & 63;
-        k = idx >> 6;
-      }
+    for (int q = 0; q < LA; ++q) {
+      const int idx = tid + q * 256;
+      const int k = TA ? idx / BM : idx % BK;
+      const int i = TA ? idx % BM : idx / BK;
       const int64_t gi = m0 + i, gk = k0 + k;
-      double va = 0.0;
-      if (gi < M && gk < K) va = TA ? A[gk * lda + gi] : A[gi * lda + gk];
-      As[k][i] = va;
-      int j;
-      if (!TB) {
-        j = idx & 63;
-        k = idx >> 6;
-      } else {
-        k = idx & 15;
-        j = idx >> 4;
-      }
-      const int64_t gj = n0 + j, gk2 = k0 + k;
-      double vb = 0.0;
-      if (gj < N && gk2 < K) vb = TB ? B[gj * ldb + gk2] : B[gk2 * ldb + gj];
-      Bs[k][j] = vb;
+      ra[q] = (gi < M && gk < K) ? (TA ? A[gk * lda + gi] : A[gi * lda + gk]) : 0.0;
     }
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      const int idx = tid + q * 256;
+      const int k = TB ? idx % BK : idx / BN;
+      const int j = TB ? idx / BK : idx % BN;
+      const int64_t gj = n0 + j, gk = k0 + k;
+      rb[q] = (gj < N && gk < K) ? (TB ? B[gj * ldb + gk] : B[gk * ldb + gj]) : 0.0;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < LA; ++q) {
+      const int idx = tid + q * 256;
+      const int k = TA ? idx / BM : idx % BK;
+      const int i = TA ? idx % BM : idx / BK;
+      As[buf][k][i] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      const int idx = tid + q * 256;
+      const int k = TB ? idx % BK : idx / BN;
+      const int j = TB ? idx / BK : idx % BN;
+      Bs[buf][k][j] = rb[q];
+    }
+  };
+  load(0);
+  store(0);
+  __syncthreads();
+  int cur = 0;
+  for (int64_t k0 = 0; k0 < K; k0 += BK) {
+    const bool more = k0 + BK < K;
+    if (more) load(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      const int kl = kk * 4 + (lane >> 4);
+      double a[WI], b[WJ];
+#pragma unroll
+      for (int bi = 0; bi < WI; ++bi) a[bi] = As[cur][kl][wm * (BM / 2) + bi * 16 + (lane & 15)];
+#pragma unroll
+      for (int bj = 0; bj < WJ; ++bj) b[bj] = Bs[cur][kl][wn * (BN / 2) + bj * 16 + (lane & 15)];
+#pragma unroll
+      for (int bi = 0; bi < WI; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < WJ; ++bj)
+          acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+    }
+    if (more) store(cur ^ 1);
     __syncthreads();
-    mfma_ktile(As, Bs, lane, wm, wn, acc);
-    __syncthreads();
+    cur ^= 1;
   }
-  store_tile(acc, lane, wm, wn, m0, n0, [&](int64_t i, int64_t j, double v) {
-    if (i < M && j < N && (!tri || i >= j)) {
-      double out = alpha * v;
-      if (beta != 0.0) out += beta * C[i * ldc + j];
-      C[i * ldc + j] = out;
-    }
-  });
+#pragma unroll
+  for (int bi = 0; bi < WI; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < WJ; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // v_mfma_f64_16x16x4f64 output: register r of lane l is row (l/16) + 4r, column l%16
+        const int64_t i = m0 + wm * (BM / 2) + bi * 16 + (lane >> 4) + 4 * r;
+        const int64_t j = n0 + wn * (BN / 2) + bj * 16 + (lane & 15);
+        if (i < M && j < N && (!tri || i >= j)) {
+          double out = alpha * acc[bi][bj][r];
+          if (beta != 0.0) out += beta * C[i * ldc + j];
+          C[i * ldc + j] = out;
+        }
+      }
+}
+
+template <bool TA, bool TB>
+static void gemm_dispatch(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda, int64_t sA,
+                          const double* B, int64_t ldb, int64_t sB, double beta, double* C, int64_t ldc, int64_t sC,
+                          int batch, int tri, hipStream_t s) {
+  const int64_t tiles128 = ceil_div(M, 128) * ceil_div(N, 128) * batch;
+  if (M >= 128 && N >= 128 && tiles128 >= 128) {
+    dim3 grid((unsigned)ceil_div(N, 128), (unsigned)ceil_div(M, 128), (unsigned)batch);
+    hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, 128, 128, 16>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B,
+                       ldb, sB, beta, C, ldc, sC, tri);
+  } else {
+    dim3 grid((unsigned)ceil_div(N, 64), (unsigned)ceil_div(M, 64), (unsigned)batch);
+    hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, 64, 64, 32>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B,
+                       ldb, sB, beta, C, ldc, sC, tri);
+  }
+  AES_LAUNCH_CHECK();
 }
 
 void gemm_f64(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
               int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta, double* C, int64_t ldc, int64_t sC,
               int batch, int tri, hipStream_t s) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
-  dim3 grid((unsigned)ceil_div(N, BT), (unsigned)ceil_div(M, BT), (unsigned)batch);
-  if (!ta && !tb)
-    hipLaunchKernelGGL((gemm_f64_kernel<false, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB,
-                       beta, C, ldc, sC, tri);
-  else if (!ta && tb)
-    hipLaunchKernelGGL((gemm_f64_kernel<false, true>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB,
-                       beta, C, ldc, sC, tri);
-  else if (ta && !tb)
-    hipLaunchKernelGGL((gemm_f64_kernel<true, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB,
-                       beta, C, ldc, sC, tri);
-  else
-    hipLaunchKernelGGL((gemm_f64_kernel<true, true>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB,
-                       beta, C, ldc, sC, tri);
-  AES_LAUNCH_CHECK();
+  if (!ta && !tb) gemm_dispatch<false, false>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tri, s);
+  else if (!ta && tb) gemm_dispatch<false, true>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tri, s);
+  else if (ta && !tb) gemm_dispatch<true, false>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tri, s);
+  else gemm_dispatch<true, true>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tri, s);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -302,109 +348,141 @@ void gram_nt_bf16(int64_t m, int64_t d, const __hip_bfloat16* SA, int64_t ldsa, 
 }
 
 // ---------------------------------------------------------------------------------------
-// Cholesky.
+// Cholesky factor and its inverse, by recursion on 2 x 2 block partitions:
+//   [A11  .  ]   L11 = chol(A11), X11 = L11^{-1}            (recursive)
+//   [A21 A22 ]   L21 = A21 X11^T,  S = A22 - L21 L21^T
+//                L22 = chol(S),    X22 = L22^{-1}            (recursive)
+//                X21 = -X22 (L21 X11)
+// Leaves are 64 x 64 blocks, factorised and inverted by one wavefront: lane i keeps row i in
+// registers and reads the pivot column through cross-lane reads, so no barrier is needed.
 // ---------------------------------------------------------------------------------------
-// Factorise one 64 x 64 diagonal block in LDS (lower), write L back (upper zeroed) and the
-// inverse of L to dinv (64 x 64, ld 64).  flag set on a non-positive / NaN pivot.
-__global__ __launch_bounds__(256) void potf2_inv_kernel(double* __restrict__ Gk, int64_t ld,
-                                                        double* __restrict__ dinv, int* __restrict__ flag) {
-  __shared__ double a[64][65];
-  __shared__ double x[64][65];
-  const int tid = threadIdx.x;
-  for (int idx = tid; idx < 64 * 64; idx += 256) {
-    const int i = idx >> 6, j = idx & 63;
-    a[i][j] = (j <= i) ? Gk[(int64_t)i * ld + j] : 0.0;
+// Leaf: one wavefront, lane i owns row i.  Left-looking (Crout) Cholesky: at step j every
+// lane forms s_i = A[i][j] - sum_{k<j} L[i][k] L[j][k] with row j of L read from LDS (a
+// broadcast read); lane j takes the square root, the lanes below divide by it.  Then the
+// inverse X = L^{-1} column-parallel: lane j owns column j and runs the forward substitution
+// x_i = (delta_ij - sum_{k<i} L[i][k] x_k) / L[i][i] with L[i][k] again a broadcast read.
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+// sum_{k<len} a[k] * row[k] with four independent partial sums and 16-byte LDS reads (row is
+// 16-byte aligned); len is a compile-time constant after unrolling.
+template <int LEN>
+__device__ __forceinline__ double dot_lds(const double (&a)[64], const double* row) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+  for (int k = 0; k + 3 < LEN; k += 4) {
+    const d2 u = *reinterpret_cast<const d2*>(row + k);
+    const d2 v = *reinterpret_cast<const d2*>(row + k + 2);
+    s0 = fma(a[k], u[0], s0);
+    s1 = fma(a[k + 1], u[1], s1);
+    s2 = fma(a[k + 2], v[0], s2);
+    s3 = fma(a[k + 3], v[1], s3);
   }
-  __syncthreads();
-  for (int j = 0; j < 64; ++j) {
-    if (tid == 0) {
-      double piv = a[j][j];
+#pragma unroll
+  for (int k = LEN & ~3; k < LEN; ++k) s0 = fma(a[k], row[k], s0);
+  return (s0 + s1) + (s2 + s3);
+}
+
+template <int J>
+struct LeafStep {
+  // Cholesky column J (left-looking) then the next column.
+  __device__ __forceinline__ static void chol(double (&r)[64], double (*Ls)[66], double* rdiag, int lane, bool& bad) {
+    const double sacc = r[J] - dot_lds<J>(r, Ls[J]);
+    if (lane == J) {
+      double piv = sacc;
       if (!(piv > 0.0)) {
-        atomicOr(flag, 1);
+        bad = true;
         piv = 1.0;
       }
-      a[j][j] = sqrt(piv);
+      Ls[J][J] = sqrt(piv);
     }
     __syncthreads();
-    const double ljj = a[j][j];
-    for (int i = j + 1 + tid; i < 64; i += 256) a[i][j] /= ljj;
+    const double ljj = Ls[J][J];
+    r[J] = (lane == J) ? ljj : sacc / ljj;
+    if (lane > J) Ls[lane][J] = r[J];
+    if (lane == J) rdiag[J] = 1.0 / ljj;
     __syncthreads();
-    const int w = 63 - j;
-    for (int idx = tid; idx < w * w; idx += 256) {
-      const int ii = j + 1 + idx / w, kk = j + 1 + idx % w;
-      if (kk <= ii) a[ii][kk] -= a[ii][j] * a[kk][j];
-    }
-    __syncthreads();
+    LeafStep<J + 1>::chol(r, Ls, rdiag, lane, bad);
   }
-  for (int idx = tid; idx < 64 * 64; idx += 256) {
-    const int i = idx >> 6, j = idx & 63;
-    Gk[(int64_t)i * ld + j] = (j <= i) ? a[i][j] : 0.0;
+  // Row J of the column-parallel forward substitution for X = L^{-1}.
+  __device__ __forceinline__ static void inv(double (&x)[64], double (*Ls)[66], const double* rdiag, int lane) {
+    const double sacc = ((J == lane) ? 1.0 : 0.0) - dot_lds<J>(x, Ls[J]);
+    x[J] = sacc * rdiag[J];
+    LeafStep<J + 1>::inv(x, Ls, rdiag, lane);
   }
-  // inverse of the lower-triangular block, row by row: X[i][j] = -(sum_{k=j}^{i-1} L[i][k] X[k][j]) / L[i][i]
-  for (int idx = tid; idx < 64 * 64; idx += 256) x[idx >> 6][idx & 63] = 0.0;
-  __syncthreads();
-  for (int i = 0; i < 64; ++i) {
-    if (tid < 64) {
-      const int j = tid;
-      double v;
-      if (j == i) {
-        v = 1.0 / a[i][i];
-      } else if (j < i) {
-        double s = 0.0;
-        for (int k = j; k < i; ++k) s += a[i][k] * x[k][j];
-        v = -s / a[i][i];
-      } else {
-        v = 0.0;
-      }
-      x[i][j] = v;
-    }
-    __syncthreads();
-  }
-  for (int idx = tid; idx < 64 * 64; idx += 256) dinv[idx] = x[idx >> 6][idx & 63];
+};
+template <>
+struct LeafStep<64> {
+  __device__ __forceinline__ static void chol(double (&)[64], double (*)[66], double*, int, bool&) {}
+  __device__ __forceinline__ static void inv(double (&)[64], double (*)[66], const double*, int) {}
+};
+
+// Leaf: one wavefront, lane i owns row i.  Left-looking (Crout) Cholesky: at step j every
+// lane forms s_i = A[i][j] - sum_{k<j} L[i][k] L[j][k] with row j of L read from LDS (a
+// broadcast read); lane j takes the square root, the lanes below divide by it.  Then the
+// inverse X = L^{-1} column-parallel: lane j owns column j and runs the forward substitution
+// x_i = (delta_ij - sum_{k<i} L[i][k] x_k) / L[i][i] with L[i][k] again a broadcast read.
+__global__ __launch_bounds__(64) void chol_inv_leaf_kernel(double* __restrict__ G, int64_t ld, double* __restrict__ X,
+                                                           int64_t ldx, int* __restrict__ flag) {
+  __shared__ __attribute__((aligned(16))) double Ls[64][66];
+  __shared__ double rdiag[64];
+  const int lane = threadIdx.x;
+  double r[64];
+#pragma unroll
+  for (int j = 0; j < 64; ++j) r[j] = (j <= lane) ? G[(int64_t)lane * ld + j] : 0.0;
+  bool bad = false;
+  LeafStep<0>::chol(r, Ls, rdiag, lane, bad);
+#pragma unroll
+  for (int j = 0; j < 64; ++j) G[(int64_t)lane * ld + j] = (j <= lane) ? r[j] : 0.0;
+  double x[64];
+  LeafStep<0>::inv(x, Ls, rdiag, lane);
+#pragma unroll
+  for (int i = 0; i < 64; ++i) X[(int64_t)i * ldx + lane] = (i >= lane) ? x[i] : 0.0;
+  if (bad && lane == 0) atomicOr(flag, 1);
 }
 
-void cholesky_inplace(double* G, int64_t np, double* dinv, int* flag, hipStream_t s) {
-  const int64_t nb = np / 64;
-  for (int64_t kb = 0; kb < nb; ++kb) {
-    const int64_t k0 = kb * 64;
-    double* Gk = G + k0 * np + k0;
-    hipLaunchKernelGGL(potf2_inv_kernel, dim3(1), dim3(256), 0, s, Gk, np, dinv + kb * 4096, flag);
-    AES_LAUNCH_CHECK();
-    const int64_t rb = np - k0 - 64;
-    if (rb > 0) {
-      double* L21 = G + (k0 + 64) * np + k0;
-      // L21 = A21 inv(L11)^T (in place: one column tile per workgroup row block)
-      gemm_f64(false, true, rb, 64, 64, 1.0, L21, np, 0, dinv + kb * 4096, 64, 0, 0.0, L21, np, 0, 1, 0, s);
-      // A22 -= L21 L21^T (lower)
-      gemm_f64(false, true, rb, rb, 64, -1.0, L21, np, 0, L21, np, 0, 1.0, G + (k0 + 64) * np + (k0 + 64), np, 0, 1, 1,
-               s);
-    }
-  }
-}
-
-__global__ void place_diag_inv_kernel(int64_t np, const double* __restrict__ dinv, double* __restrict__ Linv) {
+__global__ void copy_block_kernel(int64_t rows, int64_t cols, const double* __restrict__ src, int64_t lds,
+                                  double* __restrict__ dst, int64_t ldd) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= np * np) return;
-  const int64_t i = e / np, j = e % np;
-  const int64_t bi = i >> 6, bj = j >> 6;
-  Linv[e] = (bi == bj) ? dinv[bi * 4096 + (i & 63) * 64 + (j & 63)] : 0.0;
+  if (e >= rows * cols) return;
+  const int64_t i = e / cols, j = e % cols;
+  dst[i * ldd + j] = src[i * lds + j];
 }
 
-// Linv = L^{-1} by block diagonals: X_ij = -inv(L_ii) * sum_{k=j}^{i-1} L_ik X_kj, i = j + s.
-void trtri_lower(const double* L, int64_t np, const double* dinv, double* Linv, double* tmp, hipStream_t s) {
-  const int64_t nb = np / 64;
-  hipLaunchKernelGGL(place_diag_inv_kernel, dim3((unsigned)ceil_div(np * np, 256)), dim3(256), 0, s, np, dinv, Linv);
-  AES_LAUNCH_CHECK();
-  const int64_t dstride = 64 * np + 64;
-  for (int64_t sd = 1; sd < nb; ++sd) {
-    const int batch = (int)(nb - sd);
-    // T_j = L[(j+s) blk, j..j+s-1 blks] * X[j..j+s-1 blks, j blk]    (64 x 64, K = 64 s)
-    gemm_f64(false, false, 64, 64, 64 * sd, 1.0, L + sd * 64 * np, np, dstride, Linv, np, dstride, 0.0, tmp, 64, 4096,
-             batch, 0, s);
-    // X_(j+s),j = -inv(L_(j+s)(j+s)) T_j
-    gemm_f64(false, false, 64, 64, 64, -1.0, dinv + sd * 4096, 64, 4096, tmp, 64, 4096, 0.0, Linv + sd * 64 * np, np,
-             dstride, batch, 0, s);
+static void cholinv_rec(double* G, double* X, int64_t ld, int64_t o, int64_t h, double* tmp, int* flag,
+                        hipStream_t s) {
+  if (h == 64) {
+    hipLaunchKernelGGL(chol_inv_leaf_kernel, dim3(1), dim3(64), 0, s, G + o * ld + o, ld, X + o * ld + o, ld, flag);
+    AES_LAUNCH_CHECK();
+    return;
   }
+  const int64_t nb = h / 64;
+  const int64_t h1 = 64 * ((nb + 1) / 2), h2 = h - h1;
+  cholinv_rec(G, X, ld, o, h1, tmp, flag, s);
+  double* A21 = G + (o + h1) * ld + o;
+  double* A22 = G + (o + h1) * ld + (o + h1);
+  const double* X11 = X + o * ld + o;
+  double* T1 = tmp;             // h2 x h1: L21
+  double* T2 = tmp + h2 * h1;   // h2 x h1: L21 X11
+  // L21 = A21 X11^T
+  gemm_f64(false, true, h2, h1, h1, 1.0, A21, ld, 0, X11, ld, 0, 0.0, T1, h1, 0, 1, 0, s);
+  hipLaunchKernelGGL(copy_block_kernel, dim3((unsigned)ceil_div(h2 * h1, 256)), dim3(256), 0, s, h2, h1, T1, h1, A21,
+                     ld);
+  AES_LAUNCH_CHECK();
+  // S = A22 - L21 L21^T (lower)
+  gemm_f64(false, true, h2, h2, h1, -1.0, T1, h1, 0, T1, h1, 0, 1.0, A22, ld, 0, 1, 1, s);
+  // T2 = L21 X11
+  gemm_f64(false, false, h2, h1, h1, 1.0, T1, h1, 0, X11, ld, 0, 0.0, T2, h1, 0, 1, 0, s);
+  cholinv_rec(G, X, ld, o + h1, h2, tmp + 2 * h2 * h1, flag, s);
+  // X21 = -X22 T2
+  gemm_f64(false, false, h2, h1, h2, -1.0, X + (o + h1) * ld + (o + h1), ld, 0, T2, h1, 0, 0.0, X + (o + h1) * ld + o,
+           ld, 0, 1, 0, s);
+}
+
+size_t cholinv_tmp_size(int64_t np) { return (size_t)np * np; }
+
+void cholinv(double* G, int64_t np, double* Linv, double* tmp, int* flag, hipStream_t s) {
+  launch_fill(Linv, np * np, 0.0, s);
+  cholinv_rec(G, Linv, np, 0, np, tmp, flag, s);
 }
 
 // ---------------------------------------------------------------------------------------

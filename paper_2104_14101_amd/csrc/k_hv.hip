@@ -27,19 +27,21 @@ struct VecT<float, 4> {
   using type = float __attribute__((ext_vector_type(4)));
 };
 
+// Loads VEC consecutive elements (zero beyond nvalid); they stay in the storage type TA in
+// registers and are widened to FP64 where they are used.
 template <typename TA, int VEC>
-__device__ __forceinline__ void load_vec(const TA* __restrict__ p, bool full, int nvalid, double (&out)[VEC]) {
+__device__ __forceinline__ void load_vec(const TA* __restrict__ p, bool full, int nvalid, TA (&out)[VEC]) {
   using VT = typename VecT<TA, VEC>::type;
   if constexpr (VEC == 1) {
-    out[0] = full ? (double)__builtin_nontemporal_load(p) : 0.0;
+    out[0] = full ? __builtin_nontemporal_load(p) : TA(0);
   } else {
     if (full) {
       VT v = __builtin_nontemporal_load(reinterpret_cast<const VT*>(p));
 #pragma unroll
-      for (int i = 0; i < VEC; ++i) out[i] = (double)v[i];
+      for (int i = 0; i < VEC; ++i) out[i] = v[i];
     } else {
 #pragma unroll
-      for (int i = 0; i < VEC; ++i) out[i] = i < nvalid ? (double)p[i] : 0.0;
+      for (int i = 0; i < VEC; ++i) out[i] = i < nvalid ? p[i] : TA(0);
     }
   }
 }
@@ -74,7 +76,7 @@ __global__ __launch_bounds__(kHvThreads, 2) void hv_fused_kernel(const TA* __res
   int buf = 0;
   const int64_t stride = (int64_t)gridDim.x * ROWS;
   for (int64_t r0 = (int64_t)blockIdx.x * ROWS; r0 < n; r0 += stride) {
-    double a[ROWS][NCH][VEC];
+    TA a[ROWS][NCH][VEC];
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
       const int64_t row = r0 + r;
@@ -94,7 +96,7 @@ __global__ __launch_bounds__(kHvThreads, 2) void hv_fused_kernel(const TA* __res
 #pragma unroll
       for (int j = 0; j < NCH; ++j)
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) acc = fma(a[r][j][e], pr[j][e], acc);
+        for (int e = 0; e < VEC; ++e) acc = fma((double)a[r][j][e], pr[j][e], acc);
       dot[r] = acc;
     }
     wave_transpose_sum<ROWS>(dot, lane);
@@ -111,7 +113,7 @@ __global__ __launch_bounds__(kHvThreads, 2) void hv_fused_kernel(const TA* __res
 #pragma unroll
       for (int j = 0; j < NCH; ++j)
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) qa[j][e] = fma(z[r], a[r][j][e], qa[j][e]);
+        for (int e = 0; e < VEC; ++e) qa[j][e] = fma(z[r], (double)a[r][j][e], qa[j][e]);
     }
   }
   double* out = part + (int64_t)blockIdx.x * d;
@@ -148,13 +150,13 @@ void launch_hv_fused<double>(const double* A, int64_t n, int64_t d, int64_t lda,
     if (d <= 512) return hv_launch_cfg<double, 2, 1, 16>(A, n, d, lda, v, part, spart, nwg, s);
     if (d <= 1024) return hv_launch_cfg<double, 2, 2, 8>(A, n, d, lda, v, part, spart, nwg, s);
     if (d <= 2048) return hv_launch_cfg<double, 2, 4, 8>(A, n, d, lda, v, part, spart, nwg, s);
-    if (d <= 4096) return hv_launch_cfg<double, 2, 8, 4>(A, n, d, lda, v, part, spart, nwg, s);
-    if (d <= 8192) return hv_launch_cfg<double, 2, 16, 2>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 4096) return hv_launch_cfg<double, 2, 8, 2>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 8192) return hv_launch_cfg<double, 2, 16, 1>(A, n, d, lda, v, part, spart, nwg, s);
   } else {
     if (d <= 256) return hv_launch_cfg<double, 1, 1, 16>(A, n, d, lda, v, part, spart, nwg, s);
     if (d <= 1024) return hv_launch_cfg<double, 1, 4, 8>(A, n, d, lda, v, part, spart, nwg, s);
     if (d <= 2048) return hv_launch_cfg<double, 1, 8, 4>(A, n, d, lda, v, part, spart, nwg, s);
-    if (d <= 4096) return hv_launch_cfg<double, 1, 16, 2>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 4096) return hv_launch_cfg<double, 1, 16, 1>(A, n, d, lda, v, part, spart, nwg, s);
     if (d <= 8192) return hv_launch_cfg<double, 1, 32, 1>(A, n, d, lda, v, part, spart, nwg, s);
   }
   throw std::invalid_argument("hv_fused: d > 8192 is not supported");
@@ -165,15 +167,15 @@ void launch_hv_fused<float>(const float* A, int64_t n, int64_t d, int64_t lda, c
                             double* spart, int nwg, hipStream_t s) {
   const bool v4 = (d % 4 == 0) && (lda % 4 == 0) && ((uintptr_t)A % 16 == 0);
   if (v4) {
-    if (d <= 1024) return hv_launch_cfg<float, 4, 1, 16>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 1024) return hv_launch_cfg<float, 4, 1, 8>(A, n, d, lda, v, part, spart, nwg, s);
     if (d <= 2048) return hv_launch_cfg<float, 4, 2, 8>(A, n, d, lda, v, part, spart, nwg, s);
-    if (d <= 4096) return hv_launch_cfg<float, 4, 4, 8>(A, n, d, lda, v, part, spart, nwg, s);
-    if (d <= 8192) return hv_launch_cfg<float, 4, 8, 4>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 4096) return hv_launch_cfg<float, 4, 4, 2>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 8192) return hv_launch_cfg<float, 4, 8, 1>(A, n, d, lda, v, part, spart, nwg, s);
   } else {
     if (d <= 256) return hv_launch_cfg<float, 1, 1, 16>(A, n, d, lda, v, part, spart, nwg, s);
     if (d <= 1024) return hv_launch_cfg<float, 1, 4, 8>(A, n, d, lda, v, part, spart, nwg, s);
     if (d <= 2048) return hv_launch_cfg<float, 1, 8, 4>(A, n, d, lda, v, part, spart, nwg, s);
-    if (d <= 4096) return hv_launch_cfg<float, 1, 16, 2>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 4096) return hv_launch_cfg<float, 1, 16, 1>(A, n, d, lda, v, part, spart, nwg, s);
     if (d <= 8192) return hv_launch_cfg<float, 1, 32, 1>(A, n, d, lda, v, part, spart, nwg, s);
   }
   throw std::invalid_argument("hv_fused: d > 8192 is not supported");

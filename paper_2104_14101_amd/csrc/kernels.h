@@ -110,11 +110,11 @@ void gram_nt(int64_t m, int64_t d, const double* SA, int64_t ldsa, double nu2, c
              double* scaled, double* W, int64_t mp, hipStream_t s);
 void gram_nt_bf16(int64_t m, int64_t d, const __hip_bfloat16* SA, int64_t ldsa, double nu2,
                   const double* invlam, double* sa64, double* scaled, double* W, int64_t mp, hipStream_t s);
-// In-place blocked Cholesky of the lower triangle of G (np x np, np % 64 == 0); writes the
-// inverses of the 64 x 64 diagonal blocks of L to dinv (np/64 blocks of 64*64) and sets
-// *flag != 0 on a non-positive or NaN pivot.  Then Linv = L^{-1} (np x np) and LinvT.
-void cholesky_inplace(double* G, int64_t np, double* dinv, int* flag, hipStream_t s);
-void trtri_lower(const double* L, int64_t np, const double* dinv, double* Linv, double* tmp, hipStream_t s);
+// Lower Cholesky factor of G (np x np, np % 64 == 0, lower triangle read), written in place
+// (upper triangle zeroed), and Linv = L^{-1}; *flag != 0 on a non-positive or NaN pivot.
+// tmp: cholinv_tmp_size(np) doubles.
+size_t cholinv_tmp_size(int64_t np);
+void cholinv(double* G, int64_t np, double* Linv, double* tmp, int* flag, hipStream_t s);
 
 // ---- adjoint (k_vec.hip) ------------------------------------------------------------------
 // dA[i, j] = -(z1[i] * y2[j] + z2[i] * y1[j]) with z1 = A y1, z2 = A y2 computed in-kernel.
