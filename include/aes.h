@@ -51,10 +51,12 @@ typedef enum {
 typedef enum { AES_PCG = 0, AES_IHS = 1 } aes_method;
 typedef enum { AES_SRHT = 0, AES_GAUSS = 1 } aes_sketch_kind;
 typedef enum {
-  AES_FP64 = 0,   /* every step in FP64 */
-  AES_MIXED = 1   /* BF16 sketch + BF16 MFMA Gram (FP32 accumulation), FP32-stored A for
-                     the PCG matvecs (FP64 accumulation), FP64 Cholesky, FP64 scalars, FP64
-                     residual refinement */
+  AES_FP64 = 0,       /* every step in FP64 */
+  AES_MIXED = 1,      /* BF16 SRHT + BF16 MFMA Gram (FP32 accumulation), FP32-stored A for the
+                         PCG matvecs, FP64 Cholesky, FP64 scalars and vectors, FP64 residual
+                         refinement */
+  AES_MIXED_FP32 = 2  /* as AES_MIXED with an FP32 SRHT and an FP64 MFMA Gram of it (for small
+                         nu, where a BF16 sketch or an FP32-accumulated Gram is too coarse) */
 } aes_precision;
 typedef enum {
   AES_STOP_XREL = 0,       /* (1+sqrt rho) D_t <= nu^2 min(lambda) tol^2 ||x_t||^2 (D = r^T H_S^-1 r) */
@@ -156,7 +158,9 @@ typedef struct {
 /*
  * aes_solve_batched -- solves nprob independent problems (each with c right-hand sides that
  * share the problem's sketch, Sec. 5 "matrix variables").  Problem p draws its sketches from
- * Philox stream id p.  probs and infos are host arrays of length nprob.
+ * Philox stream id p.  probs and infos are host arrays of length nprob.  The problems run
+ * concurrently on up to 8 internal streams (default priority) that wait for `stream`; the call
+ * returns when all are done.
  */
 aes_status aes_solve_batched(aes_handle h, void* stream, int64_t nprob, const aes_problem* probs,
                              double tol, const aes_options* opt, aes_info* infos);
@@ -197,6 +201,14 @@ void aes_ctx_free(aes_ctx ctx);
  *   p, q: device length d.  pHp: device, 1 double.  lambda: device or NULL. */
 aes_status aes_hv(aes_handle h, void* stream, int64_t n, int64_t d, const double* A, int64_t lda,
                   double nu, const double* lambda, const double* p, double* q, double* pHp);
+
+/* Q = A^T (A P) + nu^2 Lambda P for c right-hand sides (P, Q device d x c, ld = c, c a power of
+ * two <= 32) -- the per-step product of the matrix-variable solves (Sec. 5).  precision
+ * AES_FP64: FP64 MFMA; AES_MIXED / AES_MIXED_FP32: A rounded to FP32 and FP32 MFMA products
+ * with FP32 accumulation within row blocks, FP64 sums across them. */
+aes_status aes_hv_multi(aes_handle h, void* stream, int64_t n, int64_t d, int64_t c, const double* A,
+                        int64_t lda, double nu, const double* lambda, const double* P, double* Q,
+                        int precision);
 
 /* SA for sketch index k of size m (Sec. 2.1).  kind AES_SRHT: SA = (1/sqrt m) R H E A_pad,
  * H the unnormalised Sylvester Walsh-Hadamard matrix of order n' = 2^ceil(log2 n), E the

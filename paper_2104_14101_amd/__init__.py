@@ -18,7 +18,7 @@ import torch
 
 from . import _binding as B
 
-__all__ = ["solve", "solve_batched", "hv", "sketch", "factor", "precond_apply", "SketchSolve", "AesError"]
+__all__ = ["solve", "solve_batched", "hv", "hv_multi", "sketch", "factor", "precond_apply", "SketchSolve", "AesError"]
 
 AesError = B.AesError
 _handles = {}
@@ -186,6 +186,21 @@ def hv(A, p, nu, lam=None):
     h = _handle(A.device)
     _check(h, _lib().aes_hv(h, _stream(A.device), n, d, _ptr(A), lda, float(nu), _ptr(lam), _ptr(p), _ptr(q), _ptr(php)))
     return q, php
+
+
+def hv_multi(A, P, nu, lam=None, precision="fp64"):
+    """Q = A^T (A P) + nu^2 Lambda P for P of shape (d, c), c a power of two <= 32."""
+    _req(A, "A", (2,))
+    A, lda = _rowmajor(A)
+    n, d = A.shape
+    P = _req(P, "P", (2,)).contiguous()
+    c = P.shape[1]
+    lam = lam.contiguous() if lam is not None else None
+    Q = torch.empty_like(P)
+    h = _handle(A.device)
+    _check(h, _lib().aes_hv_multi(h, _stream(A.device), n, d, c, _ptr(A), lda, float(nu), _ptr(lam), _ptr(P), _ptr(Q),
+                                  B.PRECISIONS[precision]))
+    return Q
 
 
 def sketch(A, m, kind="srht", seed=0, k=0, problem=0):

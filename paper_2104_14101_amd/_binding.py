@@ -16,7 +16,7 @@ STATUS_NAMES = {0: "ok", 1: "invalid_arg", 2: "not_spd", 3: "nonfinite", 4: "max
                 7: "not_implemented"}
 METHODS = {"pcg": 0, "ihs": 1}
 SKETCHES = {"srht": 0, "gauss": 1}
-PRECISIONS = {"fp64": 0, "mixed": 1}
+PRECISIONS = {"fp64": 0, "mixed": 1, "mixed_fp32": 2}
 STOPS = {"xrel": 0, "dtilde_rel": 1, "fixed": 2, "remark": 3}
 
 
@@ -67,6 +67,8 @@ _PROTOS = {
     "aes_ctx_free": (None, [c_void_p]),
     "aes_hv": (c_int, [c_void_p, c_void_p, c_int64, c_int64, c_void_p, c_int64, c_double, c_void_p, c_void_p, c_void_p,
                        c_void_p]),
+    "aes_hv_multi": (c_int, [c_void_p, c_void_p, c_int64, c_int64, c_int64, c_void_p, c_int64, c_double, c_void_p,
+                             c_void_p, c_void_p, c_int]),
     "aes_sketch": (c_int, [c_void_p, c_void_p, c_int, c_int64, c_int64, c_void_p, c_int64, c_int64, c_uint64, c_int32,
                            c_int64, c_void_p]),
     "aes_factor": (c_int, [c_void_p, c_void_p, c_int64, c_int64, c_void_p, c_double, c_void_p, c_void_p, c_void_p]),

@@ -5,12 +5,15 @@
 // Control: every device step is enqueued on the caller's stream; the host reads back one
 // small block of flags per attempted step (accepted / rejected / stopped), because the
 // accept-or-resketch decision of the algorithms is data dependent.
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <functional>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -40,8 +43,11 @@ struct aes_handle_s {
     return events[i];
   }
 
+  std::mutex mu;  // guards bufs / events / err when batched workers share the handle
+
   template <typename T>
   T* buf(const std::string& name, size_t count) {
+    std::lock_guard<std::mutex> lock(mu);
     const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
     auto it = bufs.find(name);
     if (it != bufs.end() && it->second.second >= bytes) return static_cast<T*>(it->second.first);
@@ -58,6 +64,10 @@ struct aes_handle_s {
     }
     bufs[name] = {p, alloc};
     return static_cast<T*>(p);
+  }
+  void set_err(const std::string& e) {
+    std::lock_guard<std::mutex> lock(mu);
+    err = e;
   }
   void release() {
     for (auto& kv : bufs) (void)hipFree(kv.second.first);
@@ -118,7 +128,7 @@ void validate(const ProblemDesc& P, double tol, const aes_options& o) {
   if (o.stop != AES_STOP_FIXED && !(tol > 0)) bad("tol must be > 0");
   if (o.method != AES_PCG && o.method != AES_IHS) bad("unknown method");
   if (o.sketch != AES_SRHT && o.sketch != AES_GAUSS) bad("unknown sketch");
-  if (o.precision != AES_FP64 && o.precision != AES_MIXED) bad("unknown precision");
+  if (o.precision < AES_FP64 || o.precision > AES_MIXED_FP32) bad("unknown precision");
   if (o.stop < 0 || o.stop > 3) bad("unknown stop rule");
   if (o.max_iter < 0) bad("max_iter must be >= 0");
 }
@@ -143,8 +153,9 @@ class Solver {
     npad_ = next_pow2(n_);
     mcap_ = o.m_max > 0 ? std::min<int64_t>(o.m_max, npad_) : npad_;
     nu2_ = P.nu * P.nu;
-    mixed_ = o.precision == AES_MIXED;
-    if (mixed_ && C_ > 1) throw StatusError(AES_ERR_NOT_IMPLEMENTED, "mixed precision supports c = 1");
+    mixed_ = o.precision == AES_MIXED || o.precision == AES_MIXED_FP32;
+    sketch32_ = o.precision == AES_MIXED_FP32;
+    pinned_ = h->pinned;
   }
 
   // Buffers in the handle pool, namespaced per solver role.
@@ -192,8 +203,17 @@ class Solver {
     AES_HIP(hipMemcpyAsync(active_, act.data(), C_ * sizeof(int), hipMemcpyHostToDevice, s_));
     if (mixed_) {
       A32_ = B<float>("A32", (size_t)n_ * d_);
-      A16_ = B<__hip_bfloat16>("A16", (size_t)n_ * d_);
-      launch_cast2(n_, d_, P_.A, P_.lda, A32_, A16_, s_);
+      if (sketch32_) {
+        launch_cast<float>(n_, d_, P_.A, P_.lda, A32_, s_);
+      } else {
+        A16_ = B<__hip_bfloat16>("A16", (size_t)n_ * d_);
+        launch_cast2(n_, d_, P_.A, P_.lda, A32_, A16_, s_);
+      }
+      if (C_ > 1) {
+        V32_ = B<float>("V32", (size_t)d_ * C_);
+        Z32_ = B<float>("Z32", (size_t)n_ * C_);
+        part32_ = B<float>("part32", (size_t)msplit_ * d_ * C_);
+      }
     }
     stop_scale_ = nu2_ * min_lambda() * tol_ * tol_;
     if (o_.stop == AES_STOP_REMARK) stop_scale_ = tol_ / (remark_m_delta(n_, d_) + 1.0);
@@ -228,6 +248,23 @@ class Solver {
         ++n_events_;
       }
       launch_hv_colsum(part_, nwg_, d_, 1, v, lam_, nu2_, sgn, bb, bsgn, out, s_);
+    } else if (use32) {
+      // FP32 storage and MFMA: Z = A V (n x C), partial Q_w = A_w^T Z_w over row blocks
+      narrow_f64(d_ * C_, v, V32_, s_);
+      gemm_f32(false, false, n_, C_, d_, 1.0, A32_, d_, 0, V32_, C_, 0, 0.0, Z32_, C_, 0, 1, 0, s_);
+      const int full = (int)(n_ / msplit_rows_);
+      if (full > 0)
+        gemm_f32(true, false, d_, C_, msplit_rows_, 1.0, A32_, d_, msplit_rows_ * d_, Z32_, C_, msplit_rows_ * C_, 0.0,
+                 part32_, C_, d_ * C_, full, 0, s_);
+      const int64_t tail = n_ - (int64_t)full * msplit_rows_;
+      int used = full;
+      if (tail > 0) {
+        gemm_f32(true, false, d_, C_, tail, 1.0, A32_ + (int64_t)full * msplit_rows_ * d_, d_, 0,
+                 Z32_ + (int64_t)full * msplit_rows_ * C_, C_, 0, 0.0, part32_ + (int64_t)full * d_ * C_, C_, 0, 1, 0,
+                 s_);
+        ++used;
+      }
+      launch_hv_colsum_f32(part32_, used, d_, C_, v, lam_, nu2_, sgn, bb, bsgn, out, s_);
     } else {
       // Z = A V (n x C); partial Q_w = A_w^T Z_w over row splits; fixed-order column sum.
       gemm_f64(false, false, n_, C_, d_, 1.0, P_.A, P_.lda, 0, v, C_, 0, 0.0, Z_, C_, 0, 1, 0, s_);
@@ -250,10 +287,13 @@ class Solver {
   // ---- sketch + factorisation of H_S (Sec. 4.1) ----------------------------------------
   void sketch_factor() {
     const double t0 = now_ms();
-    const bool bf = mixed_ && o_.sketch == AES_SRHT;
+    const bool bf = mixed_ && !sketch32_ && o_.sketch == AES_SRHT;
+    const bool f32 = mixed_ && sketch32_ && o_.sketch == AES_SRHT;
     woodbury_ = m_ < d_;
     if (bf) {
       SA16_ = B<__hip_bfloat16>("SA16", (size_t)m_ * d_);
+    } else if (f32) {
+      SA32_ = B<float>("SA32", (size_t)m_ * d_);
     } else {
       SA_ = B<double>("SA", (size_t)m_ * d_);
     }
@@ -271,6 +311,9 @@ class Solver {
         float* Y = B<float>("Y32", (size_t)npad_ * d_);
         launch_srht_apply<__hip_bfloat16, float, __hip_bfloat16>(A16_, n_, d_, d_, eps, npad_, sc.pos, m_, Y, SA16_, d_,
                                                                  s_);
+      } else if (f32) {
+        float* Y = B<float>("Y32", (size_t)npad_ * d_);
+        launch_srht_apply<float, float, float>(A32_, n_, d_, d_, eps, npad_, sc.pos, m_, Y, SA32_, d_, s_);
       } else {
         double* Y = B<double>("Y", (size_t)npad_ * d_);
         launch_srht_apply<double, double, double>(P_.A, n_, d_, P_.lda, eps, npad_, sc.pos, m_, Y, SA_, d_, s_);
@@ -280,7 +323,7 @@ class Solver {
     }
     int* flag = B<int>("chol_flag", 1);
     AES_HIP(hipMemsetAsync(flag, 0, sizeof(int), s_));
-    factor_from_sa(bf, flag);
+    factor_from_sa(bf ? 1 : (f32 ? 2 : 0), flag);
     int hflag = 0;
     AES_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s_));
     AES_HIP(hipStreamSynchronize(s_));
@@ -289,11 +332,21 @@ class Solver {
   }
 
   // Gram of the current sketch, its Cholesky factor and the inverse factor (Sec. 4.1).
-  void factor_from_sa(bool bf, int* flag) {
+  // sk: 0 FP64 sketch (SA_), 1 BF16 (SA16_), 2 FP32 (SA32_)
+  void factor_from_sa(int sk, int* flag) {
+    const bool bf = sk == 1;
     if (!woodbury_) {
       fp_ = round_up(d_, 64);
       double* G = B<double>("G", (size_t)fp_ * fp_);
-      if (bf) {
+      if (sk == 2) {
+        // FP32 sketch, FP64 Gram: an FP32-accumulated Gram carries errors ~ u32 ||SA||^2,
+        // above nu^2 Lambda once nu is small, and would not stay positive definite.
+        SA_ = B<double>("SA", (size_t)m_ * d_);
+        widen_f32(m_ * d_, SA32_, SA_, s_);
+        const int splits = gram_splits(h_->num_cu, m_, d_);
+        double* part = B<double>("gram_part", (size_t)splits * fp_ * fp_);
+        gram_tn(m_, d_, SA_, d_, nu2_, lam_, part, splits, G, fp_, s_);
+      } else if (bf) {
         const int splits = gram_splits(h_->num_cu, m_, d_);
         float* part = B<float>("gram_part32", (size_t)splits * fp_ * fp_);
         gram_tn_bf16(m_, d_, SA16_, d_, nu2_, lam_, part, splits, G, fp_, s_);
@@ -310,6 +363,10 @@ class Solver {
       if (bf) {
         SA_ = B<double>("SA", (size_t)m_ * d_);
         gram_nt_bf16(m_, d_, SA16_, d_, nu2_, invlam_, SA_, scaled, W, fp_, s_);
+      } else if (sk == 2) {
+        SA_ = B<double>("SA", (size_t)m_ * d_);
+        widen_f32(m_ * d_, SA32_, SA_, s_);
+        gram_nt(m_, d_, SA_, d_, nu2_, invlam_, scaled, W, fp_, s_);
       } else {
         gram_nt(m_, d_, SA_, d_, nu2_, invlam_, scaled, W, fp_, s_);
       }
@@ -349,9 +406,9 @@ class Solver {
   }
 
   void read_flags() {
-    AES_HIP(hipMemcpyAsync(h_->pinned, scal_ + 7 * C_, 8 * sizeof(double), hipMemcpyDeviceToHost, s_));
+    AES_HIP(hipMemcpyAsync(pinned_, scal_ + 7 * C_, 8 * sizeof(double), hipMemcpyDeviceToHost, s_));
     AES_HIP(hipStreamSynchronize(s_));
-    for (int i = 0; i < 8; ++i) fl_[i] = h_->pinned[i];
+    for (int i = 0; i < 8; ++i) fl_[i] = pinned_[i];
   }
 
   void trace(int64_t t, double lr, double thr, bool accept) {
@@ -485,16 +542,16 @@ class Solver {
       AES_HIP(hipStreamSynchronize(s_));
     } catch (const StatusError& e) {
       st = e.st;
-      h_->err = e.what();
+      h_->set_err(e.what());
     } catch (const HipError& e) {
       st = AES_ERR_HIP;
-      h_->err = e.what();
+      h_->set_err(e.what());
     } catch (const std::bad_alloc&) {
       st = AES_ERR_OOM;
-      h_->err = "device workspace allocation failed";
+      h_->set_err("device workspace allocation failed");
     } catch (const std::invalid_argument& e) {
       st = AES_ERR_INVALID_ARG;
-      h_->err = e.what();
+      h_->set_err(e.what());
     }
     double hv_ms = 0.0;
     if (o_.profile && st != AES_ERR_HIP) {
@@ -525,45 +582,47 @@ class Solver {
   // Mixed precision: outer FP64 residual refinement around inner adaptive PCG/IHS solves
   // on the FP32-stored A with the BF16 sketch; the sketch state persists across sweeps.
   aes_status run_mixed(bool x0) {
-    double* E = B<double>("E", d_ * C_);
-    double* Rr = B<double>("Rres", d_ * C_);
-    double* nrm = B<double>("nrm", 4);
+    const int64_t dc = d_ * C_;
+    double* E = B<double>("E", dc);
+    double* Rr = B<double>("Rres", dc);
+    double* nrm = B<double>("nrm", 2 * C_);
     bool first = true;
     bool x_zero = !x0;
     m_ = std::min<int64_t>(o_.m_init, mcap_);
     k_ = 0;
     const double inner = o_.inner_tol > 0 ? o_.inner_tol : 1e-6;
     const double inner_scale = nu2_ * min_lambda() * inner * inner;
+    std::vector<int> act(C_, 0);
+    for (int j = 0; j < c_; ++j) act[j] = 1;
+    std::vector<double> hn(2 * C_);
     for (int sweep = 0; sweep < std::max(1, o_.max_refine); ++sweep) {
       ++sweeps_;
       // r = b - H x in FP64 (one pass over the FP64 A)
       if (x_zero)
-        AES_HIP(hipMemcpyAsync(Rr, Bv_, d_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
+        AES_HIP(hipMemcpyAsync(Rr, Bv_, dc * sizeof(double), hipMemcpyDeviceToDevice, s_));
       else
         hv(X_, Rr, -1.0, Bv_, 1.0, false);
-      AES_HIP(hipMemsetAsync(E, 0, d_ * sizeof(double), s_));
-      // re-arm the column
-      const int one = 1;
-      AES_HIP(hipMemcpyAsync(active_, &one, sizeof(int), hipMemcpyHostToDevice, s_));
+      AES_HIP(hipMemsetAsync(E, 0, dc * sizeof(double), s_));
+      AES_HIP(hipMemcpyAsync(active_, act.data(), C_ * sizeof(int), hipMemcpyHostToDevice, s_));
       aes_status st = adaptive(Rr, E, true, true, AES_STOP_XREL, inner_scale, !first);
       first = false;
       if (st == AES_ERR_NONFINITE) return st;
-      launch_axpy_cols(d_, 1, X_, E, nullptr, s_);
+      launch_axpy_cols(d_, C_, X_, E, nullptr, s_);
       x_zero = false;
-      // ||e|| and ||x||
-      launch_norms(E, X_, nrm);
-      const double en = std::sqrt(h_->pinned[0]), xn = std::sqrt(h_->pinned[1]);
-      if (en <= 0.25 * tol_ * xn || xn == 0.0) return AES_OK;
+      // per column: stop when ||e|| <= tol ||x|| / 4
+      launch_colnorm2(d_, C_, E, X_, nrm, s_);
+      AES_HIP(hipMemcpyAsync(hn.data(), nrm, 2 * C_ * sizeof(double), hipMemcpyDeviceToHost, s_));
+      AES_HIP(hipStreamSynchronize(s_));
+      bool done = true;
+      for (int j = 0; j < c_; ++j) {
+        const double en = std::sqrt(hn[j]), xn = std::sqrt(hn[C_ + j]);
+        const bool ok = en <= 0.25 * tol_ * xn || xn == 0.0;
+        act[j] = ok ? 0 : 1;
+        done = done && ok;
+      }
+      if (done) return AES_OK;
     }
     return AES_ERR_MAX_ITER;
-  }
-
-  void launch_norms(const double* e, const double* x, double* nrm) {
-    // reuse the IHS init kernel machinery is overkill; use rowdot with a 1 x d "matrix"
-    launch_rowdot(1, d_, e, d_, 0, e, 1, nullptr, 1.0, nullptr, nullptr, 1.0, nrm, s_);
-    launch_rowdot(1, d_, x, d_, 0, x, 1, nullptr, 1.0, nullptr, nullptr, 1.0, nrm + 1, s_);
-    AES_HIP(hipMemcpyAsync(h_->pinned, nrm, 2 * sizeof(double), hipMemcpyDeviceToHost, s_));
-    AES_HIP(hipStreamSynchronize(s_));
   }
 
   // Factorise H_S for a caller-given sketch SA (m x d, ld d) and apply it to z (d x C).
@@ -583,13 +642,20 @@ class Solver {
     AES_HIP(hipMemcpyAsync(SA_, SA, (size_t)m_ * d_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
     int* flag = B<int>("chol_flag", 1);
     AES_HIP(hipMemsetAsync(flag, 0, sizeof(int), s_));
-    factor_from_sa(false, flag);
+    factor_from_sa(0, flag);
     int hflag = 0;
     AES_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s_));
     AES_HIP(hipStreamSynchronize(s_));
     if (hflag) throw StatusError(AES_ERR_NOT_SPD, "Cholesky pivot of the sketched Hessian is not positive");
     apply(z, v);
   }
+
+  // Q = H P for the caller's P (d x C) without a solve (kernel-level entry point).
+  void hv_external(const double* Pin, double* Qout, bool use32) {
+    setup_common();
+    hv(Pin, Qout, 1.0, nullptr, 0.0, use32);
+  }
+  void set_pinned(double* p) { pinned_ = p; }
 
   // accessors for the kept context
   int64_t m() const { return m_; }
@@ -636,6 +702,9 @@ class Solver {
   int64_t msplit_rows_ = 1;
   float* A32_ = nullptr;
   __hip_bfloat16* A16_ = nullptr;
+  float *V32_ = nullptr, *Z32_ = nullptr, *part32_ = nullptr, *SA32_ = nullptr;
+  bool sketch32_ = false;
+  double* pinned_ = nullptr;
   double *SA_ = nullptr, *SAT_ = nullptr, *Linv_ = nullptr, *LinvT_ = nullptr;
   __hip_bfloat16* SA16_ = nullptr;
   double stop_scale_ = 0, stop_sr_ = 1, tol2_ = 0;
@@ -774,28 +843,72 @@ aes_status aes_solve(aes_handle h, void* stream, int64_t n, int64_t d, int64_t c
 aes_status aes_solve_batched(aes_handle h, void* stream, int64_t nprob, const aes_problem* probs, double tol,
                              const aes_options* opt, aes_info* infos) {
   if (!h || nprob < 0 || (nprob > 0 && !probs)) return AES_ERR_INVALID_ARG;
+  if (nprob == 0) return AES_OK;
   aes_options o;
   if (opt)
     o = *opt;
   else
     aes_default_options(&o);
-  aes_status worst = AES_OK;
+  o.trace = nullptr;
+  o.trace_cap = 0;
+  o.profile = 0;
+  o.x0 = nullptr;
+  // validate everything first: on INVALID_ARG nothing is written
   for (int64_t p = 0; p < nprob; ++p) {
     const aes_problem& q = probs[p];
     ProblemDesc P{q.n, q.d, q.c, q.A, q.lda, q.b, q.ldb, q.nu, q.lambda, q.x, q.ldx};
-    aes_options op = o;
-    op.problem = (int32_t)p;
-    op.trace = nullptr;
-    op.trace_cap = 0;
-    aes_status st;
-    try {
-      st = solve_impl(h, stream, P, tol, &op, infos ? &infos[p] : nullptr, "s.", nullptr);
-    } catch (const StatusError& e) {
-      h->err = e.what();
-      st = e.st;
-    }
-    if (st != AES_OK && worst == AES_OK) worst = st;
+    aes_status st = guard(h, [&] { validate(P, tol, o); });
+    if (st != AES_OK) return st;
   }
+  hipEvent_t ready = nullptr;
+  aes_status st0 = guard(h, [&] {
+    set_device(h);
+    AES_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    AES_HIP(hipEventRecord(ready, (hipStream_t)stream));
+  });
+  if (st0 != AES_OK) return st0;
+  // Problems run concurrently on W workers, each with its own stream (default priority),
+  // pinned flag block and workspace namespace; every problem keeps its own adaptive control.
+  const int W = (int)std::min<int64_t>(nprob, 8);
+  std::vector<aes_status> sts((size_t)nprob, AES_OK);
+  std::atomic<int64_t> next{0};
+  auto worker = [&](int w) {
+    hipStream_t sw = nullptr;
+    double* pin = nullptr;
+    aes_status wst = guard(h, [&] {
+      set_device(h);
+      AES_HIP(hipStreamCreateWithFlags(&sw, hipStreamNonBlocking));
+      AES_HIP(hipStreamWaitEvent(sw, ready, 0));
+      AES_HIP(hipHostMalloc((void**)&pin, 64 * sizeof(double), hipHostMallocDefault));
+    });
+    for (;;) {
+      const int64_t p = next.fetch_add(1);
+      if (p >= nprob) break;
+      if (wst != AES_OK) {
+        sts[p] = wst;
+        continue;
+      }
+      const aes_problem& q = probs[p];
+      ProblemDesc P{q.n, q.d, q.c, q.A, q.lda, q.b, q.ldb, q.nu, q.lambda, q.x, q.ldx};
+      aes_options op = o;
+      op.problem = (int32_t)p;
+      Solver so(h, sw, P, op, tol, "w" + std::to_string(w) + ".");
+      so.set_pinned(pin);
+      sts[p] = so.run(infos ? &infos[p] : nullptr);
+    }
+    if (sw) {
+      (void)hipStreamSynchronize(sw);
+      (void)hipStreamDestroy(sw);
+    }
+    if (pin) (void)hipHostFree(pin);
+  };
+  std::vector<std::thread> th;
+  for (int w = 0; w < W; ++w) th.emplace_back(worker, w);
+  for (auto& t : th) t.join();
+  (void)hipEventDestroy(ready);
+  aes_status worst = AES_OK;
+  for (aes_status st : sts)
+    if (st != AES_OK && worst == AES_OK) worst = st;
   return worst;
 }
 
@@ -932,6 +1045,23 @@ aes_status aes_hv(aes_handle h, void* stream, int64_t n, int64_t d, const double
       launch_pcg_candidate(d, 1, spart, nwg, lambda, nu * nu, p, p, p, q, dummy, dummy + d, scal, act, s);
       AES_HIP(hipMemcpyAsync(pHp, scal + 5, sizeof(double), hipMemcpyDeviceToDevice, s));
     }
+  });
+}
+
+aes_status aes_hv_multi(aes_handle h, void* stream, int64_t n, int64_t d, int64_t c, const double* A, int64_t lda,
+                        double nu, const double* lambda, const double* P, double* Q, int precision) {
+  if (!h) return AES_ERR_INVALID_ARG;
+  return guard(h, [&] {
+    if (n < 1 || d < 1 || c < 1 || c > 32 || (c & (c - 1)) || lda < d || !A || !P || !Q || !(nu >= 0))
+      throw StatusError(AES_ERR_INVALID_ARG, "bad arguments (c must be a power of two <= 32)");
+    if (precision < AES_FP64 || precision > AES_MIXED_FP32) throw StatusError(AES_ERR_INVALID_ARG, "bad precision");
+    set_device(h);
+    aes_options o;
+    aes_default_options(&o);
+    o.precision = precision;
+    ProblemDesc Pd{n, d, c, A, lda, P, c, nu, lambda, Q, c};
+    Solver so(h, (hipStream_t)stream, Pd, o, 1e-10, "hm.");
+    so.hv_external(P, Q, precision != AES_FP64);
   });
 }
 

@@ -183,7 +183,8 @@ void launch_hv_fused<float>(const float* A, int64_t n, int64_t d, int64_t lda, c
 
 // out[j, c] = sgn * (sum_w part[w][j][c] + nu2 * lam[j] * v[j, c]) + bsgn * b[j, c]
 // 256 threads = 32 (j,c)-elements x 8 partial groups; groups combined in a fixed order.
-__global__ __launch_bounds__(256) void hv_colsum_kernel(const double* __restrict__ part, int nwg, int64_t total,
+template <typename TP>
+__global__ __launch_bounds__(256) void hv_colsum_kernel(const TP* __restrict__ part, int nwg, int64_t total,
                                                         int C, const double* __restrict__ v,
                                                         const double* __restrict__ lam, double nu2, double sgn,
                                                         const double* __restrict__ b, double bsgn,
@@ -193,7 +194,7 @@ __global__ __launch_bounds__(256) void hv_colsum_kernel(const double* __restrict
   const int64_t e = (int64_t)blockIdx.x * 32 + tx;
   double acc = 0.0;
   if (e < total)
-    for (int w = ty; w < nwg; w += 8) acc += part[(int64_t)w * total + e];
+    for (int w = ty; w < nwg; w += 8) acc += (double)part[(int64_t)w * total + e];
   sh[ty][tx] = acc;
   __syncthreads();
   if (ty == 0 && e < total) {
@@ -209,8 +210,48 @@ __global__ __launch_bounds__(256) void hv_colsum_kernel(const double* __restrict
 void launch_hv_colsum(const double* part, int nwg, int64_t d, int C, const double* v, const double* lam, double nu2,
                       double sgn, const double* b, double bsgn, double* out, hipStream_t s) {
   const int64_t total = d * C;
-  hipLaunchKernelGGL(hv_colsum_kernel, dim3((unsigned)ceil_div(total, 32)), dim3(256), 0, s, part, nwg, total, C, v,
-                     lam, nu2, sgn, b, bsgn, out);
+  hipLaunchKernelGGL(hv_colsum_kernel<double>, dim3((unsigned)ceil_div(total, 32)), dim3(256), 0, s, part, nwg, total, C,
+                     v, lam, nu2, sgn, b, bsgn, out);
+  AES_LAUNCH_CHECK();
+}
+
+void launch_hv_colsum_f32(const float* part, int nwg, int64_t d, int C, const double* v, const double* lam, double nu2,
+                          double sgn, const double* b, double bsgn, double* out, hipStream_t s) {
+  const int64_t total = d * C;
+  hipLaunchKernelGGL(hv_colsum_kernel<float>, dim3((unsigned)ceil_div(total, 32)), dim3(256), 0, s, part, nwg, total, C,
+                     v, lam, nu2, sgn, b, bsgn, out);
+  AES_LAUNCH_CHECK();
+}
+
+// out[c] = sum_i e[i,c]^2, out[C + c] = sum_i x[i,c]^2 (one workgroup, fixed-order tree)
+__global__ __launch_bounds__(1024) void colnorm2_kernel(int64_t d, int C, const double* __restrict__ e,
+                                                        const double* __restrict__ x, double* __restrict__ out) {
+  __shared__ double b1[1024], b2[1024];
+  const int tid = threadIdx.x, col = tid % C, tpc = 1024 / C;
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = tid / C; i < d; i += tpc) {
+    const double u = e[i * C + col], v = x[i * C + col];
+    s1 += u * u;
+    s2 += v * v;
+  }
+  b1[tid] = s1;
+  b2[tid] = s2;
+  __syncthreads();
+  for (int st = 512; st >= C; st >>= 1) {
+    if (tid < st) {
+      b1[tid] += b1[tid + st];
+      b2[tid] += b2[tid + st];
+    }
+    __syncthreads();
+  }
+  if (tid < C) {
+    out[tid] = b1[tid];
+    out[C + tid] = b2[tid];
+  }
+}
+
+void launch_colnorm2(int64_t d, int C, const double* e, const double* x, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(colnorm2_kernel, dim3(1), dim3(1024), 0, s, d, C, e, x, out);
   AES_LAUNCH_CHECK();
 }
 

@@ -283,22 +283,27 @@ __device__ __forceinline__ void wht_group(TACC* tile, int R, int g, int tid) {
 // rows selected by pos, scale), 3 single pass (A -> SA).
 // zero_bits > 0 (middle/last pass directly after the first): rows whose first-pass tile starts
 // at or beyond n are known zero and not read.
+// Loads and stores move VW consecutive columns (16 bytes of the accumulation type) per thread.
 template <typename TIN, typename TY, typename TOUT, int CW, int MODE>
 __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A, const TY* __restrict__ Ysrc,
                                                        TY* __restrict__ Ydst, TOUT* __restrict__ SA, int64_t ldsa,
                                                        int64_t n, int64_t d, int64_t lda, int64_t npad, int s, int b,
                                                        int zero_bits, const double* __restrict__ eps,
-                                                       const int32_t* __restrict__ pos, double scale) {
+                                                       const int32_t* __restrict__ pos, double scale,
+                                                       int a_aligned) {
   using TACC = typename AccOf<TY>::type;
+  constexpr int VW = 16 / sizeof(TACC);  // columns per vector access
+  constexpr int TPR = CW / VW;           // threads per row segment
   extern __shared__ unsigned char smem_raw[];
   TACC* tile = reinterpret_cast<TACC*>(smem_raw);
   const int tid = threadIdx.x;
   const int R = 1 << b;
-  const int64_t tile_id = blockIdx.x;
+  // column block fastest: concurrently resident workgroups cover whole rows of A / Y
+  const int64_t tile_id = blockIdx.y;
   const int64_t lo = tile_id & ((1ll << s) - 1);
   const int64_t hi = tile_id >> s;
   const int64_t base = (hi << (s + b)) | lo;
-  const int64_t c0 = (int64_t)blockIdx.y * CW;
+  const int64_t c0 = (int64_t)blockIdx.x * CW;
   constexpr bool FIRST = MODE == 0 || MODE == 3;
   constexpr bool LAST = MODE == 2 || MODE == 3;
 
@@ -308,24 +313,41 @@ __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A
     for (int j = tid; j < R; j += 256) found |= pos[base + ((int64_t)j << s)] >= 0;
     if (!__syncthreads_or(found)) return;  // no selected row in this tile
   }
+  const bool vec_in =
+      ((d % VW) == 0) && (!FIRST || ((lda % VW) == 0 && sizeof(TIN) == sizeof(TACC) && a_aligned));
   // load
-  for (int idx = tid; idx < R * CW; idx += 256) {
-    const int j = idx / CW, c = idx % CW;
+  for (int idx = tid; idx < R * TPR; idx += 256) {
+    const int j = idx / TPR, cv = (idx % TPR) * VW;
     const int64_t row = base + ((int64_t)j << s);
-    const int64_t col = c0 + c;
-    TACC v = 0;
-    if (FIRST) {
-      if (col < d && row < n) {
-        if constexpr (sizeof(TACC) == 8)
-          v = (TACC)((double)A[row * lda + col] * eps[row]);
-        else
-          v = cvt<float>(A[row * lda + col]) * (float)eps[row];
+    const int64_t col = c0 + cv;
+    TACC v[VW];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) v[e] = 0;
+    bool load = col < d;
+    const TACC sg = FIRST ? (TACC)(row < n ? eps[row] : 0.0) : TACC(1);
+    if (FIRST) load = load && row < n;
+    else load = load && !(zero_bits > 0 && ((row >> zero_bits) << zero_bits) >= n);
+    if (load) {
+      if (vec_in && col + VW <= d) {
+        if (FIRST) {
+          typedef TACC VT __attribute__((ext_vector_type(VW)));
+          const VT u = __builtin_nontemporal_load(reinterpret_cast<const VT*>(reinterpret_cast<const TACC*>(A) + row * lda + col));
+#pragma unroll
+          for (int e = 0; e < VW; ++e) v[e] = u[e] * sg;
+        } else {
+          typedef TACC VT __attribute__((ext_vector_type(VW)));
+          const VT u = __builtin_nontemporal_load(reinterpret_cast<const VT*>(Ysrc + row * d + col));
+#pragma unroll
+          for (int e = 0; e < VW; ++e) v[e] = u[e];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < VW; ++e)
+          if (col + e < d) v[e] = FIRST ? cvt<TACC>(A[row * lda + col + e]) * sg : (TACC)Ysrc[row * d + col + e];
       }
-    } else {
-      const bool zero_src = zero_bits > 0 && ((row >> zero_bits) << zero_bits) >= n;
-      if (col < d && !zero_src) v = (TACC)Ysrc[row * d + col];
     }
-    tile[j * CW + c] = v;
+#pragma unroll
+    for (int e = 0; e < VW; ++e) tile[j * CW + cv + e] = v[e];
   }
   __syncthreads();
   for (int g = 0; g < b; g += 3) {
@@ -336,34 +358,57 @@ __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A
     __syncthreads();
   }
   // store
-  for (int idx = tid; idx < R * CW; idx += 256) {
-    const int j = idx / CW, c = idx % CW;
+  for (int idx = tid; idx < R * TPR; idx += 256) {
+    const int j = idx / TPR, cv = (idx % TPR) * VW;
     const int64_t row = base + ((int64_t)j << s);
-    const int64_t col = c0 + c;
+    const int64_t col = c0 + cv;
     if (col >= d) continue;
-    const TACC v = tile[j * CW + c];
     if (LAST) {
       const int32_t pr = pos[row];
-      if (pr >= 0) {
-        if constexpr (sizeof(TACC) == 8)
-          SA[(int64_t)pr * ldsa + col] = (TOUT)(v * scale);
-        else
-          SA[(int64_t)pr * ldsa + col] = cvt<TOUT>((float)(v * (float)scale));
-      }
+      if (pr < 0) continue;
+#pragma unroll
+      for (int e = 0; e < VW; ++e)
+        if (col + e < d) {
+          const TACC v = tile[j * CW + cv + e];
+          if constexpr (sizeof(TACC) == 8)
+            SA[(int64_t)pr * ldsa + col + e] = (TOUT)(v * scale);
+          else
+            SA[(int64_t)pr * ldsa + col + e] = cvt<TOUT>((float)(v * (float)scale));
+        }
+    } else if ((d % VW) == 0 && col + VW <= d) {
+      typedef TACC VT __attribute__((ext_vector_type(VW)));
+      VT u;
+#pragma unroll
+      for (int e = 0; e < VW; ++e) u[e] = tile[j * CW + cv + e];
+      __builtin_nontemporal_store(u, reinterpret_cast<VT*>(Ydst + row * d + col));
     } else {
-      Ydst[row * d + col] = (TY)v;
+#pragma unroll
+      for (int e = 0; e < VW; ++e)
+        if (col + e < d) Ydst[row * d + col + e] = (TY)tile[j * CW + cv + e];
     }
   }
+}
+
+template <typename TIN, typename TY, typename TOUT, int CW, int MODE>
+static void wht_launch(dim3 grid, size_t shmem, hipStream_t st, const TIN* A, const TY* Ysrc, TY* Ydst, TOUT* SA,
+                       int64_t ldsa, int64_t n, int64_t d, int64_t lda, int64_t npad, int s, int b, int zero_bits,
+                       const double* eps, const int32_t* pos, double scale) {
+  const int a_aligned = ((uintptr_t)A % 16) == 0;
+  hipLaunchKernelGGL((wht_pass_kernel<TIN, TY, TOUT, CW, MODE>), grid, dim3(256), shmem, st, A, Ysrc, Ydst, SA, ldsa, n,
+                     d, lda, npad, s, b, zero_bits, eps, pos, scale, a_aligned);
+  AES_LAUNCH_CHECK();
 }
 
 template <typename TIN, typename TY, typename TOUT>
 void launch_srht_apply(const TIN* A, int64_t n, int64_t d, int64_t lda, const double* eps, int64_t npad,
                        const int32_t* pos, int64_t m, TY* Y, TOUT* SA, int64_t ldsa, hipStream_t st) {
   using TACC = typename AccOf<TY>::type;
-  constexpr int CW = sizeof(TACC) == 8 ? 16 : 32;  // 128-byte row segments
+  constexpr int CW = 256 / sizeof(TACC);  // 256-byte row segments
   int L = 0;
   while ((1ll << L) < npad) ++L;
-  const int passes = L == 0 ? 1 : (L + kMaxTileBits - 1) / kMaxTileBits;
+  // at most 8 index bits per pass (tile of 256 rows x 256 bytes = 64 KB of LDS)
+  constexpr int kBits = 8;
+  const int passes = L == 0 ? 1 : (L + kBits - 1) / kBits;
   const double scale = 1.0 / std::sqrt((double)m);
   const unsigned cblocks = (unsigned)ceil_div(d, CW);
   int s = 0;
@@ -373,29 +418,30 @@ void launch_srht_apply(const TIN* A, int64_t n, int64_t d, int64_t lda, const do
     const int left = passes - p;
     const int b = (remaining + left - 1) / left;
     const size_t shmem = (size_t)(1 << b) * CW * sizeof(TACC);
-    const dim3 grid((unsigned)(npad >> b), cblocks);
+    const dim3 grid(cblocks, (unsigned)(npad >> b));
     const int zero_bits = (p == 1) ? first_bits : 0;
     if (passes == 1) {
-      hipLaunchKernelGGL((wht_pass_kernel<TIN, TY, TOUT, CW, 3>), grid, dim3(256), shmem, st, A, (const TY*)nullptr,
-                         (TY*)nullptr, SA, ldsa, n, d, lda, npad, s, b, 0, eps, pos, scale);
+      wht_launch<TIN, TY, TOUT, CW, 3>(grid, shmem, st, A, (const TY*)nullptr, (TY*)nullptr, SA, ldsa, n, d, lda, npad,
+                                       s, b, 0, eps, pos, scale);
     } else if (p == 0) {
-      hipLaunchKernelGGL((wht_pass_kernel<TIN, TY, TOUT, CW, 0>), grid, dim3(256), shmem, st, A, (const TY*)nullptr, Y,
-                         SA, ldsa, n, d, lda, npad, s, b, 0, eps, pos, scale);
+      wht_launch<TIN, TY, TOUT, CW, 0>(grid, shmem, st, A, (const TY*)nullptr, Y, SA, ldsa, n, d, lda, npad, s, b, 0,
+                                       eps, pos, scale);
       first_bits = b;
     } else if (p == passes - 1) {
-      hipLaunchKernelGGL((wht_pass_kernel<TIN, TY, TOUT, CW, 2>), grid, dim3(256), shmem, st, A, (const TY*)Y,
-                         (TY*)nullptr, SA, ldsa, n, d, lda, npad, s, b, zero_bits, eps, pos, scale);
+      wht_launch<TIN, TY, TOUT, CW, 2>(grid, shmem, st, A, (const TY*)Y, (TY*)nullptr, SA, ldsa, n, d, lda, npad, s, b,
+                                       zero_bits, eps, pos, scale);
     } else {
-      hipLaunchKernelGGL((wht_pass_kernel<TIN, TY, TOUT, CW, 1>), grid, dim3(256), shmem, st, A, (const TY*)Y, Y, SA,
-                         ldsa, n, d, lda, npad, s, b, zero_bits, eps, pos, scale);
+      wht_launch<TIN, TY, TOUT, CW, 1>(grid, shmem, st, A, (const TY*)Y, Y, SA, ldsa, n, d, lda, npad, s, b, zero_bits,
+                                       eps, pos, scale);
     }
-    AES_LAUNCH_CHECK();
     s += b;
   }
 }
 
 template void launch_srht_apply<double, double, double>(const double*, int64_t, int64_t, int64_t, const double*, int64_t,
                                                         const int32_t*, int64_t, double*, double*, int64_t, hipStream_t);
+template void launch_srht_apply<float, float, float>(const float*, int64_t, int64_t, int64_t, const double*, int64_t,
+                                                     const int32_t*, int64_t, float*, float*, int64_t, hipStream_t);
 template void launch_srht_apply<__hip_bfloat16, float, __hip_bfloat16>(const __hip_bfloat16*, int64_t, int64_t, int64_t,
                                                                        const double*, int64_t, const int32_t*, int64_t,
                                                                        float*, __hip_bfloat16*, int64_t, hipStream_t);

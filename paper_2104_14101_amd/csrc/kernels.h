@@ -24,6 +24,11 @@ void launch_hv_colsum(const double* part, int nwg, int64_t d, int C, const doubl
                       const double* lam, double nu2, double sgn, const double* b, double bsgn,
                       double* out, hipStream_t s);
 
+void launch_hv_colsum_f32(const float* part, int nwg, int64_t d, int C, const double* v, const double* lam,
+                          double nu2, double sgn, const double* b, double bsgn, double* out, hipStream_t s);
+// out[c] = ||e[:, c]||^2, out[C + c] = ||x[:, c]||^2
+void launch_colnorm2(int64_t d, int C, const double* e, const double* x, double* out, hipStream_t s);
+
 // ---- vector kernels (k_vec.hip): one workgroup, C columns ------------------------------
 struct StepScalars;  // defined in k_vec.hip
 // PCG candidate: pHp_c = sum_w spart[w][c] + nu2 sum_j lam_j p_jc^2; alpha_c = D_c / pHp_c;
@@ -97,6 +102,11 @@ void launch_gauss_sketch(const double* A, int64_t n, int64_t d, int64_t lda, int
 void gemm_f64(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
               int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta, double* C,
               int64_t ldc, int64_t sC, int batch, int tri, hipStream_t s);
+void gemm_f32(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const float* A,
+              int64_t lda, int64_t sA, const float* B, int64_t ldb, int64_t sB, double beta, float* C,
+              int64_t ldc, int64_t sC, int batch, int tri, hipStream_t s);
+void widen_f32(int64_t count, const float* src, double* dst, hipStream_t s);
+void narrow_f64(int64_t count, const double* src, float* dst, hipStream_t s);
 // Gram of a sketch with split-K: G (dp x dp, ld dp) lower = SA^T SA + nu2 diag(lam) (padding
 // rows/cols beyond d get identity).  part: scratch of splits * dp * dp doubles.
 int gram_splits(int num_cu, int64_t m, int64_t d);
