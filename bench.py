@@ -13,7 +13,13 @@ Extra legs (outside the timed region of the headline value):
   * roofline of the fused H.v kernel: HIP-event time of every launch inside the timed solves;
   * mixed precision vs FP64 on the n = 262144, d = 4096 workload (sigma_j = 0.995^j,
     nu = 1e-2), both validated against the oracle reference (skip with --no-mixed);
-  * cpu_baseline: the oracle on the host cores (see cpu_baseline()).
+  * cpu_baseline: the oracle on the host cores (see cpu_baseline());
+  * --batched (or --all): 64 uneven problems x 32 right-hand sides (n = 256 U{32..512},
+    d = 256 U{1..8}, sigma_j = 0.98^j, nu log-uniform in [1e-4, 1e-1]) solved by the concurrent
+    batched driver in FP32 storage + FP64 refinement and in FP64, a stratified sample of four
+    problems validated against the oracle;
+  * --adjoint (or --all): forward + backward of the autograd Function on n = 131072, d = 1024
+    (sigma_j = j^-1/2, nu = 1e-2), gradients validated against the dense oracle.
 
 --hv-only runs just fused H.v launches and a calibration copy (for rocprofv3 counter runs).
 """
@@ -148,6 +154,9 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--hv-only", action="store_true")
+    ap.add_argument("--batched", action="store_true")
+    ap.add_argument("--adjoint", action="store_true")
+    ap.add_argument("--all", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU sharding of the solver is a design "
@@ -201,6 +210,11 @@ def main():
     if not args.no_mixed:
         out["mixed_vs_fp64"] = mixed_leg(aes, torch, synth)
 
+    if args.batched or args.all:
+        out["batched"] = batched_leg(aes, torch, synth)
+    if args.adjoint or args.all:
+        out["adjoint"] = adjoint_leg(aes, torch, synth)
+
     if not args.no_cpu_baseline:
         cb = cpu_baseline(P_np, info)
         cb["gpu_speedup"] = cb["value"] / sec
@@ -234,6 +248,81 @@ def mixed_leg(aes, torch, synth):
         res[prec]["valid"] = bool(e <= 1e-10)
     res["speedup"] = res["fp64"]["s_per_solve"] / res["mixed"]["s_per_solve"]
     return res
+
+
+def batched_leg(aes, torch, synth):
+    import numpy as np
+
+    from oracle import reference
+
+    specs = synth.batched_specs(64, seed=0)
+    probs, keep = [], []
+    for i, sp in enumerate(specs):
+        P = synth.make_problem(sp["n"], sp["d"], sp["decay"], sp["nu"], nrhs=32, seed=1000 + i, backend="torch",
+                               device="cuda")
+        probs.append(dict(A=P["A"], b=P["b"], nu=P["nu"]))
+        keep.append(P)
+    torch.cuda.synchronize()
+    res = {"problems": 64, "rhs": 32, "sum_nd": int(sum(sp["n"] * sp["d"] for sp in specs))}
+    outs = {}
+    for prec, steps in (("mixed_fp32", 2), ("fp64", 1)):
+        aes.solve_batched(probs, tol=1e-10, precision=prec, m_init=16, seed=7)  # warmup
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = aes.solve_batched(probs, tol=1e-10, precision=prec, m_init=16, seed=7)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        outs[prec] = r
+        res[prec] = {"s_per_batch": sec, "statuses_ok": sum(1 for _, i in r if i["status"] == "ok"),
+                     "max_final_m": max(i["final_m"] for _, i in r)}
+    order = sorted(range(64), key=lambda i: specs[i]["n"] * specs[i]["d"])
+    pick = sorted({order[0], order[-1], min(range(64), key=lambda i: specs[i]["nu"]), order[32]})
+    errs = {"mixed_fp32": [], "fp64": []}
+    for i in pick:
+        Pn = to_numpy(keep[i])
+        xr = reference.reference_solution(Pn["A"], Pn["b"], Pn["nu"], None, spectral=(Pn["V"], Pn["sigma"]))
+        for prec in errs:
+            errs[prec].append(float(np.max(reference.rel_error(outs[prec][i][0].cpu().numpy(), xr))))
+    for prec in errs:
+        res[prec]["validated_problems"] = pick
+        res[prec]["max_rel_err"] = max(errs[prec])
+        res[prec]["valid"] = bool(max(errs[prec]) <= 1e-10)
+    res["speedup_mixed_vs_fp64"] = res["fp64"]["s_per_batch"] / res["mixed_fp32"]["s_per_batch"]
+    return res
+
+
+def adjoint_leg(aes, torch, synth):
+    import numpy as np
+
+    from oracle import adjoint, reference
+
+    P = synth.make_workload("adjoint_n131072_d1024", seed=0, backend="torch", device="cuda", with_xt=True)
+    opts = dict(m_init=16, seed=3, tol=1e-12)
+
+    def step():
+        A = P["A"].detach().requires_grad_(True)
+        b = P["b"].detach().requires_grad_(True)
+        ln = torch.tensor(np.log(P["nu"]), dtype=torch.float64, device="cuda", requires_grad=True)
+        x = aes.SketchSolve.apply(A, b, ln, None, opts)
+        loss = 0.5 * torch.sum((x - P["xt"]) ** 2)
+        loss.backward()
+        return A, b, ln
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    A, b, ln = step()
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    Pn = to_numpy(P)
+    xs = reference.reference_solution(Pn["A"], Pn["b"], Pn["nu"], None, spectral=(Pn["V"], Pn["sigma"]))
+    _, adj, db, dA, dln = adjoint.gradients(Pn["A"], Pn["b"], Pn["nu"], xs - Pn["xt"], x=xs)
+    e = {"db": float(np.max(np.abs(b.grad.cpu().numpy() - db)) / np.max(np.abs(db))),
+         "dA": float(np.max(np.abs(A.grad.cpu().numpy() - dA)) / np.max(np.abs(dA))),
+         "dlognu": float(abs(ln.grad.item() - dln) / abs(dln))}
+    return {"workload": "adjoint_n131072_d1024", "s_forward_backward": sec, "grad_rel_err": e,
+            "valid": bool(max(e.values()) <= 1e-9)}
 
 
 if __name__ == "__main__":
