@@ -129,9 +129,12 @@ def hv_only(args):
     import synth
 
     w = synth.WORKLOADS[args.workload]
-    P = synth.make_workload(args.workload, seed=0, backend="torch", device="cuda")
-    A, lam = P["A"], P["lam"]
-    p = torch.randn(w.d, dtype=torch.float64, device="cuda")
+    # traffic does not depend on the values: a plain N(0,1) matrix of the workload's shape
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    A = torch.randn((w.n, w.d), dtype=torch.float64, device="cuda", generator=g)
+    lam = 1.0 + 9.0 * torch.rand(w.d, dtype=torch.float64, device="cuda", generator=g)
+    p = torch.randn(w.d, dtype=torch.float64, device="cuda", generator=g)
     for _ in range(args.steps):
         aes.hv(A, p, w.nu, lam)
     # calibration copy of known size: 1 GiB read + 1 GiB written
