@@ -160,6 +160,7 @@ def main():
     ap.add_argument("--batched", action="store_true")
     ap.add_argument("--adjoint", action="store_true")
     ap.add_argument("--all", action="store_true")
+    ap.add_argument("--skip-main", action="store_true", help="run only the selected extra legs (profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU sharding of the solver is a design "
@@ -173,6 +174,15 @@ def main():
 
     import paper_2104_14101_amd as aes
     import synth
+
+    if args.skip_main:
+        out = {}
+        if args.batched or args.all:
+            out["batched"] = batched_leg(aes, torch, synth)
+        if args.adjoint or args.all:
+            out["adjoint"] = adjoint_leg(aes, torch, synth)
+        print(json.dumps(out), flush=True)
+        return
 
     w = synth.WORKLOADS[args.workload]
     P = synth.make_workload(args.workload, seed=0, backend="torch", device="cuda")

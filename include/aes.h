@@ -159,8 +159,9 @@ typedef struct {
  * aes_solve_batched -- solves nprob independent problems (each with c right-hand sides that
  * share the problem's sketch, Sec. 5 "matrix variables").  Problem p draws its sketches from
  * Philox stream id p.  probs and infos are host arrays of length nprob.  The problems run
- * concurrently on up to 8 internal streams (default priority) that wait for `stream`; the call
- * returns when all are done.
+ * concurrently on up to 8 internal streams (default priority; the environment variable
+ * AES_BATCH_WORKERS sets another count, 1..64) that wait for `stream`; the call returns when
+ * all are done.
  */
 aes_status aes_solve_batched(aes_handle h, void* stream, int64_t nprob, const aes_problem* probs,
                              double tol, const aes_options* opt, aes_info* infos);

@@ -8,6 +8,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -310,13 +311,15 @@ class Solver {
       if (bf) {
         float* Y = B<float>("Y32", (size_t)npad_ * d_);
         launch_srht_apply<__hip_bfloat16, float, __hip_bfloat16>(A16_, n_, d_, d_, eps, npad_, sc.pos, m_, Y, SA16_, d_,
-                                                                 s_);
+                                                                 B<int32_t>("need", 512), s_);
       } else if (f32) {
         float* Y = B<float>("Y32", (size_t)npad_ * d_);
-        launch_srht_apply<float, float, float>(A32_, n_, d_, d_, eps, npad_, sc.pos, m_, Y, SA32_, d_, s_);
+        launch_srht_apply<float, float, float>(A32_, n_, d_, d_, eps, npad_, sc.pos, m_, Y, SA32_, d_,
+                                               B<int32_t>("need", 512), s_);
       } else {
         double* Y = B<double>("Y", (size_t)npad_ * d_);
-        launch_srht_apply<double, double, double>(P_.A, n_, d_, P_.lda, eps, npad_, sc.pos, m_, Y, SA_, d_, s_);
+        launch_srht_apply<double, double, double>(P_.A, n_, d_, P_.lda, eps, npad_, sc.pos, m_, Y, SA_, d_,
+                                                  B<int32_t>("need", 512), s_);
       }
     } else {
       launch_gauss_sketch(P_.A, n_, d_, P_.lda, m_, o_.seed, o_.problem, k_, SA_, d_, s_);
@@ -389,8 +392,20 @@ class Solver {
     double* t1 = B<double>("ap_t1", (size_t)std::max(m_, d_) * C_);
     if (!woodbury_) {
       if (C_ >= 8) {
-        gemm_f64(false, false, d_, C_, d_, 1.0, Linv_, fp_, 0, z, C_, 0, 0.0, t1, C_, 0, 1, 0, s_);
-        gemm_f64(false, false, d_, C_, d_, 1.0, LinvT_, fp_, 0, t1, C_, 0, 0.0, v, C_, 0, 1, 0, s_);
+        // split-K skinny GEMMs over the padded factor (zero rows/columns beyond d)
+        const int64_t np = fp_;
+        int S = 1;
+        while (S < 16 && np / (2 * S) >= 128 && (np / (2 * S)) % 64 == 0) S *= 2;
+        const int64_t Ks = np / S;
+        double* zp = B<double>("ap_zp", (size_t)np * C_);
+        double* tp = B<double>("ap_tp", (size_t)np * C_);
+        double* part = B<double>("ap_part", (size_t)S * np * C_);
+        if (np > d_) launch_fill(zp + d_ * C_, (np - d_) * C_, 0.0, s_);
+        AES_HIP(hipMemcpyAsync(zp, z, d_ * C_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
+        gemm_f64(false, false, np, C_, Ks, 1.0, Linv_, np, Ks, zp, C_, Ks * C_, 0.0, part, C_, np * C_, S, 0, s_);
+        launch_sum_parts(np * C_, S, np * C_, part, tp, s_);
+        gemm_f64(false, false, np, C_, Ks, 1.0, LinvT_, np, Ks, tp, C_, Ks * C_, 0.0, part, C_, np * C_, S, 0, s_);
+        launch_sum_parts(d_ * C_, S, np * C_, part, v, s_);
       } else {
         launch_rowdot(d_, d_, Linv_, fp_, 1, z, C_, nullptr, 1.0, nullptr, nullptr, 1.0, t1, s_);
         launch_rowdot(d_, d_, LinvT_, fp_, 2, t1, C_, nullptr, 1.0, nullptr, nullptr, 1.0, v, s_);
@@ -869,7 +884,12 @@ aes_status aes_solve_batched(aes_handle h, void* stream, int64_t nprob, const ae
   if (st0 != AES_OK) return st0;
   // Problems run concurrently on W workers, each with its own stream (default priority),
   // pinned flag block and workspace namespace; every problem keeps its own adaptive control.
-  const int W = (int)std::min<int64_t>(nprob, 8);
+  int max_workers = 8;
+  if (const char* env = std::getenv("AES_BATCH_WORKERS")) {
+    const int v = std::atoi(env);
+    if (v >= 1 && v <= 64) max_workers = v;
+  }
+  const int W = (int)std::min<int64_t>(nprob, max_workers);
   std::vector<aes_status> sts((size_t)nprob, AES_OK);
   std::atomic<int64_t> next{0};
   auto worker = [&](int w) {
@@ -1085,7 +1105,8 @@ aes_status aes_sketch(aes_handle h, void* stream, int kind, int64_t n, int64_t d
       sc.blk = h->buf<uint32_t>("sk.blk", 2 * select_blocks(npad));
       launch_srht_select(seed, problem, k, npad, m, sc, s);
       double* Y = h->buf<double>("sk.Y", (size_t)npad * d);
-      launch_srht_apply<double, double, double>(A, n, d, lda, eps, npad, sc.pos, m, Y, SA, d, s);
+      launch_srht_apply<double, double, double>(A, n, d, lda, eps, npad, sc.pos, m, Y, SA, d,
+                                                h->buf<int32_t>("sk.need", 512), s);
     } else if (kind == AES_GAUSS) {
       launch_gauss_sketch(A, n, d, lda, m, seed, problem, k, SA, d, s);
     } else {

@@ -183,7 +183,13 @@ static void gemm_dispatch(int64_t M, int64_t N, int64_t K, double alpha, const T
                           const T* B, int64_t ldb, int64_t sB, double beta, T* C, int64_t ldc, int64_t sC, int batch,
                           int tri, hipStream_t s) {
   const int64_t tiles128 = ceil_div(M, 128) * ceil_div(N, 128) * batch;
-  if (M >= 128 && N >= 128 && tiles128 >= 128) {
+  if (N <= 32 && M >= 128) {
+    // skinny products (multi-RHS matvecs, preconditioner applications): 128 x 32 tiles
+    constexpr int BKS = sizeof(T) == 8 ? 16 : 32;
+    dim3 grid(1u, (unsigned)ceil_div(M, 128), (unsigned)batch);
+    hipLaunchKernelGGL((gemm_kernel<T, TA, TB, 128, 32, BKS>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B,
+                       ldb, sB, beta, C, ldc, sC, tri);
+  } else if (M >= 128 && N >= 128 && tiles128 >= 128) {
     dim3 grid((unsigned)ceil_div(N, 128), (unsigned)ceil_div(M, 128), (unsigned)batch);
     hipLaunchKernelGGL((gemm_kernel<T, TA, TB, 128, 128, 16>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B,
                        ldb, sB, beta, C, ldc, sC, tri);
@@ -363,6 +369,22 @@ void gram_tn_bf16(int64_t m, int64_t d, const __hip_bfloat16* SA, int64_t ldsa, 
   AES_LAUNCH_CHECK();
   hipLaunchKernelGGL(gram_reduce_kernel<float>, dim3((unsigned)ceil_div(dp * dp, 256)), dim3(256), 0, s, part, used, d,
                      dp, nu2, lam, G);
+  AES_LAUNCH_CHECK();
+}
+
+// out[e] = sum_s part[s * stride + e] (fixed order), e < count
+__global__ void sum_parts_kernel(int64_t count, int splits, int64_t stride, const double* __restrict__ part,
+                                 double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  double v = 0.0;
+  for (int sp = 0; sp < splits; ++sp) v += part[(int64_t)sp * stride + e];
+  out[e] = v;
+}
+
+void launch_sum_parts(int64_t count, int splits, int64_t stride, const double* part, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)ceil_div(count, 256)), dim3(256), 0, s, count, splits, stride, part,
+                     out);
   AES_LAUNCH_CHECK();
 }
 

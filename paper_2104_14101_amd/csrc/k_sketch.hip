@@ -290,7 +290,7 @@ __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A
                                                        int64_t n, int64_t d, int64_t lda, int64_t npad, int s, int b,
                                                        int zero_bits, const double* __restrict__ eps,
                                                        const int32_t* __restrict__ pos, double scale,
-                                                       int a_aligned) {
+                                                       int a_aligned, const int32_t* __restrict__ need) {
   using TACC = typename AccOf<TY>::type;
   constexpr int VW = 16 / sizeof(TACC);  // columns per vector access
   constexpr int TPR = CW / VW;           // threads per row segment
@@ -312,6 +312,15 @@ __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A
     int found = 0;
     for (int j = tid; j < R; j += 256) found |= pos[base + ((int64_t)j << s)] >= 0;
     if (!__syncthreads_or(found)) return;  // no selected row in this tile
+  }
+  // First pass of a pruned two-pass transform: bit q of nmask says whether the row this thread
+  // stores at iteration q (row (tid + 256 q) / TPR of the tile) is needed by the last pass.
+  // R * TPR / 256 <= 32 iterations (R <= 512 rows, TPR <= 16 threads per row).
+  uint32_t nmask = 0xffffffffu;
+  if (MODE == 0 && need) {
+    nmask = 0;
+    for (int q = 0; q * 256 < R * TPR; ++q)
+      if (need[(tid + 256 * q) / TPR]) nmask |= 1u << q;
   }
   const bool vec_in =
       ((d % VW) == 0) && (!FIRST || ((lda % VW) == 0 && sizeof(TIN) == sizeof(TACC) && a_aligned));
@@ -358,7 +367,7 @@ __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A
     __syncthreads();
   }
   // store
-  for (int idx = tid; idx < R * TPR; idx += 256) {
+  for (int idx = tid, q = 0; idx < R * TPR; idx += 256, ++q) {
     const int j = idx / TPR, cv = (idx % TPR) * VW;
     const int64_t row = base + ((int64_t)j << s);
     const int64_t col = c0 + cv;
@@ -375,6 +384,8 @@ __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A
           else
             SA[(int64_t)pr * ldsa + col + e] = cvt<TOUT>((float)(v * (float)scale));
         }
+    } else if (MODE == 0 && !((nmask >> q) & 1u)) {
+      continue;  // first pass of a two-pass transform: no sampled row has these low index bits
     } else if ((d % VW) == 0 && col + VW <= d) {
       typedef TACC VT __attribute__((ext_vector_type(VW)));
       VT u;
@@ -390,60 +401,94 @@ __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A
 }
 
 template <typename TIN, typename TY, typename TOUT, int CW, int MODE>
-static void wht_launch(dim3 grid, size_t shmem, hipStream_t st, const TIN* A, const TY* Ysrc, TY* Ydst, TOUT* SA,
-                       int64_t ldsa, int64_t n, int64_t d, int64_t lda, int64_t npad, int s, int b, int zero_bits,
-                       const double* eps, const int32_t* pos, double scale) {
+static void wht_launch_cw(int64_t npad, size_t shmem, hipStream_t st, const TIN* A, const TY* Ysrc, TY* Ydst, TOUT* SA,
+                          int64_t ldsa, int64_t n, int64_t d, int64_t lda, int s, int b, int zero_bits,
+                          const double* eps, const int32_t* pos, double scale, const int32_t* need) {
   const int a_aligned = ((uintptr_t)A % 16) == 0;
+  const dim3 grid((unsigned)ceil_div(d, CW), (unsigned)(npad >> b));
   hipLaunchKernelGGL((wht_pass_kernel<TIN, TY, TOUT, CW, MODE>), grid, dim3(256), shmem, st, A, Ysrc, Ydst, SA, ldsa, n,
-                     d, lda, npad, s, b, zero_bits, eps, pos, scale, a_aligned);
+                     d, lda, npad, s, b, zero_bits, eps, pos, scale, a_aligned, need);
   AES_LAUNCH_CHECK();
+}
+
+// Tile of 2^b rows x CW columns within 64 KB of LDS: 256-byte row segments for b <= 8,
+// 128-byte segments for b = 9.
+template <typename TIN, typename TY, typename TOUT, int MODE>
+static void wht_launch(int64_t npad, hipStream_t st, const TIN* A, const TY* Ysrc, TY* Ydst, TOUT* SA, int64_t ldsa,
+                       int64_t n, int64_t d, int64_t lda, int s, int b, int zero_bits, const double* eps,
+                       const int32_t* pos, double scale, const int32_t* need) {
+  using TACC = typename AccOf<TY>::type;
+  constexpr int CW_WIDE = 256 / sizeof(TACC), CW_NARROW = 128 / sizeof(TACC);
+  if (b <= 8)
+    wht_launch_cw<TIN, TY, TOUT, CW_WIDE, MODE>(npad, (size_t)(1 << b) * CW_WIDE * sizeof(TACC), st, A, Ysrc, Ydst, SA,
+                                                ldsa, n, d, lda, s, b, zero_bits, eps, pos, scale, need);
+  else
+    wht_launch_cw<TIN, TY, TOUT, CW_NARROW, MODE>(npad, (size_t)(1 << b) * CW_NARROW * sizeof(TACC), st, A, Ysrc, Ydst,
+                                                  SA, ldsa, n, d, lda, s, b, zero_bits, eps, pos, scale, need);
+}
+
+// need[j] = 1 if some sampled padded row has low index bits j (j < R0).
+__global__ void need_mask_kernel(const int32_t* __restrict__ pos, int64_t npad, int R0, int32_t* __restrict__ need) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < npad && pos[i] >= 0) need[i & (R0 - 1)] = 1;
+}
+
+__global__ void zero_i32_kernel(int32_t* p, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0;
 }
 
 template <typename TIN, typename TY, typename TOUT>
 void launch_srht_apply(const TIN* A, int64_t n, int64_t d, int64_t lda, const double* eps, int64_t npad,
-                       const int32_t* pos, int64_t m, TY* Y, TOUT* SA, int64_t ldsa, hipStream_t st) {
-  using TACC = typename AccOf<TY>::type;
-  constexpr int CW = 256 / sizeof(TACC);  // 256-byte row segments
+                       const int32_t* pos, int64_t m, TY* Y, TOUT* SA, int64_t ldsa, int32_t* need, hipStream_t st) {
   int L = 0;
   while ((1ll << L) < npad) ++L;
-  // at most 8 index bits per pass (tile of 256 rows x 256 bytes = 64 KB of LDS)
-  constexpr int kBits = 8;
+  constexpr int kBits = 9;  // at most 9 index bits per pass
   const int passes = L == 0 ? 1 : (L + kBits - 1) / kBits;
   const double scale = 1.0 / std::sqrt((double)m);
-  const unsigned cblocks = (unsigned)ceil_div(d, CW);
   int s = 0;
   int first_bits = 0;
   for (int p = 0; p < passes; ++p) {
     const int remaining = L - s;
     const int left = passes - p;
     const int b = (remaining + left - 1) / left;
-    const size_t shmem = (size_t)(1 << b) * CW * sizeof(TACC);
-    const dim3 grid(cblocks, (unsigned)(npad >> b));
     const int zero_bits = (p == 1) ? first_bits : 0;
     if (passes == 1) {
-      wht_launch<TIN, TY, TOUT, CW, 3>(grid, shmem, st, A, (const TY*)nullptr, (TY*)nullptr, SA, ldsa, n, d, lda, npad,
-                                       s, b, 0, eps, pos, scale);
+      wht_launch<TIN, TY, TOUT, 3>(npad, st, A, (const TY*)nullptr, (TY*)nullptr, SA, ldsa, n, d, lda, s, b, 0, eps, pos,
+                                   scale, nullptr);
     } else if (p == 0) {
-      wht_launch<TIN, TY, TOUT, CW, 0>(grid, shmem, st, A, (const TY*)nullptr, Y, SA, ldsa, n, d, lda, npad, s, b, 0,
-                                       eps, pos, scale);
+      const int32_t* nd = nullptr;
+      if (passes == 2 && need && m <= (1ll << b) / 2) {
+        const int R0 = 1 << b;
+        hipLaunchKernelGGL(zero_i32_kernel, dim3((unsigned)ceil_div(R0, 256)), dim3(256), 0, st, need, R0);
+        AES_LAUNCH_CHECK();
+        hipLaunchKernelGGL(need_mask_kernel, dim3((unsigned)ceil_div(npad, 256)), dim3(256), 0, st, pos, npad, R0, need);
+        AES_LAUNCH_CHECK();
+        nd = need;
+      }
+      wht_launch<TIN, TY, TOUT, 0>(npad, st, A, (const TY*)nullptr, Y, SA, ldsa, n, d, lda, s, b, 0, eps, pos, scale,
+                                   nd);
       first_bits = b;
     } else if (p == passes - 1) {
-      wht_launch<TIN, TY, TOUT, CW, 2>(grid, shmem, st, A, (const TY*)Y, (TY*)nullptr, SA, ldsa, n, d, lda, npad, s, b,
-                                       zero_bits, eps, pos, scale);
+      wht_launch<TIN, TY, TOUT, 2>(npad, st, A, (const TY*)Y, (TY*)nullptr, SA, ldsa, n, d, lda, s, b, zero_bits, eps,
+                                   pos, scale, nullptr);
     } else {
-      wht_launch<TIN, TY, TOUT, CW, 1>(grid, shmem, st, A, (const TY*)Y, Y, SA, ldsa, n, d, lda, npad, s, b, zero_bits,
-                                       eps, pos, scale);
+      wht_launch<TIN, TY, TOUT, 1>(npad, st, A, (const TY*)Y, Y, SA, ldsa, n, d, lda, s, b, zero_bits, eps, pos, scale,
+                                   nullptr);
     }
     s += b;
   }
 }
 
 template void launch_srht_apply<double, double, double>(const double*, int64_t, int64_t, int64_t, const double*, int64_t,
-                                                        const int32_t*, int64_t, double*, double*, int64_t, hipStream_t);
+                                                        const int32_t*, int64_t, double*, double*, int64_t, int32_t*,
+                                                        hipStream_t);
 template void launch_srht_apply<float, float, float>(const float*, int64_t, int64_t, int64_t, const double*, int64_t,
-                                                     const int32_t*, int64_t, float*, float*, int64_t, hipStream_t);
+                                                     const int32_t*, int64_t, float*, float*, int64_t, int32_t*,
+                                                     hipStream_t);
 template void launch_srht_apply<__hip_bfloat16, float, __hip_bfloat16>(const __hip_bfloat16*, int64_t, int64_t, int64_t,
                                                                        const double*, int64_t, const int32_t*, int64_t,
-                                                                       float*, __hip_bfloat16*, int64_t, hipStream_t);
+                                                                       float*, __hip_bfloat16*, int64_t, int32_t*,
+                                                                       hipStream_t);
 
 }  // namespace aes

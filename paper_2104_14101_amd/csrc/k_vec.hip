@@ -46,6 +46,7 @@ __global__ __launch_bounds__(kVT) void pcg_candidate_kernel(int64_t d, int C, co
   const int tid = threadIdx.x, col = tid % C, tpc = kVT / C;
   double loc = 0.0;
   if (spart) {
+#pragma unroll 4
     for (int64_t i = tid / C; i < d; i += tpc) {
       const double pv = p[i * C + col];
       loc += (lam ? lam[i] : 1.0) * pv * pv;
@@ -53,6 +54,7 @@ __global__ __launch_bounds__(kVT) void pcg_candidate_kernel(int64_t d, int C, co
     loc *= nu2;
     for (int w = tid / C; w < nwg; w += tpc) loc += spart[(int64_t)w * C + col];
   } else {
+#pragma unroll 4
     for (int64_t i = tid / C; i < d; i += tpc) loc += p[i * C + col] * q[i * C + col];
   }
   col_reduce(buf, loc, C);
@@ -66,6 +68,7 @@ __global__ __launch_bounds__(kVT) void pcg_candidate_kernel(int64_t d, int C, co
   __syncthreads();
   const double a = alpha_s[col];
   if (active[col])
+#pragma unroll 4
     for (int64_t i = tid / C; i < d; i += tpc) {
       const int64_t e = i * C + col;
       xp[e] = x[e] + a * p[e];
@@ -113,6 +116,7 @@ __global__ __launch_bounds__(kVT) void finish_kernel(int64_t d, int C, double* _
   const bool act = active[col] != 0;
   double l1 = 0.0, l2 = 0.0, l3 = 0.0;
   if (act)
+#pragma unroll 4
     for (int64_t i = tid / C; i < d; i += tpc) {
       const int64_t e = i * C + col;
       l1 += rp[e] * rtp[e];
@@ -162,6 +166,7 @@ __global__ __launch_bounds__(kVT) void finish_kernel(int64_t d, int C, double* _
   }
   if (act) {
     const double beta = IHS ? 0.0 : dp_s[col] / scal[col];
+#pragma unroll 4
     for (int64_t i = tid / C; i < d; i += tpc) {
       const int64_t e = i * C + col;
       x[e] = xp[e];

@@ -89,10 +89,11 @@ size_t select_blocks(int64_t npad);
 void launch_srht_select(uint64_t seed, int32_t problem, int64_t k, int64_t npad, int64_t m,
                         const SelectScratch& sc, hipStream_t s);
 void launch_signs(uint64_t seed, int32_t problem, int64_t k, int64_t n, double* eps, hipStream_t s);
-// FWHT-based SRHT: SA (m x d, ld d) from A (n x d, lda); Y scratch npad x d of type TY.
+// FWHT-based SRHT: SA (m x d, ld d) from A (n x d, lda); Y scratch npad x d of type TY;
+// need: scratch of 512 ints (or NULL) for the row pruning of a two-pass transform.
 template <typename TIN, typename TY, typename TOUT>
 void launch_srht_apply(const TIN* A, int64_t n, int64_t d, int64_t lda, const double* eps, int64_t npad,
-                       const int32_t* pos, int64_t m, TY* Y, TOUT* SA, int64_t ldsa, hipStream_t s);
+                       const int32_t* pos, int64_t m, TY* Y, TOUT* SA, int64_t ldsa, int32_t* need, hipStream_t s);
 void launch_gauss_sketch(const double* A, int64_t n, int64_t d, int64_t lda, int64_t m, uint64_t seed,
                          int32_t problem, int64_t k, double* SA, int64_t ldsa, hipStream_t s);
 
@@ -106,6 +107,8 @@ void gemm_f32(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, c
               int64_t lda, int64_t sA, const float* B, int64_t ldb, int64_t sB, double beta, float* C,
               int64_t ldc, int64_t sC, int batch, int tri, hipStream_t s);
 void widen_f32(int64_t count, const float* src, double* dst, hipStream_t s);
+// out[e] = sum_{s < splits} part[s * stride + e]
+void launch_sum_parts(int64_t count, int splits, int64_t stride, const double* part, double* out, hipStream_t s);
 void narrow_f64(int64_t count, const double* src, float* dst, hipStream_t s);
 // Gram of a sketch with split-K: G (dp x dp, ld dp) lower = SA^T SA + nu2 diag(lam) (padding
 // rows/cols beyond d get identity).  part: scratch of splits * dp * dp doubles.
