@@ -21,6 +21,8 @@ FLAGS = [
     "-Wno-unused-variable", "-Wno-unused-but-set-variable",
     # packed FP32 instructions are disabled for all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs: no AGPR <-> VGPR copies around the K loops
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]
 

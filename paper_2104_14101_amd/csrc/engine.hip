@@ -346,15 +346,15 @@ class Solver {
         // above nu^2 Lambda once nu is small, and would not stay positive definite.
         SA_ = B<double>("SA", (size_t)m_ * d_);
         widen_f32(m_ * d_, SA32_, SA_, s_);
-        const int splits = gram_splits(h_->num_cu, m_, d_);
+        const int splits = gram_splits(h_->num_cu, m_, d_, true);
         double* part = B<double>("gram_part", (size_t)splits * fp_ * fp_);
         gram_tn(m_, d_, SA_, d_, nu2_, lam_, part, splits, G, fp_, s_);
       } else if (bf) {
-        const int splits = gram_splits(h_->num_cu, m_, d_);
+        const int splits = gram_splits(h_->num_cu, m_, d_, false);
         float* part = B<float>("gram_part32", (size_t)splits * fp_ * fp_);
         gram_tn_bf16(m_, d_, SA16_, d_, nu2_, lam_, part, splits, G, fp_, s_);
       } else {
-        const int splits = gram_splits(h_->num_cu, m_, d_);
+        const int splits = gram_splits(h_->num_cu, m_, d_, true);
         double* part = B<double>("gram_part", (size_t)splits * fp_ * fp_);
         gram_tn(m_, d_, SA_, d_, nu2_, lam_, part, splits, G, fp_, s_);
       }
@@ -1129,7 +1129,7 @@ aes_status aes_factor(aes_handle h, void* stream, int64_t m, int64_t d, const do
     double* invlam = h->buf<double>("fa.invlam", d);
     launch_inv(d, lambda, invlam, s);
     if (!wb) {
-      const int splits = gram_splits(h->num_cu, m, d);
+      const int splits = gram_splits(h->num_cu, m, d, true);
       double* part = h->buf<double>("fa.part", (size_t)splits * fp * fp);
       gram_tn(m, d, SA, d, nu * nu, lambda, part, splits, Gp, fp, s);
     } else {

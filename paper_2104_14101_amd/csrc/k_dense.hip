@@ -85,10 +85,16 @@ template <typename T, bool TA, bool TB, int BM, int BN, int BK>
 __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
                                                    const T* __restrict__ A, int64_t lda, int64_t sA,
                                                    const T* __restrict__ B, int64_t ldb, int64_t sB, double beta,
-                                                   T* C, int64_t ldc, int64_t sC, int tri) {
+                                                   T* C, int64_t ldc, int64_t sC, int tri, int vec) {
   typedef Mfma16<T> MF;
   typedef typename MF::acc_t acc_t;
+  // Each thread moves VW consecutive elements (16 bytes) along the contiguous direction of the
+  // operand: rows of A^T / B (TA / !TB) or the K direction (!TA / TB).
+  constexpr int VW = 16 / sizeof(T);
   constexpr int LA = BM * BK / 256, LB = BK * BN / 256;
+  constexpr int LAV = LA / VW, LBV = LB / VW;
+  static_assert(LAV * VW == LA && LBV * VW == LB, "tile too small for 16-byte loads");
+  typedef T VT __attribute__((ext_vector_type(VW)));
   constexpr int WI = BM / 32, WJ = BN / 32;  // 16 x 16 blocks per wave
   const int64_t bz = blockIdx.z;
   A += bz * sA;
@@ -96,6 +102,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
   C += bz * sC;
   const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
   if (tri && n0 > m0 + BM - 1) return;
+  // interior tile with 16-byte aligned rows (vec: checked by the host for K, lda, ldb, bases)
+  const bool interior = vec && m0 + BM <= M && n0 + BN <= N;
   __shared__ T As[2][BK][BM + 1], Bs[2][BK][BN + 1];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wm = w >> 1, wn = w & 1;
   acc_t acc[WI][WJ];
@@ -104,39 +112,73 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
 #pragma unroll
     for (int bj = 0; bj < WJ; ++bj) acc[bi][bj] = acc_t{0, 0, 0, 0};
   T ra[LA], rb[LB];
+  // (k, i) of element e of vector q of the A tile, (k, j) of the B tile
+  auto a_at = [&](int q, int e, int& k, int& i) {
+    const int idx = tid + q * 256;
+    if (TA) { k = idx / (BM / VW); i = (idx % (BM / VW)) * VW + e; }
+    else { k = (idx % (BK / VW)) * VW + e; i = idx / (BK / VW); }
+  };
+  auto b_at = [&](int q, int e, int& k, int& j) {
+    const int idx = tid + q * 256;
+    if (TB) { k = (idx % (BK / VW)) * VW + e; j = idx / (BK / VW); }
+    else { k = idx / (BN / VW); j = (idx % (BN / VW)) * VW + e; }
+  };
   auto load = [&](int64_t k0) {
+    if (interior) {
 #pragma unroll
-    for (int q = 0; q < LA; ++q) {
-      const int idx = tid + q * 256;
-      const int k = TA ? idx / BM : idx % BK;
-      const int i = TA ? idx % BM : idx / BK;
-      const int64_t gi = m0 + i, gk = k0 + k;
-      ra[q] = (gi < M && gk < K) ? (TA ? A[gk * lda + gi] : A[gi * lda + gk]) : T(0);
-    }
+      for (int q = 0; q < LAV; ++q) {
+        int k, i;
+        a_at(q, 0, k, i);
+        const VT v = *reinterpret_cast<const VT*>(TA ? A + (k0 + k) * lda + m0 + i : A + (m0 + i) * lda + k0 + k);
 #pragma unroll
-    for (int q = 0; q < LB; ++q) {
-      const int idx = tid + q * 256;
-      const int k = TB ? idx % BK : idx / BN;
-      const int j = TB ? idx / BK : idx % BN;
-      const int64_t gj = n0 + j, gk = k0 + k;
-      rb[q] = (gj < N && gk < K) ? (TB ? B[gj * ldb + gk] : B[gk * ldb + gj]) : T(0);
+        for (int e = 0; e < VW; ++e) ra[q * VW + e] = v[e];
+      }
+#pragma unroll
+      for (int q = 0; q < LBV; ++q) {
+        int k, j;
+        b_at(q, 0, k, j);
+        const VT v = *reinterpret_cast<const VT*>(TB ? B + (n0 + j) * ldb + k0 + k : B + (k0 + k) * ldb + n0 + j);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) rb[q * VW + e] = v[e];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < LAV; ++q)
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+          int k, i;
+          a_at(q, e, k, i);
+          const int64_t gi = m0 + i, gk = k0 + k;
+          ra[q * VW + e] = (gi < M && gk < K) ? (TA ? A[gk * lda + gi] : A[gi * lda + gk]) : T(0);
+        }
+#pragma unroll
+      for (int q = 0; q < LBV; ++q)
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+          int k, j;
+          b_at(q, e, k, j);
+          const int64_t gj = n0 + j, gk = k0 + k;
+          rb[q * VW + e] = (gj < N && gk < K) ? (TB ? B[gj * ldb + gk] : B[gk * ldb + gj]) : T(0);
+        }
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < LA; ++q) {
-      const int idx = tid + q * 256;
-      const int k = TA ? idx / BM : idx % BK;
-      const int i = TA ? idx % BM : idx / BK;
-      As[buf][k][i] = ra[q];
-    }
+    for (int q = 0; q < LAV; ++q)
 #pragma unroll
-    for (int q = 0; q < LB; ++q) {
-      const int idx = tid + q * 256;
-      const int k = TB ? idx % BK : idx / BN;
-      const int j = TB ? idx / BK : idx % BN;
-      Bs[buf][k][j] = rb[q];
-    }
+      for (int e = 0; e < VW; ++e) {
+        int k, i;
+        a_at(q, e, k, i);
+        As[buf][k][i] = ra[q * VW + e];
+      }
+#pragma unroll
+    for (int q = 0; q < LBV; ++q)
+#pragma unroll
+      for (int e = 0; e < VW; ++e) {
+        int k, j;
+        b_at(q, e, k, j);
+        Bs[buf][k][j] = rb[q * VW + e];
+      }
   };
   load(0);
   store(0);
@@ -183,20 +225,25 @@ static void gemm_dispatch(int64_t M, int64_t N, int64_t K, double alpha, const T
                           const T* B, int64_t ldb, int64_t sB, double beta, T* C, int64_t ldc, int64_t sC, int batch,
                           int tri, hipStream_t s) {
   const int64_t tiles128 = ceil_div(M, 128) * ceil_div(N, 128) * batch;
+  // 16-byte vector loads need 16-byte aligned operand rows and whole K-steps (32 elements
+  // covers every configuration's K-step)
+  constexpr int VW = 16 / sizeof(T);
+  const int vec = ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0) && lda % VW == 0 && ldb % VW == 0 &&
+                  sA % VW == 0 && sB % VW == 0 && K % 32 == 0;
   if (N <= 32 && M >= 128) {
     // skinny products (multi-RHS matvecs, preconditioner applications): 128 x 32 tiles
     constexpr int BKS = sizeof(T) == 8 ? 16 : 32;
     dim3 grid(1u, (unsigned)ceil_div(M, 128), (unsigned)batch);
     hipLaunchKernelGGL((gemm_kernel<T, TA, TB, 128, 32, BKS>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B,
-                       ldb, sB, beta, C, ldc, sC, tri);
+                       ldb, sB, beta, C, ldc, sC, tri, vec);
   } else if (M >= 128 && N >= 128 && tiles128 >= 128) {
     dim3 grid((unsigned)ceil_div(N, 128), (unsigned)ceil_div(M, 128), (unsigned)batch);
     hipLaunchKernelGGL((gemm_kernel<T, TA, TB, 128, 128, 16>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B,
-                       ldb, sB, beta, C, ldc, sC, tri);
+                       ldb, sB, beta, C, ldc, sC, tri, vec);
   } else {
     dim3 grid((unsigned)ceil_div(N, 64), (unsigned)ceil_div(M, 64), (unsigned)batch);
     hipLaunchKernelGGL((gemm_kernel<T, TA, TB, 64, 64, 32>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B,
-                       ldb, sB, beta, C, ldc, sC, tri);
+                       ldb, sB, beta, C, ldc, sC, tri, vec);
   }
   AES_LAUNCH_CHECK();
 }
@@ -227,13 +274,21 @@ void gemm_f32(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, c
 // ---------------------------------------------------------------------------------------
 // Gram of the sketch.
 // ---------------------------------------------------------------------------------------
-int gram_splits(int num_cu, int64_t m, int64_t d) {
-  const int64_t tiles = ceil_div(d, BT) * (ceil_div(d, BT) + 1) / 2;
-  int64_t splits = ceil_div((int64_t)num_cu * 2, tiles);
-  const int64_t max_by_k = ceil_div(m, 256);  // keep >= 256 rows per split
-  if (splits > max_by_k) splits = max_by_k;
-  if (splits > 64) splits = 64;
-  return (int)(splits < 1 ? 1 : splits);
+int gram_splits(int num_cu, int64_t m, int64_t d, bool fp64) {
+  // lower-triangle output tiles of the GEMM that will run: FP64 uses 128 x 128 tiles from
+  // d = 128 on, the BF16 Gram 64 x 64 tiles; two workgroups of either fit on a CU
+  const int64_t t = (fp64 && d >= 128) ? 128 : BT;
+  const int64_t tiles = ceil_div(d, t) * (ceil_div(d, t) + 1) / 2;
+  const int64_t slots = 2 * (int64_t)num_cu;
+  const int64_t max_by_k = std::max<int64_t>(1, m / 256);  // keep >= 256 rows per split
+  const int64_t max_s = std::min<int64_t>(16, max_by_k);
+  // rounds of resident workgroups per unit of work: ceil(tiles * s / slots) / s; the smallest
+  // split count within 5% of the best (fewer partial sums to reduce)
+  double best = 1e30;
+  for (int64_t sp = 1; sp <= max_s; ++sp) best = std::min(best, (double)ceil_div(tiles * sp, slots) / sp);
+  for (int64_t sp = 1; sp <= max_s; ++sp)
+    if ((double)ceil_div(tiles * sp, slots) / sp <= 1.05 * best) return (int)sp;
+  return 1;
 }
 
 // G[i,j] (lower, padded to dp) = sum_s part[s][i][j] + nu2 lam_i [i == j]; identity padding; upper = 0
@@ -255,9 +310,9 @@ __global__ void gram_reduce_kernel(const TP* __restrict__ part, int splits, int6
 
 void gram_tn(int64_t m, int64_t d, const double* SA, int64_t ldsa, double nu2, const double* lam, double* part,
              int splits, double* G, int64_t dp, hipStream_t s) {
-  const int64_t rows = ceil_div(m, splits);
-  // splits with identical row counts except the last: run the full batch on `rows` rows
-  // (the tail split reads rows up to m only through a separate call)
+  // splits with identical row counts (a multiple of 32, for the vector loads) except the
+  // last: run the full batch on `rows` rows; the tail split goes through a separate call
+  const int64_t rows = round_up(ceil_div(m, splits), 32);
   const int full = (int)(m / rows);
   if (full > 0)
     gemm_f64(true, false, d, d, rows, 1.0, SA, ldsa, rows * ldsa, SA, ldsa, rows * ldsa, 0.0, part, dp, dp * dp, full,
@@ -429,42 +484,42 @@ void gram_nt_bf16(int64_t m, int64_t d, const __hip_bfloat16* SA, int64_t ldsa, 
 //   [A21 A22 ]   L21 = A21 X11^T,  S = A22 - L21 L21^T
 //                L22 = chol(S),    X22 = L22^{-1}            (recursive)
 //                X21 = -X22 (L21 X11)
-// Leaves are 64 x 64 blocks, factorised and inverted by one wavefront: lane i keeps row i in
-// registers and reads the pivot column through cross-lane reads, so no barrier is needed.
+// Leaves are 64 x 64 blocks, factorised and inverted by one wavefront (below).
 // ---------------------------------------------------------------------------------------
-// Leaf: one wavefront, lane i owns row i.  Left-looking (Crout) Cholesky: at step j every
-// lane forms s_i = A[i][j] - sum_{k<j} L[i][k] L[j][k] with row j of L read from LDS (a
-// broadcast read); lane j takes the square root, the lanes below divide by it.  Then the
-// inverse X = L^{-1} column-parallel: lane j owns column j and runs the forward substitution
-// x_i = (delta_ij - sum_{k<i} L[i][k] x_k) / L[i][i] with L[i][k] again a broadcast read.
 typedef double d2 __attribute__((ext_vector_type(2)));
-
-// sum_{k<LEN} a[k] * row[k] with four independent partial sums and 16-byte LDS reads (row is
-// 16-byte aligned); LEN is a compile-time constant.
-template <int LEN>
-__device__ __forceinline__ double dot_lds(const double (&a)[64], const double* row) {
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-#pragma unroll
-  for (int k = 0; k + 3 < LEN; k += 4) {
-    const d2 u = *reinterpret_cast<const d2*>(row + k);
-    const d2 v = *reinterpret_cast<const d2*>(row + k + 2);
-    s0 = fma(a[k], u[0], s0);
-    s1 = fma(a[k + 1], u[1], s1);
-    s2 = fma(a[k + 2], v[0], s2);
-    s3 = fma(a[k + 3], v[1], s3);
-  }
-#pragma unroll
-  for (int k = LEN & ~3; k < LEN; ++k) s0 = fma(a[k], row[k], s0);
-  return (s0 + s1) + (s2 + s3);
-}
 
 template <int J>
 struct LeafStep {
-  // Cholesky column J (left-looking), then the next column.
-  __device__ __forceinline__ static void chol(double (&r)[64], double (*Ls)[66], double* rdiag, int lane, bool& bad) {
-    const double sacc = r[J] - dot_lds<J>(r, Ls[J]);
+  // Step J of the fused leaf: row J of L (columns < J) is read once from LDS, in batches of up
+  // to 16 16-byte reads issued before any is consumed, and serves both the Cholesky column J
+  // (left-looking) and row J of the forward substitution for X = L^{-1}.
+  __device__ __forceinline__ static void step(double (&r)[64], double (&x)[64], double (*Ls)[66], double* rdiag,
+                                              int lane, bool& bad) {
+    double sr0 = 0.0, sr1 = 0.0, sx0 = 0.0, sx1 = 0.0;
+#pragma unroll
+    for (int k0 = 0; k0 < J; k0 += 32) {
+      d2 buf[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (k0 + 2 * q < J) buf[q] = *reinterpret_cast<const d2*>(&Ls[J][k0 + 2 * q]);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int k = k0 + 2 * q;
+        if (k < J) {
+          sr0 = fma(r[k], buf[q][0], sr0);
+          sx0 = fma(x[k], buf[q][0], sx0);
+        }
+        if (k + 1 < J) {
+          sr1 = fma(r[k + 1], buf[q][1], sr1);
+          sx1 = fma(x[k + 1], buf[q][1], sx1);
+        }
+      }
+    }
+    const double sr = r[J] - (sr0 + sr1);
+    const double sx = ((J == lane) ? 1.0 : 0.0) - (sx0 + sx1);
     if (lane == J) {
-      double piv = sacc;
+      double piv = sr;
       if (!(piv > 0.0)) {
         bad = true;
         piv = 1.0;
@@ -477,29 +532,24 @@ struct LeafStep {
       rdiag[J] = y;
     }
     __syncthreads();
-    r[J] = (lane == J) ? Ls[J][J] : sacc * rdiag[J];
+    const double rd = rdiag[J];
+    r[J] = (lane == J) ? Ls[J][J] : sr * rd;
+    x[J] = sx * rd;
     if (lane > J) Ls[lane][J] = r[J];
     __syncthreads();
-    LeafStep<J + 1>::chol(r, Ls, rdiag, lane, bad);
-  }
-  // Row J of the column-parallel forward substitution for X = L^{-1}.
-  __device__ __forceinline__ static void inv(double (&x)[64], double (*Ls)[66], const double* rdiag, int lane) {
-    const double sacc = ((J == lane) ? 1.0 : 0.0) - dot_lds<J>(x, Ls[J]);
-    x[J] = sacc * rdiag[J];
-    LeafStep<J + 1>::inv(x, Ls, rdiag, lane);
+    LeafStep<J + 1>::step(r, x, Ls, rdiag, lane, bad);
   }
 };
 template <>
 struct LeafStep<64> {
-  __device__ __forceinline__ static void chol(double (&)[64], double (*)[66], double*, int, bool&) {}
-  __device__ __forceinline__ static void inv(double (&)[64], double (*)[66], const double*, int) {}
+  __device__ __forceinline__ static void step(double (&)[64], double (&)[64], double (*)[66], double*, int, bool&) {}
 };
 
-// Leaf: one wavefront, lane i owns row i in registers.  Left-looking (Crout) Cholesky: at step j
-// every lane forms s_i = A[i][j] - sum_{k<j} L[i][k] L[j][k] with row j of L read from LDS (a
-// broadcast read); lane j takes the reciprocal square root of its pivot, the lanes below scale
-// by it.  Then the inverse X = L^{-1} column-parallel: lane c owns column c and runs
-// x_i = (delta_ic - sum_{k<i} L[i][k] x_k) / L[i][i], L[i][k] again a broadcast read.
+// Leaf: one wavefront, lane i owns row i of L and column i of X = L^{-1} in registers.
+// Left-looking (Crout) Cholesky: at step j every lane forms s_i = A[i][j] - sum_{k<j} L[i][k]
+// L[j][k] with row j of L read from LDS (a broadcast read); lane j takes the reciprocal square
+// root of its pivot, the lanes below scale by it.  The same row j gives the column-parallel
+// forward substitution x_jc = (delta_jc - sum_{k<j} L[j][k] x_kc) / L[j][j] of lane c.
 __global__ __launch_bounds__(64) void chol_inv_leaf_kernel(double* __restrict__ G, int64_t ld, double* __restrict__ X,
                                                            int64_t ldx, int* __restrict__ flag) {
   __shared__ __attribute__((aligned(16))) double Ls[64][66];
@@ -507,15 +557,13 @@ __global__ __launch_bounds__(64) void chol_inv_leaf_kernel(double* __restrict__ 
   const int lane = threadIdx.x;
   for (int i = 0; i < 64; ++i) Ls[i][lane] = G[(int64_t)i * ld + lane];  // coalesced staging
   __syncthreads();
-  double r[64];
+  double r[64], x[64];
 #pragma unroll
   for (int j = 0; j < 64; ++j) r[j] = (j <= lane) ? Ls[lane][j] : 0.0;
   __syncthreads();
   bool bad = false;
-  LeafStep<0>::chol(r, Ls, rdiag, lane, bad);
+  LeafStep<0>::step(r, x, Ls, rdiag, lane, bad);
   for (int i = 0; i < 64; ++i) G[(int64_t)i * ld + lane] = (lane <= i) ? Ls[i][lane] : 0.0;
-  double x[64];
-  LeafStep<0>::inv(x, Ls, rdiag, lane);
 #pragma unroll
   for (int i = 0; i < 64; ++i) X[(int64_t)i * ldx + lane] = (i >= lane) ? x[i] : 0.0;
   if (bad && lane == 0) atomicOr(flag, 1);

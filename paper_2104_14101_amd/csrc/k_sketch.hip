@@ -308,55 +308,81 @@ __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A
   constexpr bool LAST = MODE == 2 || MODE == 3;
 
   if (MODE == 0 && base >= n) return;  // all-padding tile: implicit zeros
+  // per-row flags of the tile kept in LDS: output row (last pass) or "needed" (pruned first pass)
+  __shared__ int32_t rowflag[1 << kMaxTileBits];
   if (LAST) {
     int found = 0;
-    for (int j = tid; j < R; j += 256) found |= pos[base + ((int64_t)j << s)] >= 0;
+    for (int j = tid; j < R; j += 256) {
+      const int32_t pr = pos[base + ((int64_t)j << s)];
+      rowflag[j] = pr;
+      found |= pr >= 0;
+    }
     if (!__syncthreads_or(found)) return;  // no selected row in this tile
-  }
-  // First pass of a pruned two-pass transform: bit q of nmask says whether the row this thread
-  // stores at iteration q (row (tid + 256 q) / TPR of the tile) is needed by the last pass.
-  // R * TPR / 256 <= 32 iterations (R <= 512 rows, TPR <= 16 threads per row).
-  uint32_t nmask = 0xffffffffu;
-  if (MODE == 0 && need) {
-    nmask = 0;
-    for (int q = 0; q * 256 < R * TPR; ++q)
-      if (need[(tid + 256 * q) / TPR]) nmask |= 1u << q;
+  } else if (MODE == 0 && need) {
+    for (int j = tid; j < R; j += 256) rowflag[j] = need[j];
   }
   const bool vec_in =
       ((d % VW) == 0) && (!FIRST || ((lda % VW) == 0 && sizeof(TIN) == sizeof(TACC) && a_aligned));
-  // load
-  for (int idx = tid; idx < R * TPR; idx += 256) {
-    const int j = idx / TPR, cv = (idx % TPR) * VW;
-    const int64_t row = base + ((int64_t)j << s);
-    const int64_t col = c0 + cv;
-    TACC v[VW];
+  typedef TACC VT __attribute__((ext_vector_type(VW)));
+  if (vec_in) {
+    // Batches of kLoadBatch independent 16-byte loads per thread are issued before any of them
+    // is consumed, so that a workgroup keeps its whole tile in flight.
+    constexpr int kLoadBatch = 16;
+    for (int i0 = 0; i0 < R * TPR; i0 += 256 * kLoadBatch) {
+      VT u[kLoadBatch];
+      TACC sg[kLoadBatch];
 #pragma unroll
-    for (int e = 0; e < VW; ++e) v[e] = 0;
-    bool load = col < d;
-    const TACC sg = FIRST ? (TACC)(row < n ? eps[row] : 0.0) : TACC(1);
-    if (FIRST) load = load && row < n;
-    else load = load && !(zero_bits > 0 && ((row >> zero_bits) << zero_bits) >= n);
-    if (load) {
-      if (vec_in && col + VW <= d) {
-        if (FIRST) {
-          typedef TACC VT __attribute__((ext_vector_type(VW)));
-          const VT u = __builtin_nontemporal_load(reinterpret_cast<const VT*>(reinterpret_cast<const TACC*>(A) + row * lda + col));
-#pragma unroll
-          for (int e = 0; e < VW; ++e) v[e] = u[e] * sg;
+      for (int q = 0; q < kLoadBatch; ++q) {
+        const int idx = i0 + tid + 256 * q;
+        const int j = idx / TPR, cv = (idx % TPR) * VW;
+        const int64_t row = base + ((int64_t)j << s);
+        const int64_t col = c0 + cv;
+        bool load = idx < R * TPR && col < d;
+        if (FIRST) load = load && row < n;
+        else load = load && !(zero_bits > 0 && ((row >> zero_bits) << zero_bits) >= n);
+        sg[q] = TACC(1);
+        if (load) {
+          if (FIRST) {
+            u[q] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(reinterpret_cast<const TACC*>(A) + row * lda + col));
+            sg[q] = (TACC)eps[row];
+          } else {
+            u[q] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(Ysrc + row * d + col));
+          }
         } else {
-          typedef TACC VT __attribute__((ext_vector_type(VW)));
-          const VT u = __builtin_nontemporal_load(reinterpret_cast<const VT*>(Ysrc + row * d + col));
 #pragma unroll
-          for (int e = 0; e < VW; ++e) v[e] = u[e];
+          for (int e = 0; e < VW; ++e) u[q][e] = TACC(0);
         }
-      } else {
+      }
+#pragma unroll
+      for (int q = 0; q < kLoadBatch; ++q) {
+        const int idx = i0 + tid + 256 * q;
+        if (idx < R * TPR) {
+          const int j = idx / TPR, cv = (idx % TPR) * VW;
+#pragma unroll
+          for (int e = 0; e < VW; ++e) tile[j * CW + cv + e] = FIRST ? u[q][e] * sg[q] : u[q][e];
+        }
+      }
+    }
+  } else {
+    for (int idx = tid; idx < R * TPR; idx += 256) {
+      const int j = idx / TPR, cv = (idx % TPR) * VW;
+      const int64_t row = base + ((int64_t)j << s);
+      const int64_t col = c0 + cv;
+      TACC v[VW];
+#pragma unroll
+      for (int e = 0; e < VW; ++e) v[e] = 0;
+      bool load = col < d;
+      const TACC sg = FIRST ? (TACC)(row < n ? eps[row] : 0.0) : TACC(1);
+      if (FIRST) load = load && row < n;
+      else load = load && !(zero_bits > 0 && ((row >> zero_bits) << zero_bits) >= n);
+      if (load) {
 #pragma unroll
         for (int e = 0; e < VW; ++e)
           if (col + e < d) v[e] = FIRST ? cvt<TACC>(A[row * lda + col + e]) * sg : (TACC)Ysrc[row * d + col + e];
       }
-    }
 #pragma unroll
-    for (int e = 0; e < VW; ++e) tile[j * CW + cv + e] = v[e];
+      for (int e = 0; e < VW; ++e) tile[j * CW + cv + e] = v[e];
+    }
   }
   __syncthreads();
   for (int g = 0; g < b; g += 3) {
@@ -367,13 +393,13 @@ __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A
     __syncthreads();
   }
   // store
-  for (int idx = tid, q = 0; idx < R * TPR; idx += 256, ++q) {
+  for (int idx = tid; idx < R * TPR; idx += 256) {
     const int j = idx / TPR, cv = (idx % TPR) * VW;
     const int64_t row = base + ((int64_t)j << s);
     const int64_t col = c0 + cv;
     if (col >= d) continue;
     if (LAST) {
-      const int32_t pr = pos[row];
+      const int32_t pr = rowflag[j];
       if (pr < 0) continue;
 #pragma unroll
       for (int e = 0; e < VW; ++e)
@@ -384,7 +410,7 @@ __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A
           else
             SA[(int64_t)pr * ldsa + col + e] = cvt<TOUT>((float)(v * (float)scale));
         }
-    } else if (MODE == 0 && !((nmask >> q) & 1u)) {
+    } else if (MODE == 0 && need && !rowflag[j]) {
       continue;  // first pass of a two-pass transform: no sampled row has these low index bits
     } else if ((d % VW) == 0 && col + VW <= d) {
       typedef TACC VT __attribute__((ext_vector_type(VW)));

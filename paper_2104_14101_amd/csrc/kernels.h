@@ -112,7 +112,7 @@ void launch_sum_parts(int64_t count, int splits, int64_t stride, const double* p
 void narrow_f64(int64_t count, const double* src, float* dst, hipStream_t s);
 // Gram of a sketch with split-K: G (dp x dp, ld dp) lower = SA^T SA + nu2 diag(lam) (padding
 // rows/cols beyond d get identity).  part: scratch of splits * dp * dp doubles.
-int gram_splits(int num_cu, int64_t m, int64_t d);
+int gram_splits(int num_cu, int64_t m, int64_t d, bool fp64);
 void gram_tn(int64_t m, int64_t d, const double* SA, int64_t ldsa, double nu2, const double* lam,
              double* part, int splits, double* G, int64_t dp, hipStream_t s);
 // BF16 SA (m x d, ld ldsa) with FP32 accumulation on MFMA; G as above in FP64.
