@@ -488,85 +488,138 @@ void gram_nt_bf16(int64_t m, int64_t d, const __hip_bfloat16* SA, int64_t ldsa, 
 // ---------------------------------------------------------------------------------------
 typedef double d2 __attribute__((ext_vector_type(2)));
 
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)bits, l);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Leaf LDS: L row-major (Ls, read by the inverse wave and written out), L column-major (Lc,
+// broadcast rows for the Cholesky wave's rank-1 updates), 1 / L[j][j].
+struct LeafLds {
+  double Ls[64][66];
+  double Lc[64][66];
+  double rdiag[64];
+};
+
+// Cholesky wave, step J (right-looking): lane i holds row i of the partially updated matrix in
+// a[].  The pivot a[J] of lane J is broadcast with a cross-lane read, every lane scales its
+// entry, the next column is updated at once (look-ahead: it holds the next pivot), and the
+// remaining columns receive the rank-1 update with column J read back from Lc.  A barrier
+// after every 8 steps releases the inverse wave.
 template <int J>
-struct LeafStep {
-  // Step J of the fused leaf: row J of L (columns < J) is read once from LDS, in batches of up
-  // to 16 16-byte reads issued before any is consumed, and serves both the Cholesky column J
-  // (left-looking) and row J of the forward substitution for X = L^{-1}.
-  __device__ __forceinline__ static void step(double (&r)[64], double (&x)[64], double (*Ls)[66], double* rdiag,
-                                              int lane, bool& bad) {
-    double sr0 = 0.0, sr1 = 0.0, sx0 = 0.0, sx1 = 0.0;
+struct LeafChol {
+  __device__ __forceinline__ static void step(double (&a)[64], LeafLds& sm, int lane, bool& bad) {
+    const double pj = readlane_d(a[J], J);
+    const bool ok = pj > 0.0;  // uniform
+    if (!ok) bad = true;
+    const double piv = ok ? pj : 1.0;
+    // 1/sqrt(piv): hardware estimate refined by two Newton steps (y <- y (3 - p y^2) / 2)
+    double y = __builtin_amdgcn_rsq(piv);
+    y = y * fma(-0.5 * piv, y * y, 1.5);
+    y = y * fma(-0.5 * piv, y * y, 1.5);
+    const double l = lane == J ? piv * y : (lane > J ? a[J] * y : 0.0);
+    a[J] = l;
+    sm.Ls[lane][J] = l;
+    sm.Lc[J][lane] = l;
+    if (lane == 0) sm.rdiag[J] = y;
+    if constexpr (J + 1 < 64) {
+      const double l1 = readlane_d(l, J + 1);
+      a[J + 1] = fma(-l, l1, a[J + 1]);
+    }
+    if constexpr (J + 2 < 64) {
+      // Lc[J][] written above by all lanes of this wave: LDS operations of one wave complete in order
+      __builtin_amdgcn_s_waitcnt(0xC07F);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      constexpr int K0 = (J + 2) & ~1;  // 16-byte aligned start
+#pragma unroll
+      for (int k0 = K0; k0 < 64; k0 += 32) {
+        d2 buf[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (k0 + 2 * q < 64) buf[q] = *reinterpret_cast<const d2*>(&sm.Lc[J][k0 + 2 * q]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int k = k0 + 2 * q;
+          if (k < 64 && k >= J + 2) a[k] = fma(-l, buf[q][0], a[k]);
+          if (k + 1 < 64 && k + 1 >= J + 2) a[k + 1] = fma(-l, buf[q][1], a[k + 1]);
+        }
+      }
+    }
+    if constexpr ((J & 7) == 7) __syncthreads();
+    LeafChol<J + 1>::step(a, sm, lane, bad);
+  }
+};
+template <>
+struct LeafChol<64> {
+  __device__ __forceinline__ static void step(double (&)[64], LeafLds&, int, bool&) {}
+};
+
+// Inverse wave, step J: lane c owns column c of X = L^{-1} and runs the forward substitution
+// x_J = (delta_Jc - sum_{k<J} L[J][k] x_k) / L[J][J] with row J of L read from Ls (batches of
+// 16-byte broadcast reads).  Rows 8b .. 8b+7 are final after the Cholesky wave's barrier b.
+template <int J>
+struct LeafInv {
+  __device__ __forceinline__ static void step(double (&x)[64], LeafLds& sm, int lane) {
+    if constexpr ((J & 7) == 0) __syncthreads();
+    double s0 = 0.0, s1 = 0.0;
 #pragma unroll
     for (int k0 = 0; k0 < J; k0 += 32) {
       d2 buf[16];
 #pragma unroll
       for (int q = 0; q < 16; ++q)
-        if (k0 + 2 * q < J) buf[q] = *reinterpret_cast<const d2*>(&Ls[J][k0 + 2 * q]);
+        if (k0 + 2 * q < J) buf[q] = *reinterpret_cast<const d2*>(&sm.Ls[J][k0 + 2 * q]);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int k = k0 + 2 * q;
-        if (k < J) {
-          sr0 = fma(r[k], buf[q][0], sr0);
-          sx0 = fma(x[k], buf[q][0], sx0);
-        }
-        if (k + 1 < J) {
-          sr1 = fma(r[k + 1], buf[q][1], sr1);
-          sx1 = fma(x[k + 1], buf[q][1], sx1);
-        }
+        if (k < J) s0 = fma(x[k], buf[q][0], s0);
+        if (k + 1 < J) s1 = fma(x[k + 1], buf[q][1], s1);
       }
     }
-    const double sr = r[J] - (sr0 + sr1);
-    const double sx = ((J == lane) ? 1.0 : 0.0) - (sx0 + sx1);
-    if (lane == J) {
-      double piv = sr;
-      if (!(piv > 0.0)) {
-        bad = true;
-        piv = 1.0;
-      }
-      // 1/sqrt(piv): hardware estimate refined by two Newton steps (y <- y (3 - p y^2) / 2)
-      double y = __builtin_amdgcn_rsq(piv);
-      y = y * fma(-0.5 * piv, y * y, 1.5);
-      y = y * fma(-0.5 * piv, y * y, 1.5);
-      Ls[J][J] = piv * y;
-      rdiag[J] = y;
-    }
-    __syncthreads();
-    const double rd = rdiag[J];
-    r[J] = (lane == J) ? Ls[J][J] : sr * rd;
-    x[J] = sx * rd;
-    if (lane > J) Ls[lane][J] = r[J];
-    __syncthreads();
-    LeafStep<J + 1>::step(r, x, Ls, rdiag, lane, bad);
+    x[J] = (((J == lane) ? 1.0 : 0.0) - (s0 + s1)) * sm.rdiag[J];
+    LeafInv<J + 1>::step(x, sm, lane);
   }
 };
 template <>
-struct LeafStep<64> {
-  __device__ __forceinline__ static void step(double (&)[64], double (&)[64], double (*)[66], double*, int, bool&) {}
+struct LeafInv<64> {
+  __device__ __forceinline__ static void step(double (&)[64], LeafLds&, int) {}
 };
 
-// Leaf: one wavefront, lane i owns row i of L and column i of X = L^{-1} in registers.
-// Left-looking (Crout) Cholesky: at step j every lane forms s_i = A[i][j] - sum_{k<j} L[i][k]
-// L[j][k] with row j of L read from LDS (a broadcast read); lane j takes the reciprocal square
-// root of its pivot, the lanes below scale by it.  The same row j gives the column-parallel
-// forward substitution x_jc = (delta_jc - sum_{k<j} L[j][k] x_kc) / L[j][j] of lane c.
-__global__ __launch_bounds__(64) void chol_inv_leaf_kernel(double* __restrict__ G, int64_t ld, double* __restrict__ X,
-                                                           int64_t ldx, int* __restrict__ flag) {
-  __shared__ __attribute__((aligned(16))) double Ls[64][66];
-  __shared__ double rdiag[64];
-  const int lane = threadIdx.x;
-  for (int i = 0; i < 64; ++i) Ls[i][lane] = G[(int64_t)i * ld + lane];  // coalesced staging
-  __syncthreads();
-  double r[64], x[64];
+// Leaf: Cholesky factor L (written over G, upper triangle zeroed) and X = L^{-1} of a 64 x 64
+// block, by two wavefronts: wave 0 factorises, wave 1 inverts one 8-row block behind it.
+__global__ __launch_bounds__(128) void chol_inv_leaf_kernel(double* __restrict__ G, int64_t ld, double* __restrict__ X,
+                                                            int64_t ldx, int* __restrict__ flag) {
+  __shared__ __attribute__((aligned(16))) LeafLds sm;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  {
+    double v[32];
 #pragma unroll
-  for (int j = 0; j < 64; ++j) r[j] = (j <= lane) ? Ls[lane][j] : 0.0;
-  __syncthreads();
-  bool bad = false;
-  LeafStep<0>::step(r, x, Ls, rdiag, lane, bad);
-  for (int i = 0; i < 64; ++i) G[(int64_t)i * ld + lane] = (lane <= i) ? Ls[i][lane] : 0.0;
+    for (int q = 0; q < 32; ++q) v[q] = G[(int64_t)(2 * q + (tid >> 6)) * ld + lane];  // coalesced staging
 #pragma unroll
-  for (int i = 0; i < 64; ++i) X[(int64_t)i * ldx + lane] = (i >= lane) ? x[i] : 0.0;
-  if (bad && lane == 0) atomicOr(flag, 1);
+    for (int q = 0; q < 32; ++q) sm.Ls[2 * q + (tid >> 6)][lane] = v[q];
+  }
+  __syncthreads();
+  if (wave == 0) {
+    double a[64];
+#pragma unroll
+    for (int j = 0; j < 64; ++j) a[j] = (j <= lane) ? sm.Ls[lane][j] : 0.0;
+    bool bad = false;
+    LeafChol<0>::step(a, sm, lane, bad);
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll 8
+    for (int i = 0; i < 64; ++i) G[(int64_t)i * ld + lane] = sm.Ls[i][lane];
+    if (bad && lane == 0) atomicOr(flag, 1);
+  } else {
+    double x[64];
+    LeafInv<0>::step(x, sm, lane);
+#pragma unroll
+    for (int i = 0; i < 64; ++i) X[(int64_t)i * ldx + lane] = (i >= lane) ? x[i] : 0.0;
+  }
 }
 
 __global__ void copy_block_kernel(int64_t rows, int64_t cols, const double* __restrict__ src, int64_t lds,
@@ -580,7 +633,7 @@ __global__ void copy_block_kernel(int64_t rows, int64_t cols, const double* __re
 static void cholinv_rec(double* G, double* X, int64_t ld, int64_t o, int64_t h, double* tmp, int* flag,
                         hipStream_t s) {
   if (h == 64) {
-    hipLaunchKernelGGL(chol_inv_leaf_kernel, dim3(1), dim3(64), 0, s, G + o * ld + o, ld, X + o * ld + o, ld, flag);
+    hipLaunchKernelGGL(chol_inv_leaf_kernel, dim3(1), dim3(128), 0, s, G + o * ld + o, ld, X + o * ld + o, ld, flag);
     AES_LAUNCH_CHECK();
     return;
   }
