@@ -383,7 +383,7 @@ class Solver {
     Linv_ = B<double>("Linv", (size_t)np * np);
     LinvT_ = B<double>("LinvT", (size_t)np * np);
     double* tmp = B<double>("cholinv_tmp", cholinv_tmp_size(np));
-    cholinv(G, np, Linv_, tmp, flag, s_);
+    cholinv(G, np, Linv_, tmp, flag, false, s_);
     launch_transpose(np, np, Linv_, np, LinvT_, np, s_);
   }
 
@@ -1142,7 +1142,7 @@ aes_status aes_factor(aes_handle h, void* stream, int64_t m, int64_t d, const do
     AES_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
     double* linv = h->buf<double>("fa.linv", (size_t)fp * fp);
     double* tmp = h->buf<double>("fa.tmp", cholinv_tmp_size(fp));
-    cholinv(Gp, fp, linv, tmp, flag, s);
+    cholinv(Gp, fp, linv, tmp, flag, true, s);
     launch_copy_cols(dim, (int)dim, Gp, fp, (int)dim, L, dim, s);
     int hf = 0;
     AES_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -81,11 +81,15 @@ struct Mfma16<float> {
 // Tiled GEMM, 256 threads = 2 x 2 waves, wave tile (BM/2) x (BN/2) of 16 x 16 MFMA blocks.
 // The next K-step is prefetched into registers while the current one is multiplied from LDS
 // (double-buffered LDS, one barrier per K-step).
-template <typename T, bool TA, bool TB, int BM, int BN, int BK>
+// MAP 0: grid (N tiles, M tiles, batch).  MAP 1 (split-K Gram, M == N, BM == BN): grid
+// (splits, lower-triangle tiles); split z covers rows [z ksplit, min(K, (z+1) ksplit)) and the
+// split index varies fastest, so that with a multiple of 8 splits each XCD (workgroups are
+// dealt to the 8 XCDs round-robin) works on its own rows and shares them through its L2.
+template <typename T, bool TA, bool TB, int BM, int BN, int BK, int MAP = 0>
 __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
                                                    const T* __restrict__ A, int64_t lda, int64_t sA,
                                                    const T* __restrict__ B, int64_t ldb, int64_t sB, double beta,
-                                                   T* C, int64_t ldc, int64_t sC, int tri, int vec) {
+                                                   T* C, int64_t ldc, int64_t sC, int tri, int vec, int64_t ksplit) {
   typedef Mfma16<T> MF;
   typedef typename MF::acc_t acc_t;
   // Each thread moves VW consecutive elements (16 bytes) along the contiguous direction of the
@@ -96,14 +100,29 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
   static_assert(LAV * VW == LA && LBV * VW == LB, "tile too small for 16-byte loads");
   typedef T VT __attribute__((ext_vector_type(VW)));
   constexpr int WI = BM / 32, WJ = BN / 32;  // 16 x 16 blocks per wave
-  const int64_t bz = blockIdx.z;
+  int64_t bz, m0, n0;
+  if (MAP == 0) {
+    bz = blockIdx.z;
+    m0 = (int64_t)blockIdx.y * BM;
+    n0 = (int64_t)blockIdx.x * BN;
+  } else {
+    static_assert(MAP == 0 || BM == BN, "square tiles");
+    bz = blockIdx.x;
+    const int64_t t = blockIdx.y;
+    int64_t ti = (int64_t)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while (ti * (ti + 1) / 2 > t) --ti;
+    while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+    m0 = ti * BM;
+    n0 = (t - ti * (ti + 1) / 2) * BN;
+    K = K - bz * ksplit;
+    K = K < 0 ? 0 : (K > ksplit ? ksplit : K);
+  }
   A += bz * sA;
   B += bz * sB;
   C += bz * sC;
-  const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
   if (tri && n0 > m0 + BM - 1) return;
-  // interior tile with 16-byte aligned rows (vec: checked by the host for K, lda, ldb, bases)
-  const bool interior = vec && m0 + BM <= M && n0 + BN <= N;
+  // interior tile with 16-byte aligned rows (vec: alignment checked by the host) and whole K-steps
+  const bool interior = vec && m0 + BM <= M && n0 + BN <= N && K > 0 && K % BK == 0;
   __shared__ T As[2][BK][BM + 1], Bs[2][BK][BN + 1];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wm = w >> 1, wn = w & 1;
   acc_t acc[WI][WJ];
@@ -229,21 +248,27 @@ static void gemm_dispatch(int64_t M, int64_t N, int64_t K, double alpha, const T
   // covers every configuration's K-step)
   constexpr int VW = 16 / sizeof(T);
   const int vec = ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0) && lda % VW == 0 && ldb % VW == 0 &&
-                  sA % VW == 0 && sB % VW == 0 && K % 32 == 0;
+                  sA % VW == 0 && sB % VW == 0;
   if (N <= 32 && M >= 128) {
     // skinny products (multi-RHS matvecs, preconditioner applications): 128 x 32 tiles
     constexpr int BKS = sizeof(T) == 8 ? 16 : 32;
     dim3 grid(1u, (unsigned)ceil_div(M, 128), (unsigned)batch);
     hipLaunchKernelGGL((gemm_kernel<T, TA, TB, 128, 32, BKS>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B,
-                       ldb, sB, beta, C, ldc, sC, tri, vec);
+                       ldb, sB, beta, C, ldc, sC, tri, vec, (int64_t)0);
   } else if (M >= 128 && N >= 128 && tiles128 >= 128) {
     dim3 grid((unsigned)ceil_div(N, 128), (unsigned)ceil_div(M, 128), (unsigned)batch);
     hipLaunchKernelGGL((gemm_kernel<T, TA, TB, 128, 128, 16>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B,
-                       ldb, sB, beta, C, ldc, sC, tri, vec);
-  } else {
+                       ldb, sB, beta, C, ldc, sC, tri, vec, (int64_t)0);
+  } else if (ceil_div(M, 64) * ceil_div(N, 64) * batch >= 128) {
     dim3 grid((unsigned)ceil_div(N, 64), (unsigned)ceil_div(M, 64), (unsigned)batch);
     hipLaunchKernelGGL((gemm_kernel<T, TA, TB, 64, 64, 32>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B,
-                       ldb, sB, beta, C, ldc, sC, tri, vec);
+                       ldb, sB, beta, C, ldc, sC, tri, vec, (int64_t)0);
+  } else {
+    // small products (the lower levels of the recursive factorisation): 32 x 32 tiles spread
+    // the work over four times as many CUs
+    dim3 grid((unsigned)ceil_div(N, 32), (unsigned)ceil_div(M, 32), (unsigned)batch);
+    hipLaunchKernelGGL((gemm_kernel<T, TA, TB, 32, 32, 32>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B,
+                       ldb, sB, beta, C, ldc, sC, tri, vec, (int64_t)0);
   }
   AES_LAUNCH_CHECK();
 }
@@ -275,15 +300,23 @@ void gemm_f32(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, c
 // Gram of the sketch.
 // ---------------------------------------------------------------------------------------
 int gram_splits(int num_cu, int64_t m, int64_t d, bool fp64) {
-  // lower-triangle output tiles of the GEMM that will run: FP64 uses 128 x 128 tiles from
-  // d = 128 on, the BF16 Gram 64 x 64 tiles; two workgroups of either fit on a CU
-  const int64_t t = (fp64 && d >= 128) ? 128 : BT;
-  const int64_t tiles = ceil_div(d, t) * (ceil_div(d, t) + 1) / 2;
+  if (fp64 && d >= 128) {
+    // XCD-aware split-K (see gemm_kernel MAP 1): a multiple of 8 splits, as few as keep the
+    // rounds of resident workgroups per XCD (two per CU) within 5% of the best
+    const int64_t nt = ceil_div(d, 128);
+    const int64_t tiles = nt * (nt + 1) / 2;
+    const int64_t slots = std::max<int64_t>(1, 2 * (int64_t)num_cu / 8);
+    const int64_t max_q = std::max<int64_t>(1, std::min<int64_t>(4, m / (8 * 256)));
+    double best = 1e30;
+    for (int64_t q = 1; q <= max_q; ++q) best = std::min(best, (double)ceil_div(tiles * q, slots) / q);
+    for (int64_t q = 1; q <= max_q; ++q)
+      if ((double)ceil_div(tiles * q, slots) / q <= 1.05 * best) return (int)(8 * q);
+    return 8;
+  }
+  // BF16 Gram: 64 x 64 tiles, two workgroups per CU
+  const int64_t tiles = ceil_div(d, BT) * (ceil_div(d, BT) + 1) / 2;
   const int64_t slots = 2 * (int64_t)num_cu;
-  const int64_t max_by_k = std::max<int64_t>(1, m / 256);  // keep >= 256 rows per split
-  const int64_t max_s = std::min<int64_t>(16, max_by_k);
-  // rounds of resident workgroups per unit of work: ceil(tiles * s / slots) / s; the smallest
-  // split count within 5% of the best (fewer partial sums to reduce)
+  const int64_t max_s = std::min<int64_t>(16, std::max<int64_t>(1, m / 256));
   double best = 1e30;
   for (int64_t sp = 1; sp <= max_s; ++sp) best = std::min(best, (double)ceil_div(tiles * sp, slots) / sp);
   for (int64_t sp = 1; sp <= max_s; ++sp)
@@ -310,20 +343,29 @@ __global__ void gram_reduce_kernel(const TP* __restrict__ part, int splits, int6
 
 void gram_tn(int64_t m, int64_t d, const double* SA, int64_t ldsa, double nu2, const double* lam, double* part,
              int splits, double* G, int64_t dp, hipStream_t s) {
-  // splits with identical row counts (a multiple of 32, for the vector loads) except the
-  // last: run the full batch on `rows` rows; the tail split goes through a separate call
+  // split z: rows [z rows, min(m, (z+1) rows)), rows a multiple of 32 (whole K-steps of the
+  // vector path); splits past the end contribute zero tiles
   const int64_t rows = round_up(ceil_div(m, splits), 32);
-  const int full = (int)(m / rows);
-  if (full > 0)
-    gemm_f64(true, false, d, d, rows, 1.0, SA, ldsa, rows * ldsa, SA, ldsa, rows * ldsa, 0.0, part, dp, dp * dp, full,
-             1, s);
-  const int64_t tail = m - (int64_t)full * rows;
-  if (tail > 0)
-    gemm_f64(true, false, d, d, tail, 1.0, SA + (int64_t)full * rows * ldsa, ldsa, 0, SA + (int64_t)full * rows * ldsa,
-             ldsa, 0, 0.0, part + (int64_t)full * dp * dp, dp, 0, 1, 1, s);
-  const int used = full + (tail > 0 ? 1 : 0);
-  hipLaunchKernelGGL(gram_reduce_kernel<double>, dim3((unsigned)ceil_div(dp * dp, 256)), dim3(256), 0, s, part, used, d,
-                     dp, nu2, lam, G);
+  if (d >= 128) {
+    const int64_t nt = ceil_div(d, 128);
+    const int vec = ((uintptr_t)SA % 16 == 0) && ldsa % 2 == 0;
+    dim3 grid((unsigned)splits, (unsigned)(nt * (nt + 1) / 2));
+    hipLaunchKernelGGL((gemm_kernel<double, true, false, 128, 128, 16, 1>), grid, dim3(256), 0, s, d, d, m, 1.0, SA,
+                       ldsa, rows * ldsa, SA, ldsa, rows * ldsa, 0.0, part, dp, dp * dp, 1, vec, rows);
+    AES_LAUNCH_CHECK();
+  } else {
+    const int full = (int)(m / rows);
+    if (full > 0)
+      gemm_f64(true, false, d, d, rows, 1.0, SA, ldsa, rows * ldsa, SA, ldsa, rows * ldsa, 0.0, part, dp, dp * dp,
+               full, 1, s);
+    const int64_t tail = m - (int64_t)full * rows;
+    if (tail > 0)
+      gemm_f64(true, false, d, d, tail, 1.0, SA + (int64_t)full * rows * ldsa, ldsa, 0,
+               SA + (int64_t)full * rows * ldsa, ldsa, 0, 0.0, part + (int64_t)full * dp * dp, dp, 0, 1, 1, s);
+    splits = full + (tail > 0 ? 1 : 0);
+  }
+  hipLaunchKernelGGL(gram_reduce_kernel<double>, dim3((unsigned)ceil_div(dp * dp, 256)), dim3(256), 0, s, part, splits,
+                     d, dp, nu2, lam, G);
   AES_LAUNCH_CHECK();
 }
 
@@ -630,7 +672,7 @@ __global__ void copy_block_kernel(int64_t rows, int64_t cols, const double* __re
   dst[i * ldd + j] = src[i * lds + j];
 }
 
-static void cholinv_rec(double* G, double* X, int64_t ld, int64_t o, int64_t h, double* tmp, int* flag,
+static void cholinv_rec(double* G, double* X, int64_t ld, int64_t o, int64_t h, double* tmp, int* flag, bool keep_l,
                         hipStream_t s) {
   if (h == 64) {
     hipLaunchKernelGGL(chol_inv_leaf_kernel, dim3(1), dim3(128), 0, s, G + o * ld + o, ld, X + o * ld + o, ld, flag);
@@ -639,7 +681,7 @@ static void cholinv_rec(double* G, double* X, int64_t ld, int64_t o, int64_t h, 
   }
   const int64_t nb = h / 64;
   const int64_t h1 = 64 * ((nb + 1) / 2), h2 = h - h1;
-  cholinv_rec(G, X, ld, o, h1, tmp, flag, s);
+  cholinv_rec(G, X, ld, o, h1, tmp, flag, keep_l, s);
   double* A21 = G + (o + h1) * ld + o;
   double* A22 = G + (o + h1) * ld + (o + h1);
   const double* X11 = X + o * ld + o;
@@ -647,14 +689,16 @@ static void cholinv_rec(double* G, double* X, int64_t ld, int64_t o, int64_t h, 
   double* T2 = tmp + h2 * h1;   // h2 x h1: L21 X11
   // L21 = A21 X11^T
   gemm_f64(false, true, h2, h1, h1, 1.0, A21, ld, 0, X11, ld, 0, 0.0, T1, h1, 0, 1, 0, s);
-  hipLaunchKernelGGL(copy_block_kernel, dim3((unsigned)ceil_div(h2 * h1, 256)), dim3(256), 0, s, h2, h1, T1, h1, A21,
-                     ld);
-  AES_LAUNCH_CHECK();
+  if (keep_l) {
+    hipLaunchKernelGGL(copy_block_kernel, dim3((unsigned)ceil_div(h2 * h1, 256)), dim3(256), 0, s, h2, h1, T1, h1, A21,
+                       ld);
+    AES_LAUNCH_CHECK();
+  }
   // S = A22 - L21 L21^T (lower)
   gemm_f64(false, true, h2, h2, h1, -1.0, T1, h1, 0, T1, h1, 0, 1.0, A22, ld, 0, 1, 1, s);
   // T2 = L21 X11
   gemm_f64(false, false, h2, h1, h1, 1.0, T1, h1, 0, X11, ld, 0, 0.0, T2, h1, 0, 1, 0, s);
-  cholinv_rec(G, X, ld, o + h1, h2, tmp + 2 * h2 * h1, flag, s);
+  cholinv_rec(G, X, ld, o + h1, h2, tmp + 2 * h2 * h1, flag, keep_l, s);
   // X21 = -X22 T2
   gemm_f64(false, false, h2, h1, h2, -1.0, X + (o + h1) * ld + (o + h1), ld, 0, T2, h1, 0, 0.0, X + (o + h1) * ld + o,
            ld, 0, 1, 0, s);
@@ -662,9 +706,9 @@ static void cholinv_rec(double* G, double* X, int64_t ld, int64_t o, int64_t h, 
 
 size_t cholinv_tmp_size(int64_t np) { return (size_t)np * np; }
 
-void cholinv(double* G, int64_t np, double* Linv, double* tmp, int* flag, hipStream_t s) {
+void cholinv(double* G, int64_t np, double* Linv, double* tmp, int* flag, bool keep_l, hipStream_t s) {
   launch_fill(Linv, np * np, 0.0, s);
-  cholinv_rec(G, Linv, np, 0, np, tmp, flag, s);
+  cholinv_rec(G, Linv, np, 0, np, tmp, flag, keep_l, s);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -123,11 +123,12 @@ void gram_nt(int64_t m, int64_t d, const double* SA, int64_t ldsa, double nu2, c
              double* scaled, double* W, int64_t mp, hipStream_t s);
 void gram_nt_bf16(int64_t m, int64_t d, const __hip_bfloat16* SA, int64_t ldsa, double nu2,
                   const double* invlam, double* sa64, double* scaled, double* W, int64_t mp, hipStream_t s);
-// Lower Cholesky factor of G (np x np, np % 64 == 0, lower triangle read), written in place
-// (upper triangle zeroed), and Linv = L^{-1}; *flag != 0 on a non-positive or NaN pivot.
+// Linv = L^{-1} for the lower Cholesky factor L of G (np x np, np % 64 == 0, lower triangle
+// read); *flag != 0 on a non-positive or NaN pivot.  keep_l: L is written over G (upper
+// triangle zeroed); otherwise G holds only the diagonal blocks of L afterwards.
 // tmp: cholinv_tmp_size(np) doubles.
 size_t cholinv_tmp_size(int64_t np);
-void cholinv(double* G, int64_t np, double* Linv, double* tmp, int* flag, hipStream_t s);
+void cholinv(double* G, int64_t np, double* Linv, double* tmp, int* flag, bool keep_l, hipStream_t s);
 
 // ---- adjoint (k_vec.hip) ------------------------------------------------------------------
 // dA[i, j] = -(z1[i] * y2[j] + z2[i] * y1[j]) with z1 = A y1, z2 = A y2 computed in-kernel.
