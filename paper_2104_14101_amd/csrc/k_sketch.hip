@@ -278,12 +278,45 @@ __device__ __forceinline__ void wht_group(TACC* tile, int R, int g, int tid) {
   }
 }
 
+// Radix-2^NB butterflies over v[q] at runtime NB (1..3), in the fixed bit order h = 1, 2, 4.
+template <typename VT>
+__device__ __forceinline__ void wht_reg_n(VT (&v)[8], int nb) {
+  if (nb == 3) {
+#pragma unroll
+    for (int h = 1; h < 8; h <<= 1)
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if ((q & h) == 0) {
+          const VT x = v[q], y = v[q | h];
+          v[q] = x + y;
+          v[q | h] = x - y;
+        }
+  } else if (nb == 2) {
+#pragma unroll
+    for (int h = 1; h < 4; h <<= 1)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if ((q & h) == 0) {
+          const VT x = v[q], y = v[q | h];
+          v[q] = x + y;
+          v[q | h] = x - y;
+        }
+  } else if (nb == 1) {
+    const VT x = v[0], y = v[1];
+    v[0] = x + y;
+    v[1] = x - y;
+  }
+}
+
 // One WHT pass over index bits [s, s+b).  MODE: 0 first pass (src = A with signs, rows >= n
 // are zero, dst = Y; tiles past n are skipped), 1 middle pass (Y -> Y), 2 last pass (Y -> SA,
 // rows selected by pos, scale), 3 single pass (A -> SA).
 // zero_bits > 0 (middle/last pass directly after the first): rows whose first-pass tile starts
 // at or beyond n are known zero and not read.
-// Loads and stores move VW consecutive columns (16 bytes of the accumulation type) per thread.
+// A thread moves VW consecutive columns (16 bytes of the accumulation type) of 2^nf rows: the
+// lowest nf <= 3 tile bits are transformed in registers right after the loads, the highest
+// nl <= 3 bits in registers right before the stores, and only the bits between take LDS
+// round trips (3 bits each).
 template <typename TIN, typename TY, typename TOUT, int CW, int MODE>
 __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A, const TY* __restrict__ Ysrc,
                                                        TY* __restrict__ Ydst, TOUT* __restrict__ SA, int64_t ldsa,
@@ -294,10 +327,14 @@ __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A
   using TACC = typename AccOf<TY>::type;
   constexpr int VW = 16 / sizeof(TACC);  // columns per vector access
   constexpr int TPR = CW / VW;           // threads per row segment
+  typedef TACC VT __attribute__((ext_vector_type(VW)));
   extern __shared__ unsigned char smem_raw[];
   TACC* tile = reinterpret_cast<TACC*>(smem_raw);
   const int tid = threadIdx.x;
   const int R = 1 << b;
+  const int nf = b < 3 ? b : 3;
+  const int nl = (b - nf) < 3 ? (b - nf) : 3;
+  const int GF = 1 << nf, GL = 1 << nl;
   // column block fastest: concurrently resident workgroups cover whole rows of A / Y
   const int64_t tile_id = blockIdx.y;
   const int64_t lo = tile_id & ((1ll << s) - 1);
@@ -323,105 +360,124 @@ __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A
   }
   const bool vec_in =
       ((d % VW) == 0) && (!FIRST || ((lda % VW) == 0 && sizeof(TIN) == sizeof(TACC) && a_aligned));
-  typedef TACC VT __attribute__((ext_vector_type(VW)));
-  if (vec_in) {
-    // Batches of kLoadBatch independent 16-byte loads per thread are issued before any of them
-    // is consumed, so that a workgroup keeps its whole tile in flight.
-    constexpr int kLoadBatch = 16;
-    for (int i0 = 0; i0 < R * TPR; i0 += 256 * kLoadBatch) {
-      VT u[kLoadBatch];
-      TACC sg[kLoadBatch];
+  // ---- load + first nf bits: unit u = (row group jg of GF rows, column vector) --------------
+  // All loads of a batch (2 units x 8 rows of 16 bytes, with their signs) are issued before
+  // any of them is consumed, so that a workgroup keeps its tile in flight.
+  const int units_in = (R / GF) * TPR;
+  for (int u0 = 0; u0 < units_in; u0 += 256 * 2) {
+    VT v[2][8];
+    TACC sg[2][8];
+    if (vec_in) {
 #pragma unroll
-      for (int q = 0; q < kLoadBatch; ++q) {
-        const int idx = i0 + tid + 256 * q;
-        const int j = idx / TPR, cv = (idx % TPR) * VW;
-        const int64_t row = base + ((int64_t)j << s);
+      for (int w = 0; w < 2; ++w) {
+        const int u = u0 + tid + 256 * w;
+        const int cv = (u % TPR) * VW, j0 = (u / TPR) * GF;
         const int64_t col = c0 + cv;
-        bool load = idx < R * TPR && col < d;
-        if (FIRST) load = load && row < n;
-        else load = load && !(zero_bits > 0 && ((row >> zero_bits) << zero_bits) >= n);
-        sg[q] = TACC(1);
-        if (load) {
-          if (FIRST) {
-            u[q] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(reinterpret_cast<const TACC*>(A) + row * lda + col));
-            sg[q] = (TACC)eps[row];
-          } else {
-            u[q] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(Ysrc + row * d + col));
-          }
-        } else {
 #pragma unroll
-          for (int e = 0; e < VW; ++e) u[q][e] = TACC(0);
+        for (int q = 0; q < 8; ++q) {
+          const int64_t row = base + ((int64_t)(j0 + q) << s);
+          bool load = q < GF && u < units_in && col < d;
+          if (FIRST) load = load && row < n;
+          else load = load && !(zero_bits > 0 && ((row >> zero_bits) << zero_bits) >= n);
+          sg[w][q] = TACC(1);
+          if (load) {
+            if (FIRST) {
+              v[w][q] = __builtin_nontemporal_load(
+                  reinterpret_cast<const VT*>(reinterpret_cast<const TACC*>(A) + row * lda + col));
+              sg[w][q] = (TACC)eps[row];
+            } else {
+              v[w][q] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(Ysrc + row * d + col));
+            }
+          } else {
+#pragma unroll
+            for (int e = 0; e < VW; ++e) v[w][q][e] = TACC(0);
+          }
         }
       }
+    } else {
 #pragma unroll
-      for (int q = 0; q < kLoadBatch; ++q) {
-        const int idx = i0 + tid + 256 * q;
-        if (idx < R * TPR) {
-          const int j = idx / TPR, cv = (idx % TPR) * VW;
+      for (int w = 0; w < 2; ++w) {
+        const int u = u0 + tid + 256 * w;
+        const int cv = (u % TPR) * VW, j0 = (u / TPR) * GF;
+        const int64_t col = c0 + cv;
+        for (int q = 0; q < 8; ++q) {
+          const int64_t row = base + ((int64_t)(j0 + q) << s);
+          bool load = q < GF && u < units_in;
+          if (FIRST) load = load && row < n;
+          else load = load && !(zero_bits > 0 && ((row >> zero_bits) << zero_bits) >= n);
+          sg[w][q] = TACC(1);
 #pragma unroll
-          for (int e = 0; e < VW; ++e) tile[j * CW + cv + e] = FIRST ? u[q][e] * sg[q] : u[q][e];
+          for (int e = 0; e < VW; ++e) {
+            TACC x = TACC(0);
+            if (load && col + e < d) x = FIRST ? cvt<TACC>(A[row * lda + col + e]) : (TACC)Ysrc[row * d + col + e];
+            v[w][q][e] = x;
+          }
+          if (FIRST && load) sg[w][q] = (TACC)eps[row];
         }
       }
     }
-  } else {
-    for (int idx = tid; idx < R * TPR; idx += 256) {
-      const int j = idx / TPR, cv = (idx % TPR) * VW;
-      const int64_t row = base + ((int64_t)j << s);
-      const int64_t col = c0 + cv;
-      TACC v[VW];
 #pragma unroll
-      for (int e = 0; e < VW; ++e) v[e] = 0;
-      bool load = col < d;
-      const TACC sg = FIRST ? (TACC)(row < n ? eps[row] : 0.0) : TACC(1);
-      if (FIRST) load = load && row < n;
-      else load = load && !(zero_bits > 0 && ((row >> zero_bits) << zero_bits) >= n);
-      if (load) {
+    for (int w = 0; w < 2; ++w) {
+      const int u = u0 + tid + 256 * w;
+      if (u >= units_in) continue;
+      if (FIRST) {
 #pragma unroll
-        for (int e = 0; e < VW; ++e)
-          if (col + e < d) v[e] = FIRST ? cvt<TACC>(A[row * lda + col + e]) * sg : (TACC)Ysrc[row * d + col + e];
+        for (int q = 0; q < 8; ++q) v[w][q] = v[w][q] * sg[w][q];
       }
+      wht_reg_n(v[w], nf);
+      const int cv = (u % TPR) * VW, j0 = (u / TPR) * GF;
 #pragma unroll
-      for (int e = 0; e < VW; ++e) tile[j * CW + cv + e] = v[e];
+      for (int q = 0; q < 8; ++q)
+        if (q < GF) *reinterpret_cast<VT*>(&tile[(j0 + q) * CW + cv]) = v[w][q];
     }
   }
   __syncthreads();
-  for (int g = 0; g < b; g += 3) {
-    const int nb = (b - g) >= 3 ? 3 : (b - g);
+  // ---- middle bits in LDS ---------------------------------------------------------------------
+  for (int g = nf; g < b - nl; g += 3) {
+    const int nb = (b - nl - g) >= 3 ? 3 : (b - nl - g);
     if (nb == 3) wht_group<TACC, 3, CW>(tile, R, g, tid);
     else if (nb == 2) wht_group<TACC, 2, CW>(tile, R, g, tid);
     else wht_group<TACC, 1, CW>(tile, R, g, tid);
     __syncthreads();
   }
-  // store
-  for (int idx = tid; idx < R * TPR; idx += 256) {
-    const int j = idx / TPR, cv = (idx % TPR) * VW;
-    const int64_t row = base + ((int64_t)j << s);
+  // ---- last nl bits + store: unit u = (row jl below bit b - nl, column vector) ---------------
+  const int rl = R / GL;  // rows jl + q * rl, q < GL, form one group
+  const int units_out = rl * TPR;
+  for (int u = tid; u < units_out; u += 256) {
+    const int cv = (u % TPR) * VW, jl = u / TPR;
     const int64_t col = c0 + cv;
+    VT v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (q < GL) v[q] = *reinterpret_cast<const VT*>(&tile[(jl + q * rl) * CW + cv]);
+    wht_reg_n(v, nl);
     if (col >= d) continue;
-    if (LAST) {
-      const int32_t pr = rowflag[j];
-      if (pr < 0) continue;
 #pragma unroll
-      for (int e = 0; e < VW; ++e)
-        if (col + e < d) {
-          const TACC v = tile[j * CW + cv + e];
-          if constexpr (sizeof(TACC) == 8)
-            SA[(int64_t)pr * ldsa + col + e] = (TOUT)(v * scale);
-          else
-            SA[(int64_t)pr * ldsa + col + e] = cvt<TOUT>((float)(v * (float)scale));
+    for (int q = 0; q < 8; ++q) {
+      if (q >= GL) continue;
+      const int j = jl + q * rl;
+      const int64_t row = base + ((int64_t)j << s);
+      if (LAST) {
+        const int32_t pr = rowflag[j];
+        if (pr < 0) continue;
+#pragma unroll
+        for (int e = 0; e < VW; ++e)
+          if (col + e < d) {
+            if constexpr (sizeof(TACC) == 8)
+              SA[(int64_t)pr * ldsa + col + e] = (TOUT)(v[q][e] * scale);
+            else
+              SA[(int64_t)pr * ldsa + col + e] = cvt<TOUT>((float)(v[q][e] * (float)scale));
+          }
+      } else {
+        if (MODE == 0 && need && !rowflag[j]) continue;  // no sampled row has these low index bits
+        if ((d % VW) == 0) {
+          __builtin_nontemporal_store(v[q], reinterpret_cast<VT*>(Ydst + row * d + col));
+        } else {
+#pragma unroll
+          for (int e = 0; e < VW; ++e)
+            if (col + e < d) Ydst[row * d + col + e] = (TY)v[q][e];
         }
-    } else if (MODE == 0 && need && !rowflag[j]) {
-      continue;  // first pass of a two-pass transform: no sampled row has these low index bits
-    } else if ((d % VW) == 0 && col + VW <= d) {
-      typedef TACC VT __attribute__((ext_vector_type(VW)));
-      VT u;
-#pragma unroll
-      for (int e = 0; e < VW; ++e) u[e] = tile[j * CW + cv + e];
-      __builtin_nontemporal_store(u, reinterpret_cast<VT*>(Ydst + row * d + col));
-    } else {
-#pragma unroll
-      for (int e = 0; e < VW; ++e)
-        if (col + e < d) Ydst[row * d + col + e] = (TY)tile[j * CW + cv + e];
+      }
     }
   }
 }
