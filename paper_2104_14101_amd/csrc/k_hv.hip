@@ -182,23 +182,37 @@ void launch_hv_fused<float>(const float* A, int64_t n, int64_t d, int64_t lda, c
 }
 
 // out[j, c] = sgn * (sum_w part[w][j][c] + nu2 * lam[j] * v[j, c]) + bsgn * b[j, c]
-// 256 threads = 32 (j,c)-elements x 8 partial groups; groups combined in a fixed order.
+// 256 threads = 16 (j,c)-elements x 16 partial groups; a thread keeps 8 loads in flight and
+// the groups are combined in a fixed order (deterministic).
 template <typename TP>
 __global__ __launch_bounds__(256) void hv_colsum_kernel(const TP* __restrict__ part, int nwg, int64_t total,
                                                         int C, const double* __restrict__ v,
                                                         const double* __restrict__ lam, double nu2, double sgn,
                                                         const double* __restrict__ b, double bsgn,
                                                         double* __restrict__ out) {
-  __shared__ double sh[8][33];
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  const int64_t e = (int64_t)blockIdx.x * 32 + tx;
-  double acc = 0.0;
-  if (e < total)
-    for (int w = ty; w < nwg; w += 8) acc += (double)part[(int64_t)w * total + e];
-  sh[ty][tx] = acc;
+  __shared__ double sh[16][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int64_t e = (int64_t)blockIdx.x * 16 + tx;
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (e < total) {
+    int w = ty;
+    for (; w + 16 * 7 < nwg; w += 16 * 8) {
+      TP x[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) x[k] = part[(int64_t)(w + 16 * k) * total + e];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) a[k] += (double)x[k];
+    }
+    for (; w < nwg; w += 16) a[0] += (double)part[(int64_t)w * total + e];
+  }
+  sh[ty][tx] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   __syncthreads();
+  for (int st = 8; st >= 1; st >>= 1) {
+    if (ty < st) sh[ty][tx] += sh[ty + st][tx];
+    __syncthreads();
+  }
   if (ty == 0 && e < total) {
-    double sum = ((sh[0][tx] + sh[1][tx]) + (sh[2][tx] + sh[3][tx])) + ((sh[4][tx] + sh[5][tx]) + (sh[6][tx] + sh[7][tx]));
+    const double sum = sh[0][tx];
     const int64_t j = e / C;
     const double lj = lam ? lam[j] : 1.0;
     double val = sgn * (sum + nu2 * lj * v[e]);
@@ -210,7 +224,7 @@ __global__ __launch_bounds__(256) void hv_colsum_kernel(const TP* __restrict__ p
 void launch_hv_colsum(const double* part, int nwg, int64_t d, int C, const double* v, const double* lam, double nu2,
                       double sgn, const double* b, double bsgn, double* out, hipStream_t s) {
   const int64_t total = d * C;
-  hipLaunchKernelGGL(hv_colsum_kernel<double>, dim3((unsigned)ceil_div(total, 32)), dim3(256), 0, s, part, nwg, total, C,
+  hipLaunchKernelGGL(hv_colsum_kernel<double>, dim3((unsigned)ceil_div(total, 16)), dim3(256), 0, s, part, nwg, total, C,
                      v, lam, nu2, sgn, b, bsgn, out);
   AES_LAUNCH_CHECK();
 }
@@ -218,7 +232,7 @@ void launch_hv_colsum(const double* part, int nwg, int64_t d, int C, const doubl
 void launch_hv_colsum_f32(const float* part, int nwg, int64_t d, int C, const double* v, const double* lam, double nu2,
                           double sgn, const double* b, double bsgn, double* out, hipStream_t s) {
   const int64_t total = d * C;
-  hipLaunchKernelGGL(hv_colsum_kernel<float>, dim3((unsigned)ceil_div(total, 32)), dim3(256), 0, s, part, nwg, total, C,
+  hipLaunchKernelGGL(hv_colsum_kernel<float>, dim3((unsigned)ceil_div(total, 16)), dim3(256), 0, s, part, nwg, total, C,
                      v, lam, nu2, sgn, b, bsgn, out);
   AES_LAUNCH_CHECK();
 }

@@ -315,7 +315,23 @@ __global__ __launch_bounds__(256) void rowdot_kernel(int64_t nrows, int64_t ncol
 #pragma unroll
     for (int c = 0; c < CC; ++c) acc[c] = 0.0;
     const double* Mi = M + i * ldm;
-    for (int64_t j = jlo + lane; j < jhi; j += 64) {
+    int64_t j = jlo + lane;
+    if (CC == 1 && !xs) {
+      // eight loads of the row (and of x) in flight per lane before they are consumed
+      double acc2[4] = {0.0, 0.0, 0.0, 0.0};
+      for (; j + 7 * 64 < jhi; j += 8 * 64) {
+        double mv[8], xv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          mv[k] = Mi[j + 64 * k];
+          xv[k] = x[j + 64 * k];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc2[k & 3] = fma(mv[k], xv[k], acc2[k & 3]);
+      }
+      acc[0] = (acc2[0] + acc2[1]) + (acc2[2] + acc2[3]);
+    }
+    for (; j < jhi; j += 64) {
       double mv = Mi[j];
       if (xs) mv *= xs[j];
 #pragma unroll
