@@ -21,7 +21,8 @@ Extra legs (outside the timed region of the headline value):
   * --adjoint (or --all): forward + backward of the autograd Function on n = 131072, d = 1024
     (sigma_j = j^-1/2, nu = 1e-2), gradients validated against the dense oracle.
 
---hv-only runs just fused H.v launches and a calibration copy (for rocprofv3 counter runs).
+--hv-only runs just fused H.v launches and a calibration copy (for rocprofv3 counter runs);
+--sketch-only M runs just SRHT sketches of size M of the workload's A (WHT traffic counters).
 """
 import argparse
 import hashlib
@@ -146,6 +147,22 @@ def hv_only(args):
     print(json.dumps({"hv_launches": args.steps, "n": w.n, "d": w.d, "copy_bytes_each_way": 2 ** 30}))
 
 
+def sketch_only(args):
+    import torch
+
+    import paper_2104_14101_amd as aes
+    import synth
+
+    w = synth.WORKLOADS[args.workload]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    A = torch.randn((w.n, w.d), dtype=torch.float64, device="cuda", generator=g)
+    for k in range(args.steps):
+        aes.sketch(A, args.sketch_only, kind="srht", seed=1, k=k)
+    torch.cuda.synchronize()
+    print(json.dumps({"sketches": args.steps, "m": args.sketch_only, "n": w.n, "d": w.d}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +174,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--hv-only", action="store_true")
+    ap.add_argument("--sketch-only", type=int, default=0, metavar="M")
     ap.add_argument("--batched", action="store_true")
     ap.add_argument("--adjoint", action="store_true")
     ap.add_argument("--all", action="store_true")
@@ -168,6 +186,8 @@ def main():
         sys.exit(2)
     if args.hv_only:
         return hv_only(args)
+    if args.sketch_only:
+        return sketch_only(args)
 
     import numpy as np
     import torch

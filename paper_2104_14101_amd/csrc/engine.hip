@@ -309,15 +309,15 @@ class Solver {
       sc.blk = B<uint32_t>("sel_blk", 2 * select_blocks(npad_));
       launch_srht_select(o_.seed, o_.problem, k_, npad_, m_, sc, s_);
       if (bf) {
-        float* Y = B<float>("Y32", (size_t)npad_ * d_);
+        float* Y = B<float>("Y32", srht_scratch_elems(npad_, d_));
         launch_srht_apply<__hip_bfloat16, float, __hip_bfloat16>(A16_, n_, d_, d_, eps, npad_, sc.pos, m_, Y, SA16_, d_,
                                                                  B<int32_t>("need", 512), s_);
       } else if (f32) {
-        float* Y = B<float>("Y32", (size_t)npad_ * d_);
+        float* Y = B<float>("Y32", srht_scratch_elems(npad_, d_));
         launch_srht_apply<float, float, float>(A32_, n_, d_, d_, eps, npad_, sc.pos, m_, Y, SA32_, d_,
                                                B<int32_t>("need", 512), s_);
       } else {
-        double* Y = B<double>("Y", (size_t)npad_ * d_);
+        double* Y = B<double>("Y", srht_scratch_elems(npad_, d_));
         launch_srht_apply<double, double, double>(P_.A, n_, d_, P_.lda, eps, npad_, sc.pos, m_, Y, SA_, d_,
                                                   B<int32_t>("need", 512), s_);
       }
@@ -1104,7 +1104,7 @@ aes_status aes_sketch(aes_handle h, void* stream, int kind, int64_t n, int64_t d
       sc.state = h->buf<uint64_t>("sk.state", 4);
       sc.blk = h->buf<uint32_t>("sk.blk", 2 * select_blocks(npad));
       launch_srht_select(seed, problem, k, npad, m, sc, s);
-      double* Y = h->buf<double>("sk.Y", (size_t)npad * d);
+      double* Y = h->buf<double>("sk.Y", srht_scratch_elems(npad, d));
       launch_srht_apply<double, double, double>(A, n, d, lda, eps, npad, sc.pos, m, Y, SA, d,
                                                 h->buf<int32_t>("sk.need", 512), s);
     } else if (kind == AES_GAUSS) {

@@ -323,8 +323,16 @@ __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A
                                                        int64_t n, int64_t d, int64_t lda, int64_t npad, int s, int b,
                                                        int zero_bits, const double* __restrict__ eps,
                                                        const int32_t* __restrict__ pos, double scale,
-                                                       int a_aligned, const int32_t* __restrict__ need) {
+                                                       int a_aligned, const int32_t* __restrict__ need,
+                                                       int check_tiles, int pw) {
   using TACC = typename AccOf<TY>::type;
+  // Y is stored in column panels of pw columns: element (row, col) at
+  // (col / pw) * npad * pw + row * pw + col % pw, so that the strided tiles of the later passes
+  // read rows of one panel rather than rows n' * 8 bytes apart
+  const int pws = __builtin_ctz((unsigned)pw);  // pw is a power of two
+  auto ypos = [&](int64_t row, int64_t col) {
+    return (((col >> pws) * npad + row) << pws) + (col & (int64_t)(pw - 1));
+  };
   constexpr int VW = 16 / sizeof(TACC);  // columns per vector access
   constexpr int TPR = CW / VW;           // threads per row segment
   typedef TACC VT __attribute__((ext_vector_type(VW)));
@@ -347,7 +355,11 @@ __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A
   if (MODE == 0 && base >= n) return;  // all-padding tile: implicit zeros
   // per-row flags of the tile kept in LDS: output row (last pass) or "needed" (pruned first pass)
   __shared__ int32_t rowflag[1 << kMaxTileBits];
-  if (LAST) {
+  // last pass: with a sparse sample (check_tiles) the tile's rows are looked up first and a
+  // tile without a selected row is skipped; with a dense one every tile has selected rows and
+  // the lookups travel with the data loads (R <= 512: two rows per thread)
+  int32_t pf0 = -1, pf1 = -1;
+  if (LAST && check_tiles) {
     int found = 0;
     for (int j = tid; j < R; j += 256) {
       const int32_t pr = pos[base + ((int64_t)j << s)];
@@ -355,6 +367,9 @@ __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A
       found |= pr >= 0;
     }
     if (!__syncthreads_or(found)) return;  // no selected row in this tile
+  } else if (LAST) {
+    if (tid < R) pf0 = pos[base + ((int64_t)tid << s)];
+    if (tid + 256 < R) pf1 = pos[base + ((int64_t)(tid + 256) << s)];
   } else if (MODE == 0 && need) {
     for (int j = tid; j < R; j += 256) rowflag[j] = need[j];
   }
@@ -386,7 +401,7 @@ __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A
                   reinterpret_cast<const VT*>(reinterpret_cast<const TACC*>(A) + row * lda + col));
               sg[w][q] = (TACC)eps[row];
             } else {
-              v[w][q] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(Ysrc + row * d + col));
+              v[w][q] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(Ysrc + ypos(row, col)));
             }
           } else {
 #pragma unroll
@@ -409,7 +424,7 @@ __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A
 #pragma unroll
           for (int e = 0; e < VW; ++e) {
             TACC x = TACC(0);
-            if (load && col + e < d) x = FIRST ? cvt<TACC>(A[row * lda + col + e]) : (TACC)Ysrc[row * d + col + e];
+            if (load && col + e < d) x = FIRST ? cvt<TACC>(A[row * lda + col + e]) : (TACC)Ysrc[ypos(row, col + e)];
             v[w][q][e] = x;
           }
           if (FIRST && load) sg[w][q] = (TACC)eps[row];
@@ -430,6 +445,10 @@ __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A
       for (int q = 0; q < 8; ++q)
         if (q < GF) *reinterpret_cast<VT*>(&tile[(j0 + q) * CW + cv]) = v[w][q];
     }
+  }
+  if (LAST && !check_tiles) {
+    if (tid < R) rowflag[tid] = pf0;
+    if (tid + 256 < R) rowflag[tid + 256] = pf1;
   }
   __syncthreads();
   // ---- middle bits in LDS ---------------------------------------------------------------------
@@ -471,11 +490,11 @@ __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A
       } else {
         if (MODE == 0 && need && !rowflag[j]) continue;  // no sampled row has these low index bits
         if ((d % VW) == 0) {
-          __builtin_nontemporal_store(v[q], reinterpret_cast<VT*>(Ydst + row * d + col));
+          __builtin_nontemporal_store(v[q], reinterpret_cast<VT*>(Ydst + ypos(row, col)));
         } else {
 #pragma unroll
           for (int e = 0; e < VW; ++e)
-            if (col + e < d) Ydst[row * d + col + e] = (TY)v[q][e];
+            if (col + e < d) Ydst[ypos(row, col + e)] = (TY)v[q][e];
         }
       }
     }
@@ -485,11 +504,12 @@ __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A
 template <typename TIN, typename TY, typename TOUT, int CW, int MODE>
 static void wht_launch_cw(int64_t npad, size_t shmem, hipStream_t st, const TIN* A, const TY* Ysrc, TY* Ydst, TOUT* SA,
                           int64_t ldsa, int64_t n, int64_t d, int64_t lda, int s, int b, int zero_bits,
-                          const double* eps, const int32_t* pos, double scale, const int32_t* need) {
+                          const double* eps, const int32_t* pos, double scale, const int32_t* need,
+                          int check_tiles, int pw) {
   const int a_aligned = ((uintptr_t)A % 16) == 0;
   const dim3 grid((unsigned)ceil_div(d, CW), (unsigned)(npad >> b));
   hipLaunchKernelGGL((wht_pass_kernel<TIN, TY, TOUT, CW, MODE>), grid, dim3(256), shmem, st, A, Ysrc, Ydst, SA, ldsa, n,
-                     d, lda, npad, s, b, zero_bits, eps, pos, scale, a_aligned, need);
+                     d, lda, npad, s, b, zero_bits, eps, pos, scale, a_aligned, need, check_tiles, pw);
   AES_LAUNCH_CHECK();
 }
 
@@ -498,16 +518,20 @@ static void wht_launch_cw(int64_t npad, size_t shmem, hipStream_t st, const TIN*
 template <typename TIN, typename TY, typename TOUT, int MODE>
 static void wht_launch(int64_t npad, hipStream_t st, const TIN* A, const TY* Ysrc, TY* Ydst, TOUT* SA, int64_t ldsa,
                        int64_t n, int64_t d, int64_t lda, int s, int b, int zero_bits, const double* eps,
-                       const int32_t* pos, double scale, const int32_t* need) {
+                       const int32_t* pos, double scale, const int32_t* need, int check_tiles, int pw) {
   using TACC = typename AccOf<TY>::type;
   constexpr int CW_WIDE = 256 / sizeof(TACC), CW_NARROW = 128 / sizeof(TACC);
   if (b <= 8)
     wht_launch_cw<TIN, TY, TOUT, CW_WIDE, MODE>(npad, (size_t)(1 << b) * CW_WIDE * sizeof(TACC), st, A, Ysrc, Ydst, SA,
-                                                ldsa, n, d, lda, s, b, zero_bits, eps, pos, scale, need);
+                                                ldsa, n, d, lda, s, b, zero_bits, eps, pos, scale, need, check_tiles,
+                                                pw);
   else
     wht_launch_cw<TIN, TY, TOUT, CW_NARROW, MODE>(npad, (size_t)(1 << b) * CW_NARROW * sizeof(TACC), st, A, Ysrc, Ydst,
-                                                  SA, ldsa, n, d, lda, s, b, zero_bits, eps, pos, scale, need);
+                                                  SA, ldsa, n, d, lda, s, b, zero_bits, eps, pos, scale, need,
+                                                  check_tiles, pw);
 }
+
+size_t srht_scratch_elems(int64_t npad, int64_t d) { return (size_t)npad * (size_t)round_up(d, 64); }
 
 // need[j] = 1 if some sampled padded row has low index bits j (j < R0).
 __global__ void need_mask_kernel(const int32_t* __restrict__ pos, int64_t npad, int R0, int32_t* __restrict__ need) {
@@ -528,6 +552,13 @@ void launch_srht_apply(const TIN* A, int64_t n, int64_t d, int64_t lda, const do
   constexpr int kBits = 9;  // at most 9 index bits per pass
   const int passes = L == 0 ? 1 : (L + kBits - 1) / kBits;
   const double scale = 1.0 / std::sqrt((double)m);
+  // a tile of the last pass has 2^b rows; with at least 16 sampled rows per 1024 padded rows
+  // (m >= n'/64) empty tiles are rare enough that checking for them costs more than it saves
+  const int check_tiles = m * 64 < npad;
+  // panel width of Y: the column block of the narrowest pass (passes have at most 8 bits
+  // unless L > 16)
+  using TACC = typename AccOf<TY>::type;
+  const int pw = (passes > 1 && (L + passes - 1) / passes > 8) ? 128 / (int)sizeof(TACC) : 256 / (int)sizeof(TACC);
   int s = 0;
   int first_bits = 0;
   for (int p = 0; p < passes; ++p) {
@@ -537,7 +568,7 @@ void launch_srht_apply(const TIN* A, int64_t n, int64_t d, int64_t lda, const do
     const int zero_bits = (p == 1) ? first_bits : 0;
     if (passes == 1) {
       wht_launch<TIN, TY, TOUT, 3>(npad, st, A, (const TY*)nullptr, (TY*)nullptr, SA, ldsa, n, d, lda, s, b, 0, eps, pos,
-                                   scale, nullptr);
+                                   scale, nullptr, check_tiles, pw);
     } else if (p == 0) {
       const int32_t* nd = nullptr;
       if (passes == 2 && need && m <= (1ll << b) / 2) {
@@ -549,14 +580,14 @@ void launch_srht_apply(const TIN* A, int64_t n, int64_t d, int64_t lda, const do
         nd = need;
       }
       wht_launch<TIN, TY, TOUT, 0>(npad, st, A, (const TY*)nullptr, Y, SA, ldsa, n, d, lda, s, b, 0, eps, pos, scale,
-                                   nd);
+                                   nd, 0, pw);
       first_bits = b;
     } else if (p == passes - 1) {
       wht_launch<TIN, TY, TOUT, 2>(npad, st, A, (const TY*)Y, (TY*)nullptr, SA, ldsa, n, d, lda, s, b, zero_bits, eps,
-                                   pos, scale, nullptr);
+                                   pos, scale, nullptr, check_tiles, pw);
     } else {
       wht_launch<TIN, TY, TOUT, 1>(npad, st, A, (const TY*)Y, Y, SA, ldsa, n, d, lda, s, b, zero_bits, eps, pos, scale,
-                                   nullptr);
+                                   nullptr, 0, pw);
     }
     s += b;
   }

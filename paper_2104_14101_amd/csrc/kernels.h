@@ -89,7 +89,10 @@ size_t select_blocks(int64_t npad);
 void launch_srht_select(uint64_t seed, int32_t problem, int64_t k, int64_t npad, int64_t m,
                         const SelectScratch& sc, hipStream_t s);
 void launch_signs(uint64_t seed, int32_t problem, int64_t k, int64_t n, double* eps, hipStream_t s);
-// FWHT-based SRHT: SA (m x d, ld d) from A (n x d, lda); Y scratch npad x d of type TY;
+// Elements of the WHT scratch Y for a padded height npad and d columns.
+size_t srht_scratch_elems(int64_t npad, int64_t d);
+// FWHT-based SRHT: SA (m x d, ld d) from A (n x d, lda); Y scratch of srht_scratch_elems
+// elements of type TY;
 // need: scratch of 512 ints (or NULL) for the row pruning of a two-pass transform.
 template <typename TIN, typename TY, typename TOUT>
 void launch_srht_apply(const TIN* A, int64_t n, int64_t d, int64_t lda, const double* eps, int64_t npad,
