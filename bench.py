@@ -179,6 +179,7 @@ def main():
     ap.add_argument("--adjoint", action="store_true")
     ap.add_argument("--all", action="store_true")
     ap.add_argument("--skip-main", action="store_true", help="run only the selected extra legs (profiling)")
+    ap.add_argument("--mixed", action="store_true", help="with --skip-main: the mixed-precision leg")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU sharding of the solver is a design "
@@ -197,6 +198,8 @@ def main():
 
     if args.skip_main:
         out = {}
+        if args.mixed:
+            out["mixed_vs_fp64"] = mixed_leg(aes, torch, synth)
         if args.batched or args.all:
             out["batched"] = batched_leg(aes, torch, synth)
         if args.adjoint or args.all:

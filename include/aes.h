@@ -52,9 +52,9 @@ typedef enum { AES_PCG = 0, AES_IHS = 1 } aes_method;
 typedef enum { AES_SRHT = 0, AES_GAUSS = 1 } aes_sketch_kind;
 typedef enum {
   AES_FP64 = 0,       /* every step in FP64 */
-  AES_MIXED = 1,      /* BF16 SRHT + BF16 MFMA Gram (FP32 accumulation), FP32-stored A for the
-                         PCG matvecs, FP64 Cholesky, FP64 scalars and vectors, FP64 residual
-                         refinement */
+  AES_MIXED = 1,      /* FP32-stored A for the PCG matvecs and the SRHT (FP32 transform, sketch
+                         rounded to BF16), BF16 MFMA Gram (FP32 accumulation), FP64 Cholesky,
+                         FP64 scalars and vectors, FP64 residual refinement */
   AES_MIXED_FP32 = 2  /* as AES_MIXED with an FP32 SRHT and an FP64 MFMA Gram of it (for small
                          nu, where a BF16 sketch or an FP32-accumulated Gram is too coarse) */
 } aes_precision;

@@ -203,13 +203,9 @@ class Solver {
     for (int j = 0; j < c_; ++j) act[j] = 1;
     AES_HIP(hipMemcpyAsync(active_, act.data(), C_ * sizeof(int), hipMemcpyHostToDevice, s_));
     if (mixed_) {
+      // the FP32 copy feeds the inner products and every sketch of the mixed modes
       A32_ = B<float>("A32", (size_t)n_ * d_);
-      if (sketch32_) {
-        launch_cast<float>(n_, d_, P_.A, P_.lda, A32_, s_);
-      } else {
-        A16_ = B<__hip_bfloat16>("A16", (size_t)n_ * d_);
-        launch_cast2(n_, d_, P_.A, P_.lda, A32_, A16_, s_);
-      }
+      launch_cast<float>(n_, d_, P_.A, P_.lda, A32_, s_);
       if (C_ > 1) {
         V32_ = B<float>("V32", (size_t)d_ * C_);
         Z32_ = B<float>("Z32", (size_t)n_ * C_);
@@ -310,8 +306,8 @@ class Solver {
       launch_srht_select(o_.seed, o_.problem, k_, npad_, m_, sc, s_);
       if (bf) {
         float* Y = B<float>("Y32", srht_scratch_elems(npad_, d_));
-        launch_srht_apply<__hip_bfloat16, float, __hip_bfloat16>(A16_, n_, d_, d_, eps, npad_, sc.pos, m_, Y, SA16_, d_,
-                                                                 B<int32_t>("need", 512), s_);
+        launch_srht_apply<float, float, __hip_bfloat16>(A32_, n_, d_, d_, eps, npad_, sc.pos, m_, Y, SA16_, d_,
+                                                        B<int32_t>("need", 512), s_);
       } else if (f32) {
         float* Y = B<float>("Y32", srht_scratch_elems(npad_, d_));
         launch_srht_apply<float, float, float>(A32_, n_, d_, d_, eps, npad_, sc.pos, m_, Y, SA32_, d_,
@@ -716,7 +712,6 @@ class Solver {
   int nwg_ = 1, msplit_ = 1;
   int64_t msplit_rows_ = 1;
   float* A32_ = nullptr;
-  __hip_bfloat16* A16_ = nullptr;
   float *V32_ = nullptr, *Z32_ = nullptr, *part32_ = nullptr, *SA32_ = nullptr;
   bool sketch32_ = false;
   double* pinned_ = nullptr;

@@ -169,7 +169,7 @@ void launch_hv_fused<float>(const float* A, int64_t n, int64_t d, int64_t lda, c
   if (v4) {
     if (d <= 1024) return hv_launch_cfg<float, 4, 1, 8>(A, n, d, lda, v, part, spart, nwg, s);
     if (d <= 2048) return hv_launch_cfg<float, 4, 2, 8>(A, n, d, lda, v, part, spart, nwg, s);
-    if (d <= 4096) return hv_launch_cfg<float, 4, 4, 2>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 4096) return hv_launch_cfg<float, 4, 4, 4>(A, n, d, lda, v, part, spart, nwg, s);
     if (d <= 8192) return hv_launch_cfg<float, 4, 8, 1>(A, n, d, lda, v, part, spart, nwg, s);
   } else {
     if (d <= 256) return hv_launch_cfg<float, 1, 1, 16>(A, n, d, lda, v, part, spart, nwg, s);

@@ -263,18 +263,29 @@ __device__ __forceinline__ void wht_reg(TACC (&v)[1 << NB]) {
 
 template <typename TACC, int NB, int CW>
 __device__ __forceinline__ void wht_group(TACC* tile, int R, int g, int tid) {
-  // units: (R >> NB) index groups x CW columns
-  const int units = (R >> NB) * CW;
+  // units: (R >> NB) index groups x (CW / VW) column vectors of 16 bytes
+  constexpr int VW = 16 / sizeof(TACC);
+  typedef TACC VT __attribute__((ext_vector_type(VW)));
+  constexpr int CV = CW / VW;
+  const int units = (R >> NB) * CV;
   for (int u = tid; u < units; u += 256) {
-    const int c = u % CW;
-    const int jj = u / CW;
+    const int c = (u % CV) * VW;
+    const int jj = u / CV;
     const int j0 = ((jj >> g) << (g + NB)) | (jj & ((1 << g) - 1));
-    TACC v[1 << NB];
+    VT v[1 << NB];
 #pragma unroll
-    for (int q = 0; q < (1 << NB); ++q) v[q] = tile[(j0 + (q << g)) * CW + c];
-    wht_reg<TACC, NB>(v);
+    for (int q = 0; q < (1 << NB); ++q) v[q] = *reinterpret_cast<const VT*>(&tile[(j0 + (q << g)) * CW + c]);
 #pragma unroll
-    for (int q = 0; q < (1 << NB); ++q) tile[(j0 + (q << g)) * CW + c] = v[q];
+    for (int h = 1; h < (1 << NB); h <<= 1)
+#pragma unroll
+      for (int q = 0; q < (1 << NB); ++q)
+        if ((q & h) == 0) {
+          const VT x = v[q], y = v[q | h];
+          v[q] = x + y;
+          v[q | h] = x - y;
+        }
+#pragma unroll
+    for (int q = 0; q < (1 << NB); ++q) *reinterpret_cast<VT*>(&tile[(j0 + (q << g)) * CW + c]) = v[q];
   }
 }
 
@@ -599,9 +610,8 @@ template void launch_srht_apply<double, double, double>(const double*, int64_t, 
 template void launch_srht_apply<float, float, float>(const float*, int64_t, int64_t, int64_t, const double*, int64_t,
                                                      const int32_t*, int64_t, float*, float*, int64_t, int32_t*,
                                                      hipStream_t);
-template void launch_srht_apply<__hip_bfloat16, float, __hip_bfloat16>(const __hip_bfloat16*, int64_t, int64_t, int64_t,
-                                                                       const double*, int64_t, const int32_t*, int64_t,
-                                                                       float*, __hip_bfloat16*, int64_t, int32_t*,
-                                                                       hipStream_t);
+template void launch_srht_apply<float, float, __hip_bfloat16>(const float*, int64_t, int64_t, int64_t, const double*,
+                                                              int64_t, const int32_t*, int64_t, float*, __hip_bfloat16*,
+                                                              int64_t, int32_t*, hipStream_t);
 
 }  // namespace aes

@@ -446,21 +446,6 @@ void launch_cast(int64_t n, int64_t d, const double* A, int64_t lda, TO* out, hi
 }
 template void launch_cast<float>(int64_t, int64_t, const double*, int64_t, float*, hipStream_t);
 
-// One read of A (FP64), two outputs: FP32 and BF16 copies (round to nearest even).
-__global__ void cast2_kernel(int64_t n, int64_t d, const double* __restrict__ A, int64_t lda, float* __restrict__ a32,
-                             __hip_bfloat16* __restrict__ a16) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * d) return;
-  const double v = A[(e / d) * lda + (e % d)];
-  a32[e] = (float)v;
-  a16[e] = __float2bfloat16((float)v);
-}
-
-void launch_cast2(int64_t n, int64_t d, const double* A, int64_t lda, float* a32, __hip_bfloat16* a16, hipStream_t s) {
-  hipLaunchKernelGGL(cast2_kernel, dim3((unsigned)ceil_div(n * d, 256)), dim3(256), 0, s, n, d, A, lda, a32, a16);
-  AES_LAUNCH_CHECK();
-}
-
 __global__ void axpy_cols_kernel(int64_t total, int C, double* __restrict__ x, const double* __restrict__ e,
                                  const int* __restrict__ active) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -73,8 +73,6 @@ void launch_transpose(int64_t rows, int64_t cols, const double* src, int64_t lds
 void launch_inv(int64_t count, const double* src, double* dst, hipStream_t s);
 template <typename TO>
 void launch_cast(int64_t n, int64_t d, const double* A, int64_t lda, TO* out, hipStream_t s);
-void launch_cast2(int64_t n, int64_t d, const double* A, int64_t lda, float* a32, __hip_bfloat16* a16,
-                  hipStream_t s);
 void launch_axpy_cols(int64_t d, int C, double* x, const double* e, const int* active, hipStream_t s);
 
 // ---- sketches (k_sketch.hip) -------------------------------------------------------------
