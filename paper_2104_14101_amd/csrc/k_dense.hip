@@ -259,7 +259,7 @@ static void gemm_dispatch(int64_t M, int64_t N, int64_t K, double alpha, const T
     dim3 grid((unsigned)ceil_div(N, 128), (unsigned)ceil_div(M, 128), (unsigned)batch);
     hipLaunchKernelGGL((gemm_kernel<T, TA, TB, 128, 128, 16>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B,
                        ldb, sB, beta, C, ldc, sC, tri, vec, (int64_t)0);
-  } else if (ceil_div(M, 64) * ceil_div(N, 64) * batch >= 128) {
+  } else if (ceil_div(M, 64) * ceil_div(N, 64) * batch >= 512) {
     dim3 grid((unsigned)ceil_div(N, 64), (unsigned)ceil_div(M, 64), (unsigned)batch);
     hipLaunchKernelGGL((gemm_kernel<T, TA, TB, 64, 64, 32>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B,
                        ldb, sB, beta, C, ldc, sC, tri, vec, (int64_t)0);
