@@ -5,6 +5,7 @@
 // Control: every device step is enqueued on the caller's stream; the host reads back one
 // small block of flags per attempted step (accepted / rejected / stopped), because the
 // accept-or-resketch decision of the algorithms is data dependent.
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -158,6 +159,16 @@ class Solver {
     sketch32_ = o.precision == AES_MIXED_FP32;
     pinned_ = h->pinned;
   }
+  ~Solver() {
+    for (hipEvent_t& e : fev_)
+      if (e) (void)hipEventDestroy(e);
+    for (auto& e : sk_ev_) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+  }
+  Solver(const Solver&) = delete;
+  Solver& operator=(const Solver&) = delete;
 
   // Buffers in the handle pool, namespaced per solver role.
   template <typename T>
@@ -232,19 +243,20 @@ class Solver {
   }
 
   // out = sgn * (H v) + bsgn * b    (H = A^T A + nu^2 Lambda); A in FP64 or (inner) FP32.
-  void hv(const double* v, double* out, double sgn, const double* bb, double bsgn, bool use32) {
+  void hv(const double* v, double* out, double sgn, const double* bb, double bsgn, bool use32,
+          const int* gate = nullptr) {
     if (C_ == 1) {
       const bool prof = o_.profile && !use32;
       if (prof) AES_HIP(hipEventRecord(h_->event(2 * n_events_), s_));
       if (use32)
-        launch_hv_fused<float>(A32_, n_, d_, d_, v, part_, spart_, nwg_, s_);
+        launch_hv_fused<float>(A32_, n_, d_, d_, v, part_, spart_, nwg_, s_, gate);
       else
-        launch_hv_fused<double>(P_.A, n_, d_, P_.lda, v, part_, spart_, nwg_, s_);
+        launch_hv_fused<double>(P_.A, n_, d_, P_.lda, v, part_, spart_, nwg_, s_, gate);
       if (prof) {
         AES_HIP(hipEventRecord(h_->event(2 * n_events_ + 1), s_));
         ++n_events_;
       }
-      launch_hv_colsum(part_, nwg_, d_, 1, v, lam_, nu2_, sgn, bb, bsgn, out, s_);
+      launch_hv_colsum(part_, nwg_, d_, 1, v, lam_, nu2_, sgn, bb, bsgn, out, s_, gate);
     } else if (use32) {
       // FP32 storage and MFMA: Z = A V (n x C), partial Q_w = A_w^T Z_w over row blocks
       narrow_f64(d_ * C_, v, V32_, s_);
@@ -283,7 +295,13 @@ class Solver {
 
   // ---- sketch + factorisation of H_S (Sec. 4.1) ----------------------------------------
   void sketch_factor() {
-    const double t0 = now_ms();
+    {
+      std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+      AES_HIP(hipEventCreate(&ev.first));
+      AES_HIP(hipEventCreate(&ev.second));
+      sk_ev_.push_back(ev);
+      AES_HIP(hipEventRecord(ev.first, s_));
+    }
     const bool bf = mixed_ && !sketch32_ && o_.sketch == AES_SRHT;
     const bool f32 = mixed_ && sketch32_ && o_.sketch == AES_SRHT;
     woodbury_ = m_ < d_;
@@ -323,11 +341,10 @@ class Solver {
     int* flag = B<int>("chol_flag", 1);
     AES_HIP(hipMemsetAsync(flag, 0, sizeof(int), s_));
     factor_from_sa(bf ? 1 : (f32 ? 2 : 0), flag);
-    int hflag = 0;
-    AES_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s_));
-    AES_HIP(hipStreamSynchronize(s_));
-    t_sketch_ += now_ms() - t0;
-    if (hflag) throw StatusError(AES_ERR_NOT_SPD, "Cholesky pivot of the sketched Hessian is not positive");
+    // no wait here: the initialisation that follows copies the failure flag into the flag
+    // block, which the host reads next
+    chol_flag_ = flag;
+    AES_HIP(hipEventRecord(sk_ev_.back().second, s_));
   }
 
   // Gram of the current sketch, its Cholesky factor and the inverse factor (Sec. 4.1).
@@ -384,7 +401,7 @@ class Solver {
   }
 
   // v = H_S^{-1} z (z, v: d x C)
-  void apply(const double* z, double* v) {
+  void apply(const double* z, double* v, const int* gate = nullptr) {
     double* t1 = B<double>("ap_t1", (size_t)std::max(m_, d_) * C_);
     if (!woodbury_) {
       if (C_ >= 8) {
@@ -403,16 +420,16 @@ class Solver {
         gemm_f64(false, false, np, C_, Ks, 1.0, LinvT_, np, Ks, tp, C_, Ks * C_, 0.0, part, C_, np * C_, S, 0, s_);
         launch_sum_parts(d_ * C_, S, np * C_, part, v, s_);
       } else {
-        launch_rowdot(d_, d_, Linv_, fp_, 1, z, C_, nullptr, 1.0, nullptr, nullptr, 1.0, t1, s_);
-        launch_rowdot(d_, d_, LinvT_, fp_, 2, t1, C_, nullptr, 1.0, nullptr, nullptr, 1.0, v, s_);
+        launch_rowdot(d_, d_, Linv_, fp_, 1, z, C_, nullptr, 1.0, nullptr, nullptr, 1.0, t1, s_, gate);
+        launch_rowdot(d_, d_, LinvT_, fp_, 2, t1, C_, nullptr, 1.0, nullptr, nullptr, 1.0, v, s_, gate);
       }
     } else {
       double* u = B<double>("ap_u", (size_t)m_ * C_);
       double* w = B<double>("ap_w", (size_t)m_ * C_);
-      launch_rowdot(m_, d_, SA_, d_, 0, z, C_, invlam_, 1.0, nullptr, nullptr, 1.0, u, s_);
-      launch_rowdot(m_, m_, Linv_, fp_, 1, u, C_, nullptr, 1.0, nullptr, nullptr, 1.0, t1, s_);
-      launch_rowdot(m_, m_, LinvT_, fp_, 2, t1, C_, nullptr, 1.0, nullptr, nullptr, 1.0, w, s_);
-      launch_rowdot(d_, m_, SAT_, m_, 0, w, C_, nullptr, -1.0, z, invlam_, 1.0 / nu2_, v, s_);
+      launch_rowdot(m_, d_, SA_, d_, 0, z, C_, invlam_, 1.0, nullptr, nullptr, 1.0, u, s_, gate);
+      launch_rowdot(m_, m_, Linv_, fp_, 1, u, C_, nullptr, 1.0, nullptr, nullptr, 1.0, t1, s_, gate);
+      launch_rowdot(m_, m_, LinvT_, fp_, 2, t1, C_, nullptr, 1.0, nullptr, nullptr, 1.0, w, s_, gate);
+      launch_rowdot(d_, m_, SAT_, m_, 0, w, C_, nullptr, -1.0, z, invlam_, 1.0 / nu2_, v, s_, gate);
     }
   }
 
@@ -453,6 +470,12 @@ class Solver {
       cc = 4.0 * (1.0 + sr) / (1.0 - sr);
     }
     const double lphi = std::log(phi), lc = std::log(cc);
+    // With one right-hand side every kernel of a step is gated by a device word that the
+    // previous step's finish (or the initialisation) sets when it accepted and has active
+    // columns, so the next step is enqueued before the host has read the flags of the current
+    // one; the host then reads them through an event on their own pinned slot.
+    const bool spec = C_ == 1;
+    int* gate = spec ? B<int>("gate", 1) : nullptr;
     if (!reuse_factor) sketch_factor();
     // initial residual / gradient
     if (ihs) {
@@ -461,52 +484,109 @@ class Solver {
       else
         hv(x, R_, 1.0, rhs, -1.0, use32);  // g = H x - b
       apply(R_, Pv_);
-      launch_ihs_init(d_, C_, R_, Pv_, scal_, active_, nullptr, stop_rule, stop_scale, stop_sr_, tol2_, x, 1, s_);
+      launch_ihs_init(d_, C_, R_, Pv_, scal_, active_, gate, stop_rule, stop_scale, stop_sr_, tol2_, x, 1, s_,
+                      chol_flag_);
     } else {
       if (x_is_zero)
         AES_HIP(hipMemcpyAsync(R_, rhs, d_ * C_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
       else
         hv(x, R_, -1.0, rhs, 1.0, use32);  // r = b - H x
       apply(R_, RTP_);
-      launch_pcg_init(d_, C_, R_, RTP_, Pv_, scal_, active_, nullptr, stop_rule, stop_scale, stop_sr_, tol2_, x, 1, s_);
+      launch_pcg_init(d_, C_, R_, RTP_, Pv_, scal_, active_, gate, stop_rule, stop_scale, stop_sr_, tol2_, x, 1, s_,
+                      chol_flag_);
     }
     read_flags();
+    if (fl_[6] != 0.0) throw StatusError(AES_ERR_NOT_SPD, "Cholesky pivot of the sketched Hessian is not positive");
     if (fl_[2] != 0.0) return AES_ERR_NONFINITE;
     int64_t t = 0, I = 0;
     bool forced = false;
-    while (fl_[1] > 0.5) {
-      if (t >= o_.max_iter) return stop_rule == AES_STOP_FIXED ? AES_OK : AES_ERR_MAX_ITER;
-      const double thr = lc + (double)(t + 1 - I) * lphi;
-      const int force = (o_.adaptive && o_.force_reject_at >= 0 && t == o_.force_reject_at && !forced) ? 1 : 0;
-      if (force) forced = true;
+    // one enqueued step: its index, forced-rejection flag, flag slot and first H.v event
+    struct Step {
+      int64_t t;
+      int force;
+      int slot;
+      int64_t ev;
+    };
+    auto enqueue_step = [&](int64_t tt, int force, int slot) -> Step {
+      const double thr = lc + (double)(tt + 1 - I) * lphi;
       const int at_cap = m_ >= mcap_ ? 1 : 0;
+      const int64_t ev = (o_.profile && !use32 && C_ == 1) ? n_events_ : -1;
       if (ihs) {
-        launch_ihs_candidate(d_, C_, x, Pv_, mu, XP_, active_, s_);
-        hv(XP_, RP_, 1.0, rhs, -1.0, use32);
-        apply(RP_, RTP_);
-        launch_ihs_finish(d_, C_, x, R_, Pv_, XP_, RP_, RTP_, scal_, active_, nullptr, thr, force, o_.adaptive, at_cap,
+        launch_ihs_candidate(d_, C_, x, Pv_, mu, XP_, active_, s_, gate);
+        hv(XP_, RP_, 1.0, rhs, -1.0, use32, gate);
+        apply(RP_, RTP_, gate);
+        launch_ihs_finish(d_, C_, x, R_, Pv_, XP_, RP_, RTP_, scal_, active_, gate, thr, force, o_.adaptive, at_cap,
                           stop_rule, stop_scale, stop_sr_, tol2_, s_);
       } else {
-        hv(Pv_, Q_, 1.0, nullptr, 0.0, use32);
+        hv(Pv_, Q_, 1.0, nullptr, 0.0, use32, gate);
         launch_pcg_candidate(d_, C_, C_ == 1 ? spart_ : nullptr, nwg_, lam_, nu2_, x, R_, Pv_, Q_, XP_, RP_, scal_,
-                             active_, s_);
-        apply(RP_, RTP_);
-        launch_pcg_finish(d_, C_, x, R_, Pv_, XP_, RP_, RTP_, scal_, active_, nullptr, thr, force, o_.adaptive, at_cap,
+                             active_, s_, gate);
+        apply(RP_, RTP_, gate);
+        launch_pcg_finish(d_, C_, x, R_, Pv_, XP_, RP_, RTP_, scal_, active_, gate, thr, force, o_.adaptive, at_cap,
                           stop_rule, stop_scale, stop_sr_, tol2_, s_);
       }
-      read_flags();
+      if (spec) {
+        AES_HIP(hipMemcpyAsync(pinned_ + 8 * slot, scal_ + 7 * C_, 8 * sizeof(double), hipMemcpyDeviceToHost, s_));
+        AES_HIP(hipEventRecord(flag_event(slot), s_));
+      }
+      return Step{tt, force, slot, ev};
+    };
+    // a speculatively enqueued step that did not run: its pass and timing event do not count
+    auto discard = [&](const Step& st) {
+      --a_passes_;
+      if (st.ev >= 0) skip_events_.push_back(st.ev);
+    };
+    auto force_at = [&](int64_t tt, bool already) {
+      return (o_.adaptive && o_.force_reject_at >= 0 && tt == o_.force_reject_at && !already) ? 1 : 0;
+    };
+    bool have_next = false;
+    Step next{};
+    while (fl_[1] > 0.5) {
+      if (t >= o_.max_iter) {
+        if (have_next) discard(next);
+        return stop_rule == AES_STOP_FIXED ? AES_OK : AES_ERR_MAX_ITER;
+      }
+      Step cur = have_next ? next : enqueue_step(t, force_at(t, forced), (int)(t & 1));
+      have_next = false;
+      if (spec && t + 1 < o_.max_iter) {
+        // enqueue step t+1 as if step t is accepted (its force flag as the host would decide it)
+        next = enqueue_step(t + 1, force_at(t + 1, forced || cur.force != 0), (int)((t + 1) & 1));
+        have_next = true;
+      }
+      if (spec) {
+        AES_HIP(hipEventSynchronize(flag_event(cur.slot)));
+        for (int i = 0; i < 8; ++i) fl_[i] = pinned_[8 * cur.slot + i];
+      } else {
+        read_flags();
+      }
+      if (cur.force) forced = true;
       ++attempts_;
       const bool fail = fl_[0] != 0.0, accepted = fl_[3] != 0.0;
-      trace(t, fl_[4], thr, accepted);
-      if (fl_[2] != 0.0) return AES_ERR_NONFINITE;
+      trace(t, fl_[4], thr_of(lc, lphi, t, I), accepted);
+      if (fl_[2] != 0.0) {
+        if (have_next) discard(next);
+        return AES_ERR_NONFINITE;
+      }
       if (accepted) {
         ++t;
         ++iters_;
         if (fail && o_.adaptive) m_cap_reached_ = 1;
-        if (stop_rule == AES_STOP_FIXED && t >= o_.max_iter) return AES_OK;
+        if (stop_rule == AES_STOP_FIXED && t >= o_.max_iter) {
+          if (have_next) discard(next);
+          return AES_OK;
+        }
+        if (fl_[1] <= 0.5 && have_next) {
+          discard(next);  // stopped: the gate kept step t+1 from running
+          have_next = false;
+        }
         continue;
       }
-      // rejected: double m, fresh sketch, restart at x_t (Algorithm 2 / Algorithm 1)
+      // rejected (the gate kept a speculative step t+1 from running): double m, fresh sketch,
+      // restart at x_t (Algorithm 2 / Algorithm 1)
+      if (have_next) {
+        discard(next);
+        have_next = false;
+      }
       I = t;
       m_ = std::min<int64_t>(2 * m_, mcap_);
       ++k_;
@@ -514,19 +594,30 @@ class Solver {
       sketch_factor();
       if (ihs) {
         apply(R_, Pv_);
-        launch_ihs_init(d_, C_, R_, Pv_, scal_, active_, nullptr, stop_rule, stop_scale, stop_sr_, tol2_, x, 0, s_);
+        launch_ihs_init(d_, C_, R_, Pv_, scal_, active_, gate, stop_rule, stop_scale, stop_sr_, tol2_, x, 0, s_,
+                        chol_flag_);
       } else {
         if (x_is_zero && t == 0)
           AES_HIP(hipMemcpyAsync(R_, rhs, d_ * C_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
         else
           hv(x, R_, -1.0, rhs, 1.0, use32);  // explicit r_t = b - H x_t
         apply(R_, RTP_);
-        launch_pcg_init(d_, C_, R_, RTP_, Pv_, scal_, active_, nullptr, stop_rule, stop_scale, stop_sr_, tol2_, x, 0, s_);
+        launch_pcg_init(d_, C_, R_, RTP_, Pv_, scal_, active_, gate, stop_rule, stop_scale, stop_sr_, tol2_, x, 0, s_,
+                        chol_flag_);
       }
       read_flags();
+      if (fl_[6] != 0.0) throw StatusError(AES_ERR_NOT_SPD, "Cholesky pivot of the sketched Hessian is not positive");
       if (fl_[2] != 0.0) return AES_ERR_NONFINITE;
     }
+    if (have_next) discard(next);
     return AES_OK;
+  }
+
+  static double thr_of(double lc, double lphi, int64_t t, int64_t I) { return lc + (double)(t + 1 - I) * lphi; }
+
+  hipEvent_t flag_event(int slot) {
+    if (!fev_[slot]) AES_HIP(hipEventCreateWithFlags(&fev_[slot], hipEventDisableTiming));
+    return fev_[slot];
   }
 
   aes_status run(aes_info* info, bool reuse_factor = false) {
@@ -565,15 +656,20 @@ class Solver {
       h_->set_err(e.what());
     }
     double hv_ms = 0.0;
+    int64_t hv_n = 0;
     if (o_.profile && st != AES_ERR_HIP) {
       for (int64_t i = 0; i < n_events_; ++i) {
+        if (std::find(skip_events_.begin(), skip_events_.end(), i) != skip_events_.end()) continue;
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, h_->events[2 * i], h_->events[2 * i + 1]) == hipSuccess) hv_ms += ms;
+        if (hipEventElapsedTime(&ms, h_->events[2 * i], h_->events[2 * i + 1]) == hipSuccess) {
+          hv_ms += ms;
+          ++hv_n;
+        }
       }
     }
     if (info) {
       info->time_hv_ms = hv_ms;
-      info->hv_launches = n_events_;
+      info->hv_launches = hv_n;
       info->iterations = iters_;
       info->attempts = attempts_;
       info->final_m = m_;
@@ -582,7 +678,13 @@ class Solver {
       info->refine_sweeps = sweeps_;
       info->trace_len = trace_len_;
       info->dtilde_final = fl_[5];
-      info->time_sketch_ms = t_sketch_;
+      double sk_ms = 0.0;
+      if (st != AES_ERR_HIP)
+        for (auto& e : sk_ev_) {
+          float ms = 0.f;
+          if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) sk_ms += ms;
+        }
+      info->time_sketch_ms = sk_ms;
       info->time_total_ms = now_ms() - t0;
       info->m_cap_reached = m_cap_reached_;
       info->status = st;
@@ -721,8 +823,11 @@ class Solver {
   double fl_[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int64_t iters_ = 0, attempts_ = 0, resketches_ = 0, a_passes_ = 0, sweeps_ = 0, trace_len_ = 0;
   int m_cap_reached_ = 0;
-  double t_sketch_ = 0;
   int64_t n_events_ = 0;
+  std::vector<int64_t> skip_events_;  // timing events of speculative steps that did not run
+  hipEvent_t fev_[2] = {nullptr, nullptr};  // flag-copy events of the two pinned slots
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> sk_ev_;  // start / end of every sketch + factorisation
+  const int* chol_flag_ = nullptr;
 };
 
 aes_status guard(aes_handle h, const std::function<void()>& f) {

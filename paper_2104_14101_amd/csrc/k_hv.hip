@@ -55,7 +55,9 @@ template <typename TA, int VEC, int NCH, int ROWS>
 __global__ __launch_bounds__(kHvThreads, 2) void hv_fused_kernel(const TA* __restrict__ A, int64_t n, int d,
                                                                   int64_t lda, const double* __restrict__ v,
                                                                   double* __restrict__ part,
-                                                                  double* __restrict__ spart) {
+                                                                  double* __restrict__ spart,
+                                                                  const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   constexpr int CH = kHvThreads * VEC;  // columns per chunk
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -136,47 +138,47 @@ int hv_num_blocks(int num_cu, int64_t n) {
 
 template <typename TA, int VEC, int NCH, int ROWS>
 static void hv_launch_cfg(const TA* A, int64_t n, int64_t d, int64_t lda, const double* v, double* part,
-                          double* spart, int nwg, hipStream_t s) {
+                          double* spart, int nwg, hipStream_t s, const int* gate) {
   hipLaunchKernelGGL((hv_fused_kernel<TA, VEC, NCH, ROWS>), dim3(nwg), dim3(kHvThreads), 0, s, A, n, (int)d, lda,
-                     v, part, spart);
+                     v, part, spart, gate);
   AES_LAUNCH_CHECK();
 }
 
 template <>
 void launch_hv_fused<double>(const double* A, int64_t n, int64_t d, int64_t lda, const double* v, double* part,
-                             double* spart, int nwg, hipStream_t s) {
+                             double* spart, int nwg, hipStream_t s, const int* gate) {
   const bool v2 = (d % 2 == 0) && (lda % 2 == 0) && ((uintptr_t)A % 16 == 0);
   if (v2) {
-    if (d <= 512) return hv_launch_cfg<double, 2, 1, 16>(A, n, d, lda, v, part, spart, nwg, s);
-    if (d <= 1024) return hv_launch_cfg<double, 2, 2, 8>(A, n, d, lda, v, part, spart, nwg, s);
-    if (d <= 2048) return hv_launch_cfg<double, 2, 4, 8>(A, n, d, lda, v, part, spart, nwg, s);
-    if (d <= 4096) return hv_launch_cfg<double, 2, 8, 2>(A, n, d, lda, v, part, spart, nwg, s);
-    if (d <= 8192) return hv_launch_cfg<double, 2, 16, 1>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 512) return hv_launch_cfg<double, 2, 1, 16>(A, n, d, lda, v, part, spart, nwg, s, gate);
+    if (d <= 1024) return hv_launch_cfg<double, 2, 2, 8>(A, n, d, lda, v, part, spart, nwg, s, gate);
+    if (d <= 2048) return hv_launch_cfg<double, 2, 4, 8>(A, n, d, lda, v, part, spart, nwg, s, gate);
+    if (d <= 4096) return hv_launch_cfg<double, 2, 8, 2>(A, n, d, lda, v, part, spart, nwg, s, gate);
+    if (d <= 8192) return hv_launch_cfg<double, 2, 16, 1>(A, n, d, lda, v, part, spart, nwg, s, gate);
   } else {
-    if (d <= 256) return hv_launch_cfg<double, 1, 1, 16>(A, n, d, lda, v, part, spart, nwg, s);
-    if (d <= 1024) return hv_launch_cfg<double, 1, 4, 8>(A, n, d, lda, v, part, spart, nwg, s);
-    if (d <= 2048) return hv_launch_cfg<double, 1, 8, 4>(A, n, d, lda, v, part, spart, nwg, s);
-    if (d <= 4096) return hv_launch_cfg<double, 1, 16, 1>(A, n, d, lda, v, part, spart, nwg, s);
-    if (d <= 8192) return hv_launch_cfg<double, 1, 32, 1>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 256) return hv_launch_cfg<double, 1, 1, 16>(A, n, d, lda, v, part, spart, nwg, s, gate);
+    if (d <= 1024) return hv_launch_cfg<double, 1, 4, 8>(A, n, d, lda, v, part, spart, nwg, s, gate);
+    if (d <= 2048) return hv_launch_cfg<double, 1, 8, 4>(A, n, d, lda, v, part, spart, nwg, s, gate);
+    if (d <= 4096) return hv_launch_cfg<double, 1, 16, 1>(A, n, d, lda, v, part, spart, nwg, s, gate);
+    if (d <= 8192) return hv_launch_cfg<double, 1, 32, 1>(A, n, d, lda, v, part, spart, nwg, s, gate);
   }
   throw std::invalid_argument("hv_fused: d > 8192 is not supported");
 }
 
 template <>
 void launch_hv_fused<float>(const float* A, int64_t n, int64_t d, int64_t lda, const double* v, double* part,
-                            double* spart, int nwg, hipStream_t s) {
+                            double* spart, int nwg, hipStream_t s, const int* gate) {
   const bool v4 = (d % 4 == 0) && (lda % 4 == 0) && ((uintptr_t)A % 16 == 0);
   if (v4) {
-    if (d <= 1024) return hv_launch_cfg<float, 4, 1, 8>(A, n, d, lda, v, part, spart, nwg, s);
-    if (d <= 2048) return hv_launch_cfg<float, 4, 2, 8>(A, n, d, lda, v, part, spart, nwg, s);
-    if (d <= 4096) return hv_launch_cfg<float, 4, 4, 4>(A, n, d, lda, v, part, spart, nwg, s);
-    if (d <= 8192) return hv_launch_cfg<float, 4, 8, 1>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 1024) return hv_launch_cfg<float, 4, 1, 8>(A, n, d, lda, v, part, spart, nwg, s, gate);
+    if (d <= 2048) return hv_launch_cfg<float, 4, 2, 8>(A, n, d, lda, v, part, spart, nwg, s, gate);
+    if (d <= 4096) return hv_launch_cfg<float, 4, 4, 4>(A, n, d, lda, v, part, spart, nwg, s, gate);
+    if (d <= 8192) return hv_launch_cfg<float, 4, 8, 1>(A, n, d, lda, v, part, spart, nwg, s, gate);
   } else {
-    if (d <= 256) return hv_launch_cfg<float, 1, 1, 16>(A, n, d, lda, v, part, spart, nwg, s);
-    if (d <= 1024) return hv_launch_cfg<float, 1, 4, 8>(A, n, d, lda, v, part, spart, nwg, s);
-    if (d <= 2048) return hv_launch_cfg<float, 1, 8, 4>(A, n, d, lda, v, part, spart, nwg, s);
-    if (d <= 4096) return hv_launch_cfg<float, 1, 16, 1>(A, n, d, lda, v, part, spart, nwg, s);
-    if (d <= 8192) return hv_launch_cfg<float, 1, 32, 1>(A, n, d, lda, v, part, spart, nwg, s);
+    if (d <= 256) return hv_launch_cfg<float, 1, 1, 16>(A, n, d, lda, v, part, spart, nwg, s, gate);
+    if (d <= 1024) return hv_launch_cfg<float, 1, 4, 8>(A, n, d, lda, v, part, spart, nwg, s, gate);
+    if (d <= 2048) return hv_launch_cfg<float, 1, 8, 4>(A, n, d, lda, v, part, spart, nwg, s, gate);
+    if (d <= 4096) return hv_launch_cfg<float, 1, 16, 1>(A, n, d, lda, v, part, spart, nwg, s, gate);
+    if (d <= 8192) return hv_launch_cfg<float, 1, 32, 1>(A, n, d, lda, v, part, spart, nwg, s, gate);
   }
   throw std::invalid_argument("hv_fused: d > 8192 is not supported");
 }
@@ -189,7 +191,8 @@ __global__ __launch_bounds__(256) void hv_colsum_kernel(const TP* __restrict__ p
                                                         int C, const double* __restrict__ v,
                                                         const double* __restrict__ lam, double nu2, double sgn,
                                                         const double* __restrict__ b, double bsgn,
-                                                        double* __restrict__ out) {
+                                                        double* __restrict__ out, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   __shared__ double sh[16][17];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int64_t e = (int64_t)blockIdx.x * 16 + tx;
@@ -222,10 +225,10 @@ __global__ __launch_bounds__(256) void hv_colsum_kernel(const TP* __restrict__ p
 }
 
 void launch_hv_colsum(const double* part, int nwg, int64_t d, int C, const double* v, const double* lam, double nu2,
-                      double sgn, const double* b, double bsgn, double* out, hipStream_t s) {
+                      double sgn, const double* b, double bsgn, double* out, hipStream_t s, const int* gate) {
   const int64_t total = d * C;
   hipLaunchKernelGGL(hv_colsum_kernel<double>, dim3((unsigned)ceil_div(total, 16)), dim3(256), 0, s, part, nwg, total, C,
-                     v, lam, nu2, sgn, b, bsgn, out);
+                     v, lam, nu2, sgn, b, bsgn, out, gate);
   AES_LAUNCH_CHECK();
 }
 
@@ -233,7 +236,7 @@ void launch_hv_colsum_f32(const float* part, int nwg, int64_t d, int C, const do
                           double sgn, const double* b, double bsgn, double* out, hipStream_t s) {
   const int64_t total = d * C;
   hipLaunchKernelGGL(hv_colsum_kernel<float>, dim3((unsigned)ceil_div(total, 16)), dim3(256), 0, s, part, nwg, total, C,
-                     v, lam, nu2, sgn, b, bsgn, out);
+                     v, lam, nu2, sgn, b, bsgn, out, nullptr);
   AES_LAUNCH_CHECK();
 }
 

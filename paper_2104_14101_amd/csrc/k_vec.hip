@@ -40,7 +40,9 @@ __global__ __launch_bounds__(kVT) void pcg_candidate_kernel(int64_t d, int C, co
                                                             const double* __restrict__ x, const double* __restrict__ r,
                                                             const double* __restrict__ p, const double* __restrict__ q,
                                                             double* __restrict__ xp, double* __restrict__ rp,
-                                                            double* __restrict__ scal, const int* __restrict__ active) {
+                                                            double* __restrict__ scal, const int* __restrict__ active,
+                                                            const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   __shared__ double buf[kVT];
   __shared__ double alpha_s[64];
   const int tid = threadIdx.x, col = tid % C, tpc = kVT / C;
@@ -78,9 +80,9 @@ __global__ __launch_bounds__(kVT) void pcg_candidate_kernel(int64_t d, int C, co
 
 void launch_pcg_candidate(int64_t d, int C, const double* spart, int nwg, const double* lam, double nu2, const double* x,
                           const double* r, const double* p, const double* q, double* xp, double* rp, double* scal,
-                          const int* active, hipStream_t s) {
+                          const int* active, hipStream_t s, const int* gate) {
   hipLaunchKernelGGL(pcg_candidate_kernel, dim3(1), dim3(kVT), 0, s, d, C, spart, nwg, lam, nu2, x, r, p, q, xp, rp, scal,
-                     active);
+                     active, gate);
   AES_LAUNCH_CHECK();
 }
 
@@ -106,9 +108,10 @@ __global__ __launch_bounds__(kVT) void finish_kernel(int64_t d, int C, double* _
                                                      double* __restrict__ p, const double* __restrict__ xp,
                                                      const double* __restrict__ rp, const double* __restrict__ rtp,
                                                      double* __restrict__ scal, int* __restrict__ active,
-                                                     int* __restrict__ flags, double thr, int force_reject,
+                                                     int* __restrict__ gate, double thr, int force_reject,
                                                      int adaptive, int at_cap, int stop_rule, double stop_scale,
                                                      double stop_sr, double tol2) {
+  if (gate && *gate == 0) return;
   __shared__ double buf[kVT];
   __shared__ double dp_s[64], xn_s[64], rz_s[64];
   __shared__ int accept_s;
@@ -161,6 +164,7 @@ __global__ __launch_bounds__(kVT) void finish_kernel(int64_t d, int C, double* _
       int na = 0;
       for (int c = 0; c < C; ++c) na += active[c] != 0;
       scal[7 * C + 1] = (double)na;
+      if (gate) *gate = 0;
     }
     return;
   }
@@ -191,23 +195,24 @@ __global__ __launch_bounds__(kVT) void finish_kernel(int64_t d, int C, double* _
     }
     scal[7 * C + 1] = (double)na;
     scal[7 * C + 5] = maxD;
+    if (gate) *gate = na > 0 ? 1 : 0;
   }
 }
 
 void launch_pcg_finish(int64_t d, int C, double* x, double* r, double* p, const double* xp, const double* rp,
-                       const double* rtp, double* scal, int* active, int* flags, double thr, int force_reject,
+                       const double* rtp, double* scal, int* active, int* gate, double thr, int force_reject,
                        int adaptive, int at_cap, int stop_rule, double stop_scale, double stop_sr, double tol2,
                        hipStream_t s) {
-  hipLaunchKernelGGL(finish_kernel<false>, dim3(1), dim3(kVT), 0, s, d, C, x, r, p, xp, rp, rtp, scal, active, flags, thr,
+  hipLaunchKernelGGL(finish_kernel<false>, dim3(1), dim3(kVT), 0, s, d, C, x, r, p, xp, rp, rtp, scal, active, gate, thr,
                      force_reject, adaptive, at_cap, stop_rule, stop_scale, stop_sr, tol2);
   AES_LAUNCH_CHECK();
 }
 
 void launch_ihs_finish(int64_t d, int C, double* x, double* g, double* sd, const double* xp, const double* gp,
-                       const double* sp, double* scal, int* active, int* flags, double thr, int force_reject,
+                       const double* sp, double* scal, int* active, int* gate, double thr, int force_reject,
                        int adaptive, int at_cap, int stop_rule, double stop_scale, double stop_sr, double tol2,
                        hipStream_t s) {
-  hipLaunchKernelGGL(finish_kernel<true>, dim3(1), dim3(kVT), 0, s, d, C, x, g, sd, xp, gp, sp, scal, active, flags, thr,
+  hipLaunchKernelGGL(finish_kernel<true>, dim3(1), dim3(kVT), 0, s, d, C, x, g, sd, xp, gp, sp, scal, active, gate, thr,
                      force_reject, adaptive, at_cap, stop_rule, stop_scale, stop_sr, tol2);
   AES_LAUNCH_CHECK();
 }
@@ -219,7 +224,8 @@ __global__ __launch_bounds__(kVT) void init_kernel(int64_t d, int C, const doubl
                                                    const double* __restrict__ rt, double* __restrict__ p,
                                                    double* __restrict__ scal, int* __restrict__ active,
                                                    int stop_rule, double stop_scale, double stop_sr, double tol2,
-                                                   const double* __restrict__ x, int set_d0) {
+                                                   const double* __restrict__ x, int set_d0, int* __restrict__ gate,
+                                                   const int* __restrict__ chol_flag) {
   __shared__ double buf[kVT];
   __shared__ double dd[64], xn[64], rz[64];
   const int tid = threadIdx.x, col = tid % C, tpc = kVT / C;
@@ -260,37 +266,43 @@ __global__ __launch_bounds__(kVT) void init_kernel(int64_t d, int C, const doubl
     }
     scal[7 * C + 1] = (double)na;
     scal[7 * C + 5] = maxD;
+    // flag 6: the factorisation this initialisation follows met a non-positive pivot
+    const bool bad = chol_flag && *chol_flag != 0;
+    scal[7 * C + 6] = bad ? 1.0 : 0.0;
+    if (gate) *gate = (!bad && na > 0 && scal[7 * C + 2] == 0.0) ? 1 : 0;
   }
 }
 
 void launch_pcg_init(int64_t d, int C, const double* r, const double* rt, double* p, double* scal, int* active,
-                     int* flags, int stop_rule, double stop_scale, double stop_sr, double tol2, const double* x,
-                     int set_d0, hipStream_t s) {
+                     int* gate, int stop_rule, double stop_scale, double stop_sr, double tol2, const double* x,
+                     int set_d0, hipStream_t s, const int* chol_flag) {
   hipLaunchKernelGGL(init_kernel<false>, dim3(1), dim3(kVT), 0, s, d, C, r, rt, p, scal, active, stop_rule, stop_scale,
-                     stop_sr, tol2, x, set_d0);
+                     stop_sr, tol2, x, set_d0, gate, chol_flag);
   AES_LAUNCH_CHECK();
 }
 
-void launch_ihs_init(int64_t d, int C, const double* g, const double* sd, double* scal, int* active, int* flags,
+void launch_ihs_init(int64_t d, int C, const double* g, const double* sd, double* scal, int* active, int* gate,
                      int stop_rule, double stop_scale, double stop_sr, double tol2, const double* x, int set_d0,
-                     hipStream_t s) {
+                     hipStream_t s, const int* chol_flag) {
   hipLaunchKernelGGL(init_kernel<true>, dim3(1), dim3(kVT), 0, s, d, C, g, sd, nullptr, scal, active, stop_rule,
-                     stop_scale, stop_sr, tol2, x, set_d0);
+                     stop_scale, stop_sr, tol2, x, set_d0, gate, chol_flag);
   AES_LAUNCH_CHECK();
 }
 
 __global__ void ihs_candidate_kernel(int64_t total, int C, const double* __restrict__ x, const double* __restrict__ sd,
-                                     double mu, double* __restrict__ xp, const int* __restrict__ active) {
+                                     double mu, double* __restrict__ xp, const int* __restrict__ active,
+                                     const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
   xp[e] = active[e % C] ? x[e] - mu * sd[e] : x[e];
 }
 
 void launch_ihs_candidate(int64_t d, int C, const double* x, const double* sd, double mu, double* xp, const int* active,
-                          hipStream_t s) {
+                          hipStream_t s, const int* gate) {
   const int64_t total = d * C;
   hipLaunchKernelGGL(ihs_candidate_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, total, C, x, sd, mu, xp,
-                     active);
+                     active, gate);
   AES_LAUNCH_CHECK();
 }
 
@@ -303,7 +315,8 @@ __global__ __launch_bounds__(256) void rowdot_kernel(int64_t nrows, int64_t ncol
                                                      const double* __restrict__ xs, double ysgn,
                                                      const double* __restrict__ zadd,
                                                      const double* __restrict__ rowscale, double gscale,
-                                                     double* __restrict__ y) {
+                                                     double* __restrict__ y, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -351,18 +364,18 @@ __global__ __launch_bounds__(256) void rowdot_kernel(int64_t nrows, int64_t ncol
 
 void launch_rowdot(int64_t nrows, int64_t ncols, const double* M, int64_t ldm, int tri, const double* x, int C,
                    const double* xs, double ysgn, const double* zadd, const double* rowscale, double gscale, double* y,
-                   hipStream_t s) {
+                   hipStream_t s, const int* gate) {
   if (nrows <= 0) return;
   int64_t blocks = ceil_div(nrows, 4);
   if (blocks > 4096) blocks = 4096;
   dim3 g((unsigned)blocks), b(256);
   switch (C) {
-    case 1: hipLaunchKernelGGL(rowdot_kernel<1>, g, b, 0, s, nrows, ncols, M, ldm, tri, x, xs, ysgn, zadd, rowscale, gscale, y); break;
-    case 2: hipLaunchKernelGGL(rowdot_kernel<2>, g, b, 0, s, nrows, ncols, M, ldm, tri, x, xs, ysgn, zadd, rowscale, gscale, y); break;
-    case 4: hipLaunchKernelGGL(rowdot_kernel<4>, g, b, 0, s, nrows, ncols, M, ldm, tri, x, xs, ysgn, zadd, rowscale, gscale, y); break;
-    case 8: hipLaunchKernelGGL(rowdot_kernel<8>, g, b, 0, s, nrows, ncols, M, ldm, tri, x, xs, ysgn, zadd, rowscale, gscale, y); break;
-    case 16: hipLaunchKernelGGL(rowdot_kernel<16>, g, b, 0, s, nrows, ncols, M, ldm, tri, x, xs, ysgn, zadd, rowscale, gscale, y); break;
-    case 32: hipLaunchKernelGGL(rowdot_kernel<32>, g, b, 0, s, nrows, ncols, M, ldm, tri, x, xs, ysgn, zadd, rowscale, gscale, y); break;
+    case 1: hipLaunchKernelGGL(rowdot_kernel<1>, g, b, 0, s, nrows, ncols, M, ldm, tri, x, xs, ysgn, zadd, rowscale, gscale, y, gate); break;
+    case 2: hipLaunchKernelGGL(rowdot_kernel<2>, g, b, 0, s, nrows, ncols, M, ldm, tri, x, xs, ysgn, zadd, rowscale, gscale, y, gate); break;
+    case 4: hipLaunchKernelGGL(rowdot_kernel<4>, g, b, 0, s, nrows, ncols, M, ldm, tri, x, xs, ysgn, zadd, rowscale, gscale, y, gate); break;
+    case 8: hipLaunchKernelGGL(rowdot_kernel<8>, g, b, 0, s, nrows, ncols, M, ldm, tri, x, xs, ysgn, zadd, rowscale, gscale, y, gate); break;
+    case 16: hipLaunchKernelGGL(rowdot_kernel<16>, g, b, 0, s, nrows, ncols, M, ldm, tri, x, xs, ysgn, zadd, rowscale, gscale, y, gate); break;
+    case 32: hipLaunchKernelGGL(rowdot_kernel<32>, g, b, 0, s, nrows, ncols, M, ldm, tri, x, xs, ysgn, zadd, rowscale, gscale, y, gate); break;
     default: throw std::invalid_argument("rowdot: C must be a power of two <= 32");
   }
   AES_LAUNCH_CHECK();

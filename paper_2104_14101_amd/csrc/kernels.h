@@ -12,9 +12,11 @@ namespace aes {
 // Number of workgroups used by hv_fused for a problem (the size of the partial buffers).
 int hv_num_blocks(int num_cu, int64_t n);
 // part[w*d + j] (w < nwg) and spart[w]: per-workgroup partials of A^T (A v) and ||A v||^2.
+// gate (optional, device): when *gate == 0 the launch does nothing (a speculatively enqueued
+// step of the adaptive loop whose predecessor was not accepted).
 template <typename TA>
 void launch_hv_fused(const TA* A, int64_t n, int64_t d, int64_t lda, const double* v, double* part,
-                     double* spart, int nwg, hipStream_t s);
+                     double* spart, int nwg, hipStream_t s, const int* gate = nullptr);
 // Multi-RHS variant (C right-hand sides, V is d x C row-major): part[w][d][C], spart[w][C].
 template <typename TA>
 void launch_hv_multi(const TA* A, int64_t n, int64_t d, int64_t lda, const double* V, int C,
@@ -22,7 +24,7 @@ void launch_hv_multi(const TA* A, int64_t n, int64_t d, int64_t lda, const doubl
 // out[j,c] = sgn * (sum_w part[w][j][c] + nu2 * lam[j] * v[j,c]) + (b ? bsgn*b[j,c] : 0)
 void launch_hv_colsum(const double* part, int nwg, int64_t d, int C, const double* v,
                       const double* lam, double nu2, double sgn, const double* b, double bsgn,
-                      double* out, hipStream_t s);
+                      double* out, hipStream_t s, const int* gate = nullptr);
 
 void launch_hv_colsum_f32(const float* part, int nwg, int64_t d, int C, const double* v, const double* lam,
                           double nu2, double sgn, const double* b, double bsgn, double* out, hipStream_t s);
@@ -35,26 +37,31 @@ struct StepScalars;  // defined in k_vec.hip
 // xp = x + alpha p; rp = r - alpha q   (only for active columns)
 void launch_pcg_candidate(int64_t d, int C, const double* spart, int nwg, const double* lam, double nu2,
                           const double* x, const double* r, const double* p, const double* q,
-                          double* xp, double* rp, double* scal, const int* active, hipStream_t s);
+                          double* xp, double* rp, double* scal, const int* active, hipStream_t s,
+                          const int* gate = nullptr);
 // PCG finish: Dp = rp . rtp per column; test; commit if accepted; stop rule.  See k_vec.hip.
+// gate (optional): read first (0: do nothing), then set to 1 iff the step was accepted, is
+// finite and a column is still active — the gate of the next, speculatively enqueued step.
 void launch_pcg_finish(int64_t d, int C, double* x, double* r, double* p, const double* xp,
-                       const double* rp, const double* rtp, double* scal, int* active, int* flags,
+                       const double* rp, const double* rtp, double* scal, int* active, int* gate,
                        double thr, int force_reject, int adaptive, int at_cap, int stop_rule,
                        double stop_scale, double stop_sr, double tol2, hipStream_t s);
 // PCG (re)initialisation after a factorisation: rt = H_S^{-1} r given; p = rt; D = r.rt; DI = D.
+// gate (optional): set to 1 iff finite and a column is active.  chol_flag (optional): the
+// factorisation's failure flag, copied to flag 6 of the flag block (and closing the gate).
 void launch_pcg_init(int64_t d, int C, const double* r, const double* rt, double* p, double* scal,
-                     int* active, int* flags, int stop_rule, double stop_scale, double stop_sr,
-                     double tol2, const double* x, int set_d0, hipStream_t s);
+                     int* active, int* gate, int stop_rule, double stop_scale, double stop_sr,
+                     double tol2, const double* x, int set_d0, hipStream_t s, const int* chol_flag = nullptr);
 // IHS: xp = x - mu s
 void launch_ihs_candidate(int64_t d, int C, const double* x, const double* sd, double mu, double* xp,
-                          const int* active, hipStream_t s);
+                          const int* active, hipStream_t s, const int* gate = nullptr);
 void launch_ihs_finish(int64_t d, int C, double* x, double* g, double* sd, const double* xp,
-                       const double* gp, const double* sp, double* scal, int* active, int* flags,
+                       const double* gp, const double* sp, double* scal, int* active, int* gate,
                        double thr, int force_reject, int adaptive, int at_cap, int stop_rule,
                        double stop_scale, double stop_sr, double tol2, hipStream_t s);
 void launch_ihs_init(int64_t d, int C, const double* g, const double* sd, double* scal, int* active,
-                     int* flags, int stop_rule, double stop_scale, double stop_sr, double tol2,
-                     const double* x, int set_d0, hipStream_t s);
+                     int* gate, int stop_rule, double stop_scale, double stop_sr, double tol2,
+                     const double* x, int set_d0, hipStream_t s, const int* chol_flag = nullptr);
 
 // ---- triangular / dense GEMV (k_vec.hip) ------------------------------------------------
 // y[i, c] = (ysgn * sum_{j in tri(i)} M[i, j] * xs[j] * x[j, c] + (zadd ? zadd[i, c] : 0))
@@ -62,7 +69,8 @@ void launch_ihs_init(int64_t d, int C, const double* g, const double* sd, double
 // tri: 0 full [0, ncols), 1 lower [0, i], 2 upper [i, ncols)
 void launch_rowdot(int64_t nrows, int64_t ncols, const double* M, int64_t ldm, int tri,
                    const double* x, int C, const double* xs, double ysgn, const double* zadd,
-                   const double* rowscale, double gscale, double* y, hipStream_t s);
+                   const double* rowscale, double gscale, double* y, hipStream_t s,
+                   const int* gate = nullptr);
 
 // ---- misc (k_vec.hip) --------------------------------------------------------------------
 void launch_copy_cols(int64_t rows, int C, const double* src, int64_t lds, int csrc, double* dst,
