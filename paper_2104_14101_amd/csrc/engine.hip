@@ -495,43 +495,56 @@ class Solver {
       launch_pcg_init(d_, C_, R_, RTP_, Pv_, scal_, active_, gate, stop_rule, stop_scale, stop_sr_, tol2_, x, 1, s_,
                       chol_flag_);
     }
-    read_flags();
-    if (fl_[6] != 0.0) throw StatusError(AES_ERR_NOT_SPD, "Cholesky pivot of the sketched Hessian is not positive");
-    if (fl_[2] != 0.0) return AES_ERR_NONFINITE;
+    // Flags of an initialisation: read at once without speculation; with it, the first step is
+    // enqueued behind the initialisation and its flags tell whether it ran (flag 7 = its
+    // sequence number) or whether the initialisation closed the gate.
+    bool after_init = true;
+    auto check_init = [&]() -> aes_status {
+      if (fl_[6] != 0.0) throw StatusError(AES_ERR_NOT_SPD, "Cholesky pivot of the sketched Hessian is not positive");
+      return fl_[2] != 0.0 ? AES_ERR_NONFINITE : AES_OK;
+    };
+    if (!spec) {
+      read_flags();
+      if (check_init() != AES_OK) return AES_ERR_NONFINITE;
+      after_init = false;
+    }
     int64_t t = 0, I = 0;
     bool forced = false;
-    // one enqueued step: its index, forced-rejection flag, flag slot and first H.v event
+    double seq_ctr = 0.0;
+    // one enqueued step: its index, forced-rejection flag, flag slot, first H.v event, stamp
     struct Step {
       int64_t t;
       int force;
       int slot;
       int64_t ev;
+      double seq;
     };
     auto enqueue_step = [&](int64_t tt, int force, int slot) -> Step {
-      const double thr = lc + (double)(tt + 1 - I) * lphi;
+      const double thr = thr_of(lc, lphi, tt, I);
       const int at_cap = m_ >= mcap_ ? 1 : 0;
       const int64_t ev = (o_.profile && !use32 && C_ == 1) ? n_events_ : -1;
+      const double seq = spec ? (seq_ctr += 1.0) : -1.0;
       if (ihs) {
         launch_ihs_candidate(d_, C_, x, Pv_, mu, XP_, active_, s_, gate);
         hv(XP_, RP_, 1.0, rhs, -1.0, use32, gate);
         apply(RP_, RTP_, gate);
         launch_ihs_finish(d_, C_, x, R_, Pv_, XP_, RP_, RTP_, scal_, active_, gate, thr, force, o_.adaptive, at_cap,
-                          stop_rule, stop_scale, stop_sr_, tol2_, s_);
+                          stop_rule, stop_scale, stop_sr_, tol2_, s_, seq);
       } else {
         hv(Pv_, Q_, 1.0, nullptr, 0.0, use32, gate);
         launch_pcg_candidate(d_, C_, C_ == 1 ? spart_ : nullptr, nwg_, lam_, nu2_, x, R_, Pv_, Q_, XP_, RP_, scal_,
                              active_, s_, gate);
         apply(RP_, RTP_, gate);
         launch_pcg_finish(d_, C_, x, R_, Pv_, XP_, RP_, RTP_, scal_, active_, gate, thr, force, o_.adaptive, at_cap,
-                          stop_rule, stop_scale, stop_sr_, tol2_, s_);
+                          stop_rule, stop_scale, stop_sr_, tol2_, s_, seq);
       }
       if (spec) {
         AES_HIP(hipMemcpyAsync(pinned_ + 8 * slot, scal_ + 7 * C_, 8 * sizeof(double), hipMemcpyDeviceToHost, s_));
         AES_HIP(hipEventRecord(flag_event(slot), s_));
       }
-      return Step{tt, force, slot, ev};
+      return Step{tt, force, slot, ev, seq};
     };
-    // a speculatively enqueued step that did not run: its pass and timing event do not count
+    // an enqueued step that did not run: its pass and timing event do not count
     auto discard = [&](const Step& st) {
       --a_passes_;
       if (st.ev >= 0) skip_events_.push_back(st.ev);
@@ -541,9 +554,15 @@ class Solver {
     };
     bool have_next = false;
     Step next{};
-    while (fl_[1] > 0.5) {
+    for (;;) {
+      if (!after_init && fl_[1] <= 0.5) break;  // every column stopped
       if (t >= o_.max_iter) {
         if (have_next) discard(next);
+        if (after_init) {
+          read_flags();
+          if (check_init() != AES_OK) return AES_ERR_NONFINITE;
+          if (fl_[1] <= 0.5) break;
+        }
         return stop_rule == AES_STOP_FIXED ? AES_OK : AES_ERR_MAX_ITER;
       }
       Step cur = have_next ? next : enqueue_step(t, force_at(t, forced), (int)(t & 1));
@@ -556,9 +575,18 @@ class Solver {
       if (spec) {
         AES_HIP(hipEventSynchronize(flag_event(cur.slot)));
         for (int i = 0; i < 8; ++i) fl_[i] = pinned_[8 * cur.slot + i];
+        if (fl_[7] != cur.seq) {
+          // the initialisation before this step closed the gate: its own flags are in the block
+          discard(cur);
+          if (have_next) discard(next);
+          have_next = false;
+          if (check_init() != AES_OK) return AES_ERR_NONFINITE;
+          break;  // stopped at the initialisation
+        }
       } else {
         read_flags();
       }
+      after_init = false;
       if (cur.force) forced = true;
       ++attempts_;
       const bool fail = fl_[0] != 0.0, accepted = fl_[3] != 0.0;
@@ -605,9 +633,12 @@ class Solver {
         launch_pcg_init(d_, C_, R_, RTP_, Pv_, scal_, active_, gate, stop_rule, stop_scale, stop_sr_, tol2_, x, 0, s_,
                         chol_flag_);
       }
-      read_flags();
-      if (fl_[6] != 0.0) throw StatusError(AES_ERR_NOT_SPD, "Cholesky pivot of the sketched Hessian is not positive");
-      if (fl_[2] != 0.0) return AES_ERR_NONFINITE;
+      if (!spec) {
+        read_flags();
+        if (check_init() != AES_OK) return AES_ERR_NONFINITE;
+      } else {
+        after_init = true;
+      }
     }
     if (have_next) discard(next);
     return AES_OK;

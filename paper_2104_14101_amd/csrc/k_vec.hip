@@ -110,7 +110,7 @@ __global__ __launch_bounds__(kVT) void finish_kernel(int64_t d, int C, double* _
                                                      double* __restrict__ scal, int* __restrict__ active,
                                                      int* __restrict__ gate, double thr, int force_reject,
                                                      int adaptive, int at_cap, int stop_rule, double stop_scale,
-                                                     double stop_sr, double tol2) {
+                                                     double stop_sr, double tol2, double seq) {
   if (gate && *gate == 0) return;
   __shared__ double buf[kVT];
   __shared__ double dp_s[64], xn_s[64], rz_s[64];
@@ -164,6 +164,7 @@ __global__ __launch_bounds__(kVT) void finish_kernel(int64_t d, int C, double* _
       int na = 0;
       for (int c = 0; c < C; ++c) na += active[c] != 0;
       scal[7 * C + 1] = (double)na;
+      scal[7 * C + 7] = seq;
       if (gate) *gate = 0;
     }
     return;
@@ -195,6 +196,7 @@ __global__ __launch_bounds__(kVT) void finish_kernel(int64_t d, int C, double* _
     }
     scal[7 * C + 1] = (double)na;
     scal[7 * C + 5] = maxD;
+    scal[7 * C + 7] = seq;
     if (gate) *gate = na > 0 ? 1 : 0;
   }
 }
@@ -202,18 +204,18 @@ __global__ __launch_bounds__(kVT) void finish_kernel(int64_t d, int C, double* _
 void launch_pcg_finish(int64_t d, int C, double* x, double* r, double* p, const double* xp, const double* rp,
                        const double* rtp, double* scal, int* active, int* gate, double thr, int force_reject,
                        int adaptive, int at_cap, int stop_rule, double stop_scale, double stop_sr, double tol2,
-                       hipStream_t s) {
+                       hipStream_t s, double seq) {
   hipLaunchKernelGGL(finish_kernel<false>, dim3(1), dim3(kVT), 0, s, d, C, x, r, p, xp, rp, rtp, scal, active, gate, thr,
-                     force_reject, adaptive, at_cap, stop_rule, stop_scale, stop_sr, tol2);
+                     force_reject, adaptive, at_cap, stop_rule, stop_scale, stop_sr, tol2, seq);
   AES_LAUNCH_CHECK();
 }
 
 void launch_ihs_finish(int64_t d, int C, double* x, double* g, double* sd, const double* xp, const double* gp,
                        const double* sp, double* scal, int* active, int* gate, double thr, int force_reject,
                        int adaptive, int at_cap, int stop_rule, double stop_scale, double stop_sr, double tol2,
-                       hipStream_t s) {
+                       hipStream_t s, double seq) {
   hipLaunchKernelGGL(finish_kernel<true>, dim3(1), dim3(kVT), 0, s, d, C, x, g, sd, xp, gp, sp, scal, active, gate, thr,
-                     force_reject, adaptive, at_cap, stop_rule, stop_scale, stop_sr, tol2);
+                     force_reject, adaptive, at_cap, stop_rule, stop_scale, stop_sr, tol2, seq);
   AES_LAUNCH_CHECK();
 }
 
@@ -269,6 +271,7 @@ __global__ __launch_bounds__(kVT) void init_kernel(int64_t d, int C, const doubl
     // flag 6: the factorisation this initialisation follows met a non-positive pivot
     const bool bad = chol_flag && *chol_flag != 0;
     scal[7 * C + 6] = bad ? 1.0 : 0.0;
+    scal[7 * C + 7] = -1.0;  // no step has run since this initialisation
     if (gate) *gate = (!bad && na > 0 && scal[7 * C + 2] == 0.0) ? 1 : 0;
   }
 }

@@ -42,10 +42,11 @@ void launch_pcg_candidate(int64_t d, int C, const double* spart, int nwg, const 
 // PCG finish: Dp = rp . rtp per column; test; commit if accepted; stop rule.  See k_vec.hip.
 // gate (optional): read first (0: do nothing), then set to 1 iff the step was accepted, is
 // finite and a column is still active — the gate of the next, speculatively enqueued step.
+// seq: written to flag 7 of the flag block when the step runs (the initialisations write -1).
 void launch_pcg_finish(int64_t d, int C, double* x, double* r, double* p, const double* xp,
                        const double* rp, const double* rtp, double* scal, int* active, int* gate,
                        double thr, int force_reject, int adaptive, int at_cap, int stop_rule,
-                       double stop_scale, double stop_sr, double tol2, hipStream_t s);
+                       double stop_scale, double stop_sr, double tol2, hipStream_t s, double seq = -1.0);
 // PCG (re)initialisation after a factorisation: rt = H_S^{-1} r given; p = rt; D = r.rt; DI = D.
 // gate (optional): set to 1 iff finite and a column is active.  chol_flag (optional): the
 // factorisation's failure flag, copied to flag 6 of the flag block (and closing the gate).
@@ -58,7 +59,7 @@ void launch_ihs_candidate(int64_t d, int C, const double* x, const double* sd, d
 void launch_ihs_finish(int64_t d, int C, double* x, double* g, double* sd, const double* xp,
                        const double* gp, const double* sp, double* scal, int* active, int* gate,
                        double thr, int force_reject, int adaptive, int at_cap, int stop_rule,
-                       double stop_scale, double stop_sr, double tol2, hipStream_t s);
+                       double stop_scale, double stop_sr, double tol2, hipStream_t s, double seq = -1.0);
 void launch_ihs_init(int64_t d, int C, const double* g, const double* sd, double* scal, int* active,
                      int* gate, int stop_rule, double stop_scale, double stop_sr, double tol2,
                      const double* x, int set_d0, hipStream_t s, const int* chol_flag = nullptr);

@@ -87,6 +87,30 @@ def test_forced_rejection_and_max_iter(small):
     assert reference.rel_error(x3.cpu().numpy(), xo3) <= 1e-8
 
 
+def test_initialisation_stop_and_error_paths(small):
+    """Paths where the step enqueued behind an initialisation must not run."""
+    # zero right-hand side: the initialisation stops the only column, no step is taken
+    zb = torch.zeros_like(small["db"])
+    x, info = aes.solve(small["dA"], zb, small["nu"], small["dlam"], m_init=8, seed=1, trace_cap=8)
+    xo, io = solvers.adaptive_pcg(small["A"], np.zeros_like(small["b"]), small["nu"], small["lam"],
+                                  solvers.Options(m_init=8, seed=1))
+    assert info["status"] == "ok" and info["attempts"] == 0 and info["trace"] == []
+    assert info["a_passes"] == io.a_passes and float(x.abs().max()) == 0.0
+    # no step allowed
+    x, info = aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], m_init=8, seed=1, max_iter=0)
+    assert info["status"] == "max_iter" and info["attempts"] == 0
+    # a zero column and nu^2 below the smallest double: the Cholesky branch (m >= d) meets a
+    # zero pivot, reported through the solver
+    A = small["A"].copy()
+    A[:, 0] = 0.0
+    with pytest.raises(aes.AesError, match="not_spd"):
+        aes.solve(to_dev(A), small["db"], 1e-200, None, m_init=512, seed=1)
+    # the handle stays usable afterwards and reproduces the plain solve
+    x1, info1 = aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], m_init=8, seed=1)
+    assert info1["status"] == "ok"
+    assert reference.rel_error(x1.cpu().numpy(), small["xref"]) <= 1e-10
+
+
 @pytest.mark.parametrize("stop", ["dtilde_rel", "fixed", "remark"])
 def test_stop_rules(small, stop):
     tol = {"dtilde_rel": 1e-9, "fixed": 1e-10, "remark": 1e-12}[stop]
