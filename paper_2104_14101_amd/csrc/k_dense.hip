@@ -630,8 +630,27 @@ struct LeafInv<64> {
   __device__ __forceinline__ static void step(double (&)[64], LeafLds&, int) {}
 };
 
+// Factorises the 64 x 64 block held in sm.Ls (lower triangle read): on return sm.Ls holds L
+// (zeros above the diagonal), sm.rdiag 1 / L[j][j], and wave 1's x[] column lane of L^{-1}.
+// Wave 0 factorises, wave 1 inverts one 8-row block behind it; further waves of the workgroup
+// only take part in the 8 barriers.  The caller synchronises before and after.
+__device__ __forceinline__ void leaf_run(LeafLds& sm, int tid, bool& bad, double (&x)[64]) {
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  if (wave == 0) {
+    double a[64];
+#pragma unroll
+    for (int j = 0; j < 64; ++j) a[j] = (j <= lane) ? sm.Ls[lane][j] : 0.0;
+    LeafChol<0>::step(a, sm, lane, bad);
+  } else if (wave == 1) {
+    LeafInv<0>::step(x, sm, lane);
+  } else {
+    for (int b = 0; b < 8; ++b) __syncthreads();
+  }
+}
+
 // Leaf: Cholesky factor L (written over G, upper triangle zeroed) and X = L^{-1} of a 64 x 64
-// block, by two wavefronts: wave 0 factorises, wave 1 inverts one 8-row block behind it.
+// block, by two wavefronts.
 __global__ __launch_bounds__(128) void chol_inv_leaf_kernel(double* __restrict__ G, int64_t ld, double* __restrict__ X,
                                                             int64_t ldx, int* __restrict__ flag) {
   __shared__ __attribute__((aligned(16))) LeafLds sm;
@@ -645,23 +664,147 @@ __global__ __launch_bounds__(128) void chol_inv_leaf_kernel(double* __restrict__
     for (int q = 0; q < 32; ++q) sm.Ls[2 * q + (tid >> 6)][lane] = v[q];
   }
   __syncthreads();
+  bool bad = false;
+  double x[64];
+  leaf_run(sm, tid, bad, x);
   if (wave == 0) {
-    double a[64];
-#pragma unroll
-    for (int j = 0; j < 64; ++j) a[j] = (j <= lane) ? sm.Ls[lane][j] : 0.0;
-    bool bad = false;
-    LeafChol<0>::step(a, sm, lane, bad);
     __builtin_amdgcn_s_waitcnt(0xC07F);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll 8
     for (int i = 0; i < 64; ++i) G[(int64_t)i * ld + lane] = sm.Ls[i][lane];
     if (bad && lane == 0) atomicOr(flag, 1);
   } else {
-    double x[64];
-    LeafInv<0>::step(x, sm, lane);
 #pragma unroll
     for (int i = 0; i < 64; ++i) X[(int64_t)i * ldx + lane] = (i >= lane) ? x[i] : 0.0;
   }
+}
+
+// 64 x 64 x 64 product on the workgroup's 4 waves: wave w accumulates rows 16w .. 16w+15,
+// block bj columns 16bj .. 16bj+15; a_at(i, k), b_at(k, j) fetch the operands.
+template <typename FA, typename FB>
+__device__ __forceinline__ void mm64(FA a_at, FB b_at, d4 (&acc)[4], int lane, int wave) {
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) {
+    const int k = kk * 4 + (lane >> 4);
+    const double av = a_at(wave * 16 + (lane & 15), k);
+    double bv[4];
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) bv[bj] = b_at(k, bj * 16 + (lane & 15));
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) acc[bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[bj], acc[bj], 0, 0, 0);
+  }
+}
+
+// Node of the recursion with a 128 x 128 block, in one workgroup of 4 waves: leaf on A11,
+// L21 = A21 X11^T, S = A22 - L21 L21^T, T2 = L21 X11, leaf on S, X21 = -X22 T2.  X (= L^{-1}) is
+// written in full (the caller zero-fills the block above the diagonal); L only if keep_l.
+struct NodeLds {
+  LeafLds leaf;           // the leaves; leaf.Lc doubles as X11 / X22 between them
+  double L21[64][65];
+  double T2[64][65];
+};
+
+__global__ __launch_bounds__(256) void chol_inv_node128_kernel(double* __restrict__ G, int64_t ld,
+                                                               double* __restrict__ X, int64_t ldx,
+                                                               int* __restrict__ flag, int keep_l) {
+  __shared__ __attribute__((aligned(16))) NodeLds sm;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const double* A21 = G + 64 * ld;
+  const double* A22 = G + 64 * ld + 64;
+  bool bad = false;
+  double x[64];
+  // ---- leaf on A11
+  {
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = G[(int64_t)(4 * q + wave) * ld + lane];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) sm.leaf.Ls[4 * q + wave][lane] = v[q];
+  }
+  __syncthreads();
+  leaf_run(sm.leaf, tid, bad, x);
+  __syncthreads();
+  // X11 -> LDS (row-major in leaf.Lc) and X; L11 -> G
+  if (wave == 1) {
+#pragma unroll
+    for (int i = 0; i < 64; ++i) {
+      const double xv = (i >= lane) ? x[i] : 0.0;
+      sm.leaf.Lc[i][lane] = xv;
+      X[(int64_t)i * ldx + lane] = xv;
+    }
+  } else if (wave == 0 && keep_l) {
+#pragma unroll 8
+    for (int i = 0; i < 64; ++i) G[(int64_t)i * ld + lane] = sm.leaf.Ls[i][lane];
+  }
+  __syncthreads();
+  // ---- L21 = A21 X11^T
+  {
+    d4 acc[4];
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) acc[bj] = d4{0.0, 0.0, 0.0, 0.0};
+    mm64([&](int i, int k) { return A21[(int64_t)i * ld + k]; }, [&](int k, int j) { return sm.leaf.Lc[j][k]; }, acc,
+         lane, wave);
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sm.L21[wave * 16 + (lane >> 4) + 4 * r][bj * 16 + (lane & 15)] = acc[bj][r];
+  }
+  __syncthreads();
+  // ---- S = A22 - L21 L21^T (into the leaf's input) and T2 = L21 X11
+  {
+    d4 acc[4];
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[bj][r] = A22[(int64_t)(wave * 16 + (lane >> 4) + 4 * r) * ld + bj * 16 + (lane & 15)];
+    mm64([&](int i, int k) { return -sm.L21[i][k]; }, [&](int k, int j) { return sm.L21[j][k]; }, acc, lane, wave);
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sm.leaf.Ls[wave * 16 + (lane >> 4) + 4 * r][bj * 16 + (lane & 15)] = acc[bj][r];
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) acc[bj] = d4{0.0, 0.0, 0.0, 0.0};
+    mm64([&](int i, int k) { return sm.L21[i][k]; }, [&](int k, int j) { return sm.leaf.Lc[k][j]; }, acc, lane, wave);
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sm.T2[wave * 16 + (lane >> 4) + 4 * r][bj * 16 + (lane & 15)] = acc[bj][r];
+  }
+  if (keep_l) {
+    for (int e = tid; e < 64 * 64; e += 256) G[(int64_t)(64 + e / 64) * ld + e % 64] = sm.L21[e / 64][e % 64];
+  }
+  __syncthreads();
+  // ---- leaf on S
+  leaf_run(sm.leaf, tid, bad, x);
+  __syncthreads();
+  // X22 -> LDS (leaf.Lc) and X; L22 -> G
+  double* X22 = X + 64 * ldx + 64;
+  if (wave == 1) {
+#pragma unroll
+    for (int i = 0; i < 64; ++i) {
+      const double xv = (i >= lane) ? x[i] : 0.0;
+      sm.leaf.Lc[i][lane] = xv;
+      X22[(int64_t)i * ldx + lane] = xv;
+    }
+  } else if (wave == 0 && keep_l) {
+#pragma unroll 8
+    for (int i = 0; i < 64; ++i) G[(int64_t)(64 + i) * ld + 64 + lane] = sm.leaf.Ls[i][lane];
+  }
+  __syncthreads();
+  // ---- X21 = -X22 T2
+  {
+    d4 acc[4];
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) acc[bj] = d4{0.0, 0.0, 0.0, 0.0};
+    mm64([&](int i, int k) { return -sm.leaf.Lc[i][k]; }, [&](int k, int j) { return sm.T2[k][j]; }, acc, lane, wave);
+    double* X21 = X + 64 * ldx;
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) X21[(int64_t)(wave * 16 + (lane >> 4) + 4 * r) * ldx + bj * 16 + (lane & 15)] = acc[bj][r];
+  }
+  if (bad && tid == 0) atomicOr(flag, 1);
 }
 
 __global__ void copy_block_kernel(int64_t rows, int64_t cols, const double* __restrict__ src, int64_t lds,
@@ -676,6 +819,12 @@ static void cholinv_rec(double* G, double* X, int64_t ld, int64_t o, int64_t h, 
                         hipStream_t s) {
   if (h == 64) {
     hipLaunchKernelGGL(chol_inv_leaf_kernel, dim3(1), dim3(128), 0, s, G + o * ld + o, ld, X + o * ld + o, ld, flag);
+    AES_LAUNCH_CHECK();
+    return;
+  }
+  if (h == 128) {
+    hipLaunchKernelGGL(chol_inv_node128_kernel, dim3(1), dim3(256), 0, s, G + o * ld + o, ld, X + o * ld + o, ld, flag,
+                       keep_l ? 1 : 0);
     AES_LAUNCH_CHECK();
     return;
   }
