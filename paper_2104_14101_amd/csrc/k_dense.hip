@@ -300,9 +300,10 @@ void gemm_f32(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, c
 // Gram of the sketch.
 // ---------------------------------------------------------------------------------------
 int gram_splits(int num_cu, int64_t m, int64_t d, bool fp64) {
-  if (fp64 && d >= 128) {
-    // XCD-aware split-K (see gemm_kernel MAP 1): a multiple of 8 splits, as few as keep the
-    // rounds of resident workgroups per XCD (two per CU) within 5% of the best
+  if (!fp64 || d >= 128) {
+    // XCD-aware split-K over 128 x 128 tiles (gemm_kernel MAP 1 and the BF16 Gram): a multiple
+    // of 8 splits, as few as keep the rounds of resident workgroups per XCD (two per CU) within
+    // 5% of the best
     const int64_t nt = ceil_div(d, 128);
     const int64_t tiles = nt * (nt + 1) / 2;
     const int64_t slots = std::max<int64_t>(1, 2 * (int64_t)num_cu / 8);
@@ -313,7 +314,7 @@ int gram_splits(int num_cu, int64_t m, int64_t d, bool fp64) {
       if ((double)ceil_div(tiles * q, slots) / q <= 1.05 * best) return (int)(8 * q);
     return 8;
   }
-  // BF16 Gram: 64 x 64 tiles, two workgroups per CU
+  // FP64 Gram with d < 128 (64 x 64 tiles), two workgroups per CU
   const int64_t tiles = ceil_div(d, BT) * (ceil_div(d, BT) + 1) / 2;
   const int64_t slots = 2 * (int64_t)num_cu;
   const int64_t max_s = std::min<int64_t>(16, std::max<int64_t>(1, m / 256));
@@ -408,63 +409,119 @@ void gram_nt(int64_t m, int64_t d, const double* SA, int64_t ldsa, double nu2, c
 // ---------------------------------------------------------------------------------------
 __device__ __forceinline__ short bf16_bits(__hip_bfloat16 v) { return *reinterpret_cast<short*>(&v); }
 
+// BF16 Gram partials, XCD-aware split-K over lower-triangle 128 x 128 tiles (grid: splits x
+// tiles, split fastest, as the FP64 Gram): part[z][i][j] = sum over split z's rows k of
+// SA[k][i] SA[k][j] in FP32 (i >= j).  4 waves, each a 2 x 2 block of 32 x 32 outputs of
+// v_mfma_f32_32x32x16_bf16 (register r of lane l: row 8(r/4) + 4(l/32) + r%4, column l%32);
+// 32 rows of SA per K-step staged k-major in LDS through 16-byte loads, the next K-step
+// prefetched into registers (double-buffered LDS, one barrier per K-step).
 __global__ __launch_bounds__(256) void gram_bf16_kernel(int64_t m, int64_t d, const __hip_bfloat16* __restrict__ SA,
                                                         int64_t ldsa, int64_t rows_per_split,
-                                                        float* __restrict__ part, int64_t dp) {
-  const int64_t split = blockIdx.z;
+                                                        float* __restrict__ part, int64_t dp, int vec) {
+  constexpr int GT = 128, GK = 32, PADC = GT + 8;
+  typedef short s8v __attribute__((ext_vector_type(8)));
+  typedef float f16v __attribute__((ext_vector_type(16)));
+  const int64_t split = blockIdx.x;
+  const int64_t t = blockIdx.y;
+  int64_t ti = (int64_t)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+  while (ti * (ti + 1) / 2 > t) --ti;
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  const int64_t i0 = ti * GT, j0 = (t - ti * (ti + 1) / 2) * GT;
   const int64_t r_begin = split * rows_per_split;
   int64_t r_end = r_begin + rows_per_split;
   if (r_end > m) r_end = m;
-  const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
-  if (j0 > i0 + 63) return;
-  // k-major staging: Ts[k][c] for the 64 columns of the i tile and the j tile
-  __shared__ short Ti[16][64 + 8], Tj[16][64 + 8];
+  __shared__ __attribute__((aligned(16))) short Ti[2][GK][PADC], Tj[2][GK][PADC];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wm = w >> 1, wn = w & 1;
-  typedef float f16v __attribute__((ext_vector_type(16)));
-  f16v accv = {};
-  for (int64_t k0 = r_begin; k0 < r_end; k0 += 16) {
+  const bool full_cols = vec && i0 + GT <= d && j0 + GT <= d;
+  f16v acc[2][2];
 #pragma unroll
-    for (int rep = 0; rep < 4; ++rep) {
-      const int idx = tid + rep * 256;  // 0..1023 : 16 rows x 64 cols
-      const int k = idx >> 6, c = idx & 63;
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = f16v{};
+  s8v ra[2], rb[2];
+  // thread's two 16-byte pieces of each operand: row k = idx / 16, columns c8 .. c8 + 7
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int idx = tid + 256 * q;
+      const int k = idx >> 4, c8 = (idx & 15) * 8;
       const int64_t gk = k0 + k;
-      short vi = 0, vj = 0;
-      if (gk < r_end) {
-        if (i0 + c < d) vi = bf16_bits(SA[gk * ldsa + i0 + c]);
-        if (j0 + c < d) vj = bf16_bits(SA[gk * ldsa + j0 + c]);
-      }
-      Ti[k][c] = vi;
-      Tj[k][c] = vj;
-    }
-    __syncthreads();
-    s8 a, b;
-    const int kb = 8 * (lane >> 5);
+      if (gk < r_end && full_cols) {
+        ra[q] = *reinterpret_cast<const s8v*>(SA + gk * ldsa + i0 + c8);
+        rb[q] = *reinterpret_cast<const s8v*>(SA + gk * ldsa + j0 + c8);
+      } else {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      a[e] = Ti[kb + e][wm * 32 + (lane & 31)];
-      b[e] = Tj[kb + e][wn * 32 + (lane & 31)];
+        for (int e = 0; e < 8; ++e) {
+          ra[q][e] = (gk < r_end && i0 + c8 + e < d) ? bf16_bits(SA[gk * ldsa + i0 + c8 + e]) : (short)0;
+          rb[q][e] = (gk < r_end && j0 + c8 + e < d) ? bf16_bits(SA[gk * ldsa + j0 + c8 + e]) : (short)0;
+        }
+      }
     }
-    accv = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(b8, a), __builtin_bit_cast(b8, b), accv, 0, 0, 0);
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int idx = tid + 256 * q;
+      const int k = idx >> 4, c8 = (idx & 15) * 8;
+      *reinterpret_cast<s8v*>(&Ti[buf][k][c8]) = ra[q];
+      *reinterpret_cast<s8v*>(&Tj[buf][k][c8]) = rb[q];
+    }
+  };
+  if (r_begin < r_end) {
+    load(r_begin);
+    store(0);
     __syncthreads();
+    int cur = 0;
+    for (int64_t k0 = r_begin; k0 < r_end; k0 += GK) {
+      const bool more = k0 + GK < r_end;
+      if (more) load(k0 + GK);
+#pragma unroll
+      for (int ks = 0; ks < GK / 16; ++ks) {
+        const int kb = ks * 16 + 8 * (lane >> 5);
+        s8 a[2], b[2];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) a[bi][e] = Ti[cur][kb + e][wm * 64 + bi * 32 + (lane & 31)];
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) b[bj][e] = Tj[cur][kb + e][wn * 64 + bj * 32 + (lane & 31)];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj)
+            acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(b8, a[bi]),
+                                                                  __builtin_bit_cast(b8, b[bj]), acc[bi][bj], 0, 0, 0);
+      }
+      if (more) store(cur ^ 1);
+      __syncthreads();
+      cur ^= 1;
+    }
   }
   float* out = part + split * dp * dp;
-  // D layout of 32x32 MFMA: register r of lane l: row = 8*(r/4) + 4*(l/32) + (r%4), col = l%32
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int64_t i = i0 + wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-    const int64_t j = j0 + wn * 32 + (lane & 31);
-    if (i < d && j < d && i >= j) out[i * dp + j] = accv[r];
-  }
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t i = i0 + wm * 64 + bi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int64_t j = j0 + wn * 64 + bj * 32 + (lane & 31);
+        if (i < d && j < d && i >= j) out[i * dp + j] = acc[bi][bj][r];
+      }
 }
 
 void gram_tn_bf16(int64_t m, int64_t d, const __hip_bfloat16* SA, int64_t ldsa, double nu2, const double* lam,
                   float* part, int splits, double* G, int64_t dp, hipStream_t s) {
-  const int64_t rows = round_up(ceil_div(m, splits), 16);
-  const int used = (int)ceil_div(m, rows);
-  dim3 grid((unsigned)ceil_div(d, 64), (unsigned)ceil_div(d, 64), (unsigned)used);
-  hipLaunchKernelGGL(gram_bf16_kernel, grid, dim3(256), 0, s, m, d, SA, ldsa, rows, part, dp);
+  // split z: rows [z rows, min(m, (z+1) rows)), rows a multiple of the 32-row K-step
+  const int64_t rows = round_up(ceil_div(m, splits), 32);
+  const int64_t nt = ceil_div(d, 128);
+  const int vec = ((uintptr_t)SA % 16 == 0) && ldsa % 8 == 0;
+  dim3 grid((unsigned)splits, (unsigned)(nt * (nt + 1) / 2));
+  hipLaunchKernelGGL(gram_bf16_kernel, grid, dim3(256), 0, s, m, d, SA, ldsa, rows, part, dp, vec);
   AES_LAUNCH_CHECK();
-  hipLaunchKernelGGL(gram_reduce_kernel<float>, dim3((unsigned)ceil_div(dp * dp, 256)), dim3(256), 0, s, part, used, d,
+  hipLaunchKernelGGL(gram_reduce_kernel<float>, dim3((unsigned)ceil_div(dp * dp, 256)), dim3(256), 0, s, part, splits, d,
                      dp, nu2, lam, G);
   AES_LAUNCH_CHECK();
 }
