@@ -202,7 +202,10 @@ class Solver {
       part_ = B<double>("part", (size_t)nwg_ * d_);
       spart_ = B<double>("spart", nwg_);
     } else {
-      const int64_t split_rows = std::max<int64_t>(4096, ceil_div(n_, 64));
+      // row splits of A^T Z: about four workgroups (of 128 columns) per CU in flight
+      const int64_t col_tiles = ceil_div(d_, 128);
+      const int64_t want = std::max<int64_t>(1, 4 * (int64_t)h_->num_cu / col_tiles);
+      const int64_t split_rows = round_up(std::max<int64_t>(512, ceil_div(n_, want)), 32);
       msplit_ = (int)ceil_div(n_, split_rows);
       msplit_rows_ = split_rows;
       part_ = B<double>("part", (size_t)msplit_ * d_ * C_);
