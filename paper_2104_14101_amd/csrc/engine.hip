@@ -418,9 +418,9 @@ class Solver {
         double* part = B<double>("ap_part", (size_t)S * np * C_);
         if (np > d_) launch_fill(zp + d_ * C_, (np - d_) * C_, 0.0, s_);
         AES_HIP(hipMemcpyAsync(zp, z, d_ * C_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
-        gemm_f64(false, false, np, C_, Ks, 1.0, Linv_, np, Ks, zp, C_, Ks * C_, 0.0, part, C_, np * C_, S, 0, s_);
+        gemm_f64(false, false, np, C_, Ks, 1.0, Linv_, np, Ks, zp, C_, Ks * C_, 0.0, part, C_, np * C_, S, 0, s_, 1, Ks);
         launch_sum_parts(np * C_, S, np * C_, part, tp, s_);
-        gemm_f64(false, false, np, C_, Ks, 1.0, LinvT_, np, Ks, tp, C_, Ks * C_, 0.0, part, C_, np * C_, S, 0, s_);
+        gemm_f64(false, false, np, C_, Ks, 1.0, LinvT_, np, Ks, tp, C_, Ks * C_, 0.0, part, C_, np * C_, S, 0, s_, 2, Ks);
         launch_sum_parts(d_ * C_, S, np * C_, part, v, s_);
       } else {
         launch_rowdot(d_, d_, Linv_, fp_, 1, z, C_, nullptr, 1.0, nullptr, nullptr, 1.0, t1, s_, gate);

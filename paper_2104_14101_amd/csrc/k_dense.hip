@@ -89,7 +89,8 @@ template <typename T, bool TA, bool TB, int BM, int BN, int BK, int MAP = 0>
 __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
                                                    const T* __restrict__ A, int64_t lda, int64_t sA,
                                                    const T* __restrict__ B, int64_t ldb, int64_t sB, double beta,
-                                                   T* C, int64_t ldc, int64_t sC, int tri, int vec, int64_t ksplit) {
+                                                   T* C, int64_t ldc, int64_t sC, int tri, int vec, int64_t ksplit,
+                                                   int atri) {
   typedef Mfma16<T> MF;
   typedef typename MF::acc_t acc_t;
   // Each thread moves VW consecutive elements (16 bytes) along the contiguous direction of the
@@ -121,8 +122,19 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
   B += bz * sB;
   C += bz * sC;
   if (tri && n0 > m0 + BM - 1) return;
+  // atri (MAP 0, split-K with batch z covering global k = z ksplit + local k): A lower (1) or
+  // upper (2) triangular, so only local k in [kbeg, kend) can meet nonzeros of the row tile
+  int64_t kbeg = 0;
+  if (MAP == 0 && atri == 1) {
+    const int64_t e = m0 + BM - bz * ksplit;
+    K = e < K ? (e < 0 ? 0 : e) : K;
+  } else if (MAP == 0 && atri == 2) {
+    const int64_t b0 = m0 - bz * ksplit;
+    kbeg = b0 > 0 ? (b0 / BK) * BK : 0;
+    if (kbeg > K) kbeg = K;
+  }
   // interior tile with 16-byte aligned rows (vec: alignment checked by the host) and whole K-steps
-  const bool interior = vec && m0 + BM <= M && n0 + BN <= N && K > 0 && K % BK == 0;
+  const bool interior = vec && m0 + BM <= M && n0 + BN <= N && K > kbeg && (K - kbeg) % BK == 0;
   __shared__ T As[2][BK][BM + 1], Bs[2][BK][BN + 1];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wm = w >> 1, wn = w & 1;
   acc_t acc[WI][WJ];
@@ -199,11 +211,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
         Bs[buf][k][j] = rb[q * VW + e];
       }
   };
-  load(0);
+  load(kbeg);
   store(0);
   __syncthreads();
   int cur = 0;
-  for (int64_t k0 = 0; k0 < K; k0 += BK) {
+  for (int64_t k0 = kbeg; k0 < K; k0 += BK) {
     const bool more = k0 + BK < K;
     if (more) load(k0 + BK);
 #pragma unroll
@@ -242,7 +254,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
 template <typename T, bool TA, bool TB>
 static void gemm_dispatch(int64_t M, int64_t N, int64_t K, double alpha, const T* A, int64_t lda, int64_t sA,
                           const T* B, int64_t ldb, int64_t sB, double beta, T* C, int64_t ldc, int64_t sC, int batch,
-                          int tri, hipStream_t s) {
+                          int tri, hipStream_t s, int atri, int64_t kofs) {
   const int64_t tiles128 = ceil_div(M, 128) * ceil_div(N, 128) * batch;
   // 16-byte vector loads need 16-byte aligned operand rows and whole K-steps (32 elements
   // covers every configuration's K-step)
@@ -254,21 +266,21 @@ static void gemm_dispatch(int64_t M, int64_t N, int64_t K, double alpha, const T
     constexpr int BKS = sizeof(T) == 8 ? 16 : 32;
     dim3 grid(1u, (unsigned)ceil_div(M, 128), (unsigned)batch);
     hipLaunchKernelGGL((gemm_kernel<T, TA, TB, 128, 32, BKS>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B,
-                       ldb, sB, beta, C, ldc, sC, tri, vec, (int64_t)0);
+                       ldb, sB, beta, C, ldc, sC, tri, vec, kofs, atri);
   } else if (M >= 128 && N >= 128 && tiles128 >= 128) {
     dim3 grid((unsigned)ceil_div(N, 128), (unsigned)ceil_div(M, 128), (unsigned)batch);
     hipLaunchKernelGGL((gemm_kernel<T, TA, TB, 128, 128, 16>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B,
-                       ldb, sB, beta, C, ldc, sC, tri, vec, (int64_t)0);
+                       ldb, sB, beta, C, ldc, sC, tri, vec, kofs, atri);
   } else if (ceil_div(M, 64) * ceil_div(N, 64) * batch >= 512) {
     dim3 grid((unsigned)ceil_div(N, 64), (unsigned)ceil_div(M, 64), (unsigned)batch);
     hipLaunchKernelGGL((gemm_kernel<T, TA, TB, 64, 64, 32>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B,
-                       ldb, sB, beta, C, ldc, sC, tri, vec, (int64_t)0);
+                       ldb, sB, beta, C, ldc, sC, tri, vec, kofs, atri);
   } else {
     // small products (the lower levels of the recursive factorisation): 32 x 32 tiles spread
     // the work over four times as many CUs
     dim3 grid((unsigned)ceil_div(N, 32), (unsigned)ceil_div(M, 32), (unsigned)batch);
     hipLaunchKernelGGL((gemm_kernel<T, TA, TB, 32, 32, 32>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B,
-                       ldb, sB, beta, C, ldc, sC, tri, vec, (int64_t)0);
+                       ldb, sB, beta, C, ldc, sC, tri, vec, kofs, atri);
   }
   AES_LAUNCH_CHECK();
 }
@@ -276,24 +288,28 @@ static void gemm_dispatch(int64_t M, int64_t N, int64_t K, double alpha, const T
 template <typename T>
 static void gemm_any(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const T* A, int64_t lda,
                      int64_t sA, const T* B, int64_t ldb, int64_t sB, double beta, T* C, int64_t ldc, int64_t sC,
-                     int batch, int tri, hipStream_t s) {
+                     int batch, int tri, hipStream_t s, int atri, int64_t kofs) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
-  if (!ta && !tb) gemm_dispatch<T, false, false>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tri, s);
-  else if (!ta && tb) gemm_dispatch<T, false, true>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tri, s);
-  else if (ta && !tb) gemm_dispatch<T, true, false>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tri, s);
-  else gemm_dispatch<T, true, true>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tri, s);
+  if (!ta && !tb)
+    gemm_dispatch<T, false, false>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tri, s, atri, kofs);
+  else if (!ta && tb)
+    gemm_dispatch<T, false, true>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tri, s, atri, kofs);
+  else if (ta && !tb)
+    gemm_dispatch<T, true, false>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tri, s, atri, kofs);
+  else
+    gemm_dispatch<T, true, true>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tri, s, atri, kofs);
 }
 
 void gemm_f64(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
               int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta, double* C, int64_t ldc, int64_t sC,
-              int batch, int tri, hipStream_t s) {
-  gemm_any<double>(ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tri, s);
+              int batch, int tri, hipStream_t s, int atri, int64_t kofs) {
+  gemm_any<double>(ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tri, s, atri, kofs);
 }
 
 void gemm_f32(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const float* A, int64_t lda,
               int64_t sA, const float* B, int64_t ldb, int64_t sB, double beta, float* C, int64_t ldc, int64_t sC,
               int batch, int tri, hipStream_t s) {
-  gemm_any<float>(ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tri, s);
+  gemm_any<float>(ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tri, s, 0, 0);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -352,7 +368,7 @@ void gram_tn(int64_t m, int64_t d, const double* SA, int64_t ldsa, double nu2, c
     const int vec = ((uintptr_t)SA % 16 == 0) && ldsa % 2 == 0;
     dim3 grid((unsigned)splits, (unsigned)(nt * (nt + 1) / 2));
     hipLaunchKernelGGL((gemm_kernel<double, true, false, 128, 128, 16, 1>), grid, dim3(256), 0, s, d, d, m, 1.0, SA,
-                       ldsa, rows * ldsa, SA, ldsa, rows * ldsa, 0.0, part, dp, dp * dp, 1, vec, rows);
+                       ldsa, rows * ldsa, SA, ldsa, rows * ldsa, 0.0, part, dp, dp * dp, 1, vec, rows, 0);
     AES_LAUNCH_CHECK();
   } else {
     const int full = (int)(m / rows);

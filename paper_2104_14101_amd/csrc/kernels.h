@@ -110,9 +110,11 @@ void launch_gauss_sketch(const double* A, int64_t n, int64_t d, int64_t lda, int
 // ---- dense linear algebra on MFMA (k_dense.hip) ------------------------------------------
 // C = alpha * opA(A) * opB(B) + beta * C, batched with element strides; tri = 1 writes only
 // elements with row >= col (and skips tiles strictly above the diagonal).
+// atri (split-K products, batch z covering global k = z kofs + local k): A lower (1) or upper (2)
+// triangular — K-blocks of zeros are not read; a batch entry with none left writes zeros.
 void gemm_f64(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
               int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta, double* C,
-              int64_t ldc, int64_t sC, int batch, int tri, hipStream_t s);
+              int64_t ldc, int64_t sC, int batch, int tri, hipStream_t s, int atri = 0, int64_t kofs = 0);
 void gemm_f32(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const float* A,
               int64_t lda, int64_t sA, const float* B, int64_t ldb, int64_t sB, double beta, float* C,
               int64_t ldc, int64_t sC, int batch, int tri, hipStream_t s);
