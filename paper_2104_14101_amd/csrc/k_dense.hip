@@ -350,7 +350,16 @@ __global__ void gram_reduce_kernel(const TP* __restrict__ part, int splits, int6
   const int64_t i = e / dp, j = e % dp;
   double v = 0.0;
   if (i < d && j < d && i >= j) {
-    for (int s = 0; s < splits; ++s) v += (double)part[(int64_t)s * dp * dp + i * dp + j];
+    // eight partials in flight per thread; summed in split order
+    int s = 0;
+    for (; s + 8 <= splits; s += 8) {
+      TP x[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) x[q] = part[(int64_t)(s + q) * dp * dp + i * dp + j];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v += (double)x[q];
+    }
+    for (; s < splits; ++s) v += (double)part[(int64_t)s * dp * dp + i * dp + j];
     if (i == j) v += nu2 * (lam ? lam[i] : 1.0);
   } else if (i == j) {
     v = 1.0;
