@@ -339,7 +339,9 @@ class Solver {
                                                   B<int32_t>("need", 512), s_);
       }
     } else {
-      launch_gauss_sketch(P_.A, n_, d_, P_.lda, m_, o_.seed, o_.problem, k_, SA_, d_, s_);
+      const GaussPlan gp = gauss_plan(h_->num_cu, n_, d_, m_);
+      launch_gauss_sketch(gp, P_.A, n_, d_, P_.lda, m_, o_.seed, o_.problem, k_, SA_, B<double>("gauss_gt", gp.gt_elems),
+                          gp.part_elems ? B<double>("gauss_part", gp.part_elems) : nullptr, s_);
     }
     int* flag = B<int>("chol_flag", 1);
     AES_HIP(hipMemsetAsync(flag, 0, sizeof(int), s_));
@@ -1242,7 +1244,9 @@ aes_status aes_sketch(aes_handle h, void* stream, int kind, int64_t n, int64_t d
       launch_srht_apply<double, double, double>(A, n, d, lda, eps, npad, sc.pos, m, Y, SA, d,
                                                 h->buf<int32_t>("sk.need", 512), s);
     } else if (kind == AES_GAUSS) {
-      launch_gauss_sketch(A, n, d, lda, m, seed, problem, k, SA, d, s);
+      const GaussPlan gp = gauss_plan(h->num_cu, n, d, m);
+      launch_gauss_sketch(gp, A, n, d, lda, m, seed, problem, k, SA, h->buf<double>("sk.gt", gp.gt_elems),
+                          gp.part_elems ? h->buf<double>("sk.part", gp.part_elems) : nullptr, s);
     } else {
       throw StatusError(AES_ERR_INVALID_ARG, "unknown sketch kind");
     }

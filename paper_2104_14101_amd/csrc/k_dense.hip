@@ -943,54 +943,68 @@ void cholinv(double* G, int64_t np, double* Linv, double* tmp, int* flag, bool k
 }
 
 // ---------------------------------------------------------------------------------------
-// Gaussian sketch: SA (m x d) = G A / sqrt(m), G generated per K-step in LDS.
+// Gaussian sketch: SA (m x d) = G A / sqrt(m) with G_ij ~ N(0, 1) (Sec. 2.1).  Each entry of G
+// is generated exactly once per sketch: a slab of K-rows at a time goes into the K-major buffer
+// Gt (row r holds G[0..m, i0 + r]), and the slab is contracted with the same rows of A by the
+// FP64 MFMA GEMM (the layout of the Gram, opA = Gt^T).  When the m x d output has too few
+// tiles to fill the chip, the slab is cut into a batch of K-ranges writing partial products
+// that are summed at the end in a fixed order.
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void gauss_sketch_kernel(const double* __restrict__ A, int64_t n, int64_t d,
-                                                           int64_t lda, int64_t m, uint64_t k0key, uint64_t k1key,
-                                                           double scale, double* __restrict__ SA, int64_t ldsa) {
-  const int64_t m0 = (int64_t)blockIdx.y * BT, n0 = (int64_t)blockIdx.x * BT;
-  __shared__ double As[BKT][BT + 1], Bs[BKT][BT + 1];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wm = w >> 1, wn = w & 1;
-  d4 acc[2][2];
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
-  const int gk_local = tid & 15, gq = tid >> 4;  // column of G in the K-step, row quad
-  for (int64_t k0 = 0; k0 < n; k0 += BKT) {
-    {
-      const int64_t i = k0 + gk_local;
-      double z[4] = {0.0, 0.0, 0.0, 0.0};
-      if (i < n) {
-        const Rand4 r = philox4x64_10((uint64_t)i, kStreamGauss, (uint64_t)(m0 / 4 + gq), 0, k0key, k1key);
-        gauss4(r, z);
-      }
-#pragma unroll
-      for (int e = 0; e < 4; ++e) As[gk_local][4 * gq + e] = z[e];
-    }
-#pragma unroll
-    for (int rep = 0; rep < 4; ++rep) {
-      const int idx = tid + rep * 256;
-      const int j = idx & 63, k = idx >> 6;
-      const int64_t gj = n0 + j, gk = k0 + k;
-      Bs[k][j] = (gj < d && gk < n) ? A[gk * lda + gj] : 0.0;
-    }
-    __syncthreads();
-    mfma_ktile(As, Bs, lane, wm, wn, acc);
-    __syncthreads();
+__global__ __launch_bounds__(256) void gauss_gen_kernel(int64_t i0, int64_t rows, int64_t nq, int64_t mp,
+                                                        uint64_t k0key, uint64_t k1key, double* __restrict__ Gt) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= nq) return;
+  for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) {
+    // four consecutive rows of G (4q .. 4q + 3) in column i0 + r come from one Philox block
+    const Rand4 rn = philox4x64_10((uint64_t)(i0 + r), kStreamGauss, (uint64_t)q, 0, k0key, k1key);
+    double z[4];
+    gauss4(rn, z);
+    double2* dst = reinterpret_cast<double2*>(Gt + r * mp + 4 * q);
+    dst[0] = make_double2(z[0], z[1]);
+    dst[1] = make_double2(z[2], z[3]);
   }
-  store_tile(acc, lane, wm, wn, m0, n0, [&](int64_t i, int64_t j, double v) {
-    if (i < m && j < d) SA[i * ldsa + j] = v * scale;
-  });
 }
 
-void launch_gauss_sketch(const double* A, int64_t n, int64_t d, int64_t lda, int64_t m, uint64_t seed, int32_t problem,
-                         int64_t k, double* SA, int64_t ldsa, hipStream_t s) {
+GaussPlan gauss_plan(int num_cu, int64_t n, int64_t d, int64_t m) {
+  GaussPlan p;
+  p.mp = round_up(m, 4);
+  const int64_t tiles = ceil_div(m, 128) * ceil_div(d, 128);
+  int64_t splits = std::min<int64_t>(64, std::max<int64_t>(1, ceil_div(2 * (int64_t)num_cu, tiles)));
+  splits = std::min(splits, ceil_div(n, 64));
+  // at most 2^25 generated entries resident at once (256 MiB)
+  constexpr int64_t kBudget = int64_t(1) << 25;
+  const int64_t cap = std::max<int64_t>(64, kBudget / (splits * p.mp) / 64 * 64);
+  p.ks = std::min(round_up(ceil_div(n, splits), 64), cap);
+  // every K-range of the first slab holds rows, so that slab initialises every output
+  p.splits = (int)std::min(splits, ceil_div(n, p.ks));
+  p.gt_elems = (size_t)p.splits * p.ks * p.mp;
+  p.part_elems = p.splits > 1 ? (size_t)p.splits * m * d : 0;
+  return p;
+}
+
+void launch_gauss_sketch(const GaussPlan& p, const double* A, int64_t n, int64_t d, int64_t lda, int64_t m,
+                         uint64_t seed, int32_t problem, int64_t k, double* SA, double* gt, double* part,
+                         hipStream_t s) {
   const RngKey key = make_key(seed, problem, k);
-  dim3 grid((unsigned)ceil_div(d, BT), (unsigned)ceil_div(m, BT));
-  hipLaunchKernelGGL(gauss_sketch_kernel, grid, dim3(256), 0, s, A, n, d, lda, m, key.k0, key.k1,
-                     1.0 / std::sqrt((double)m), SA, ldsa);
-  AES_LAUNCH_CHECK();
+  const double alpha = 1.0 / std::sqrt((double)m);
+  const int S = p.splits;
+  double* out = S > 1 ? part : SA;
+  const int64_t slab = (int64_t)S * p.ks, nq = p.mp / 4, md = m * d;
+  for (int64_t base = 0; base < n; base += slab) {
+    const int64_t rows = std::min(slab, n - base);
+    dim3 grid((unsigned)ceil_div(nq, 256), (unsigned)std::min<int64_t>(rows, 16384));
+    hipLaunchKernelGGL(gauss_gen_kernel, grid, dim3(256), 0, s, base, rows, nq, p.mp, key.k0, key.k1, gt);
+    AES_LAUNCH_CHECK();
+    const double beta = base > 0 ? 1.0 : 0.0;
+    const int64_t full = rows / p.ks, rem = rows % p.ks;
+    if (full > 0)
+      gemm_f64(true, false, m, d, p.ks, alpha, gt, p.mp, p.ks * p.mp, A + base * lda, lda, p.ks * lda, beta, out, d,
+               md, (int)full, 0, s);
+    if (rem > 0)
+      gemm_f64(true, false, m, d, rem, alpha, gt + full * p.ks * p.mp, p.mp, 0, A + (base + full * p.ks) * lda, lda,
+               0, beta, out + full * md, d, 0, 1, 0, s);
+  }
+  if (S > 1) launch_sum_parts(md, S, md, part, SA, s);
 }
 
 }  // namespace aes

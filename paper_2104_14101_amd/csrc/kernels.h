@@ -104,8 +104,19 @@ size_t srht_scratch_elems(int64_t npad, int64_t d);
 template <typename TIN, typename TY, typename TOUT>
 void launch_srht_apply(const TIN* A, int64_t n, int64_t d, int64_t lda, const double* eps, int64_t npad,
                        const int32_t* pos, int64_t m, TY* Y, TOUT* SA, int64_t ldsa, int32_t* need, hipStream_t s);
-void launch_gauss_sketch(const double* A, int64_t n, int64_t d, int64_t lda, int64_t m, uint64_t seed,
-                         int32_t problem, int64_t k, double* SA, int64_t ldsa, hipStream_t s);
+// Gaussian sketch SA (m x d, ld d) = G A / sqrt(m): the plan sizes the generated slab of G
+// (gt_elems doubles) and the split-K partials (part_elems doubles, none with one split).
+struct GaussPlan {
+  int splits;
+  int64_t ks;    // K-rows per split and slab
+  int64_t mp;    // leading dimension of the slab (m rounded up to 4)
+  size_t gt_elems;
+  size_t part_elems;
+};
+GaussPlan gauss_plan(int num_cu, int64_t n, int64_t d, int64_t m);
+void launch_gauss_sketch(const GaussPlan& p, const double* A, int64_t n, int64_t d, int64_t lda, int64_t m,
+                         uint64_t seed, int32_t problem, int64_t k, double* SA, double* gt, double* part,
+                         hipStream_t s);
 
 // ---- dense linear algebra on MFMA (k_dense.hip) ------------------------------------------
 // C = alpha * opA(A) * opB(B) + beta * C, batched with element strides; tri = 1 writes only

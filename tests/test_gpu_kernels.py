@@ -85,7 +85,8 @@ def test_srht_full_size_sampled_rows():
         assert np.max(np.abs(SA[j] - ref)) <= 1e-13 * np.max(np.abs(ref)) * 16
 
 
-@pytest.mark.parametrize("n,d,m", [(300, 40, 70), (1000, 65, 128), (129, 7, 3)])
+# (2000, 130, 512): 32 split-K ranges, the last one ragged
+@pytest.mark.parametrize("n,d,m", [(300, 40, 70), (1000, 65, 128), (129, 7, 3), (2000, 130, 512)])
 def test_gaussian_sketch(n, d, m):
     rng = np.random.default_rng(6)
     A = rng.standard_normal((n, d))
@@ -93,6 +94,19 @@ def test_gaussian_sketch(n, d, m):
     ref = osk.gaussian(A, m, 8, 2)
     # G entries agree to a few ulps (device and host libm), sums of n terms
     assert np.max(np.abs(SA - ref)) <= 1e-13 * np.sqrt(n) * np.max(np.abs(ref)) + 1e-14
+
+
+# (10000, 256, 8192): three generated slabs of four split-K ranges, the last slab ragged;
+# (65536, 2048, 16383): the bench workload's largest sketch (32 slabs, one split, m ragged)
+@pytest.mark.parametrize("n,d,m", [(10000, 256, 8192), (65536, 2048, 16383)])
+def test_gaussian_sampled_rows(n, d, m):
+    P = synth.make_problem(n, d, "pow:1", 1e-3, seed=13, backend="torch", device="cuda")
+    A = P["A"]
+    SA = aes.sketch(A, m, "gauss", seed=9, k=3).cpu().numpy()
+    An = A.cpu().numpy()
+    rows = np.array([0, 1, 5, m // 2 + 3, m - 1])
+    ref = philox.gaussian_rows(9, 3, rows, 0, n) @ An / np.sqrt(m)
+    assert np.max(np.abs(SA[rows] - ref)) <= 1e-13 * np.sqrt(n) * np.max(np.abs(ref)) + 1e-14
 
 
 @pytest.mark.parametrize("m,d", [(200, 100), (100, 100), (37, 100), (1, 5), (300, 257), (129, 130)])
