@@ -18,6 +18,9 @@ without replacement" and "i.i.d. N(0, 1/m)" in Sec. 2.1):
   GAUSS   counter (i, 3, r >> 2, 0): the four words give four N(0,1) values for sketch rows
           4*(r>>2) .. 4*(r>>2)+3 of data column i, by the Box-Muller transform on the word
           pairs (w0, w1) and (w2, w3).
+  SJLT    counter (i, 4, 0, 0): column i of S has its one non-zero in row
+          h_i = floor(w0 * m / 2^64) (the high word of the 128-bit product, uniform on
+          [0, m) up to m / 2^64), with value -1 iff bit 63 of w1 is set, else +1.
 """
 import numpy as np
 
@@ -28,7 +31,7 @@ _W1 = np.uint64(0xBB67AE8584CAA73B)
 _MASK32 = np.uint64(0xFFFFFFFF)
 _S32 = np.uint64(32)
 
-SIGN, ROW, GAUSS = 1, 2, 3
+SIGN, ROW, GAUSS, SJLT = 1, 2, 3, 4
 
 
 def _mulhilo(a, b):
@@ -113,3 +116,14 @@ def gaussian_rows(seed, k, rows, i0, i1, problem=0):
     rad = np.sqrt(-2.0 * np.log(ua))
     ang = 2.0 * np.pi * ub
     return np.where((sel & 1) == 0, rad * np.cos(ang), rad * np.sin(ang))
+
+
+def sjlt_hash(seed, k, n, m, problem=0):
+    """Row h_i in [0, m) and sign of the single non-zero of column i < n of an SJLT (s = 1)."""
+    k0, k1 = stream_key(seed, k, problem)
+    i = np.arange(n, dtype=np.uint64)
+    w0, w1, _, _ = philox4x64(i, SJLT, 0, 0, k0, k1)
+    with np.errstate(over="ignore"):
+        hi, _ = _mulhilo(w0, np.full_like(w0, np.uint64(m)))
+    sgn = np.where((w1 >> np.uint64(63)) != 0, -1.0, 1.0)
+    return hi.astype(np.int64), sgn

@@ -13,9 +13,15 @@ H_unnorm[i, j] = (-1)^popcount(i & j) is the Sylvester (natural) ordering.
 
 Gaussian (Sec. 2.1): S has i.i.d. N(0, 1/m) entries, S = G / sqrt(m).
 
+SJLT with s = 1 (Sec. 2.1): every column of S has exactly one non-zero, in a uniformly random
+row, equal to +-1 with equal probability (1/sqrt(s) = 1), so S^T S has a unit diagonal and
+E[S^T S] = I; S A adds each signed row of A into its row of the sketch.
+
 Pins (tests/test_oracle_sketch.py): FWHT == scipy.linalg.hadamard(n') @ X, H^2 = n' I,
 bit-exact on integer data; m = n' SRHT gives (SA)^T SA = A^T A; Monte-Carlo E[S^T S] = I for
-both embeddings; uniform marginals of the row sample; Gaussian moments.
+the three embeddings; uniform marginals of the row sample; Gaussian moments; the SJLT as a dense
+S with one +-1 per column, its hash against big-integer arithmetic, uniform buckets and the
+closed-form second moment of U^T S^T S U - I.
 """
 import numpy as np
 
@@ -104,6 +110,22 @@ def gaussian(A, m, seed, k, problem=0, chunk=4096):
     return out / np.sqrt(m)
 
 
+def sjlt(A, m, seed, k, problem=0):
+    """S A for an SJLT with s = 1 of size m x n (Sec. 2.1); A is n x d, returns m x d float64.
+
+    Row r of S A is the sum, in increasing data-row order starting from zero, of sigma_i A_i
+    over the rows i hashed to r.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    n, d = A.shape
+    if m < 1:
+        raise ValueError("SJLT sketch size must be positive")
+    h, sgn = philox.sjlt_hash(seed, k, n, m, problem)
+    out = np.zeros((m, d))
+    np.add.at(out, h, sgn[:, None] * A)  # unbuffered: applied row by row in order of i
+    return out
+
+
 def gaussian_cols(seed, k, rows, i0, i1, problem=0):
     """Block G[rows, i0:i1] of the unscaled Gaussian matrix."""
     return philox.gaussian_rows(seed, k, rows, i0, i1, problem)
@@ -114,6 +136,8 @@ def sketch(A, m, kind, seed, k, problem=0):
         return srht(A, m, seed, k, problem)
     if kind == "gauss":
         return gaussian(A, m, seed, k, problem)
+    if kind == "sjlt":
+        return sjlt(A, m, seed, k, problem)
     raise ValueError(f"unknown sketch kind {kind!r}")
 
 

@@ -55,7 +55,7 @@ from .factor import NotSPDError, SketchedHessian
 @dataclass
 class Options:
     method: str = "pcg"          # 'pcg' | 'ihs'
-    sketch: str = "srht"         # 'srht' | 'gauss'
+    sketch: str = "srht"         # 'srht' | 'gauss' | 'sjlt'
     rho: float = 0.125
     m_init: int = 1
     m_max: int = 0               # 0 -> n'

@@ -57,7 +57,7 @@ def _sts(kind, n, m, seed, k):
     return np.array(sk.sketch(np.eye(n), m, kind, seed, k)).T @ np.array(sk.sketch(np.eye(n), m, kind, seed, k))
 
 
-@pytest.mark.parametrize("kind", ["srht", "gauss"])
+@pytest.mark.parametrize("kind", ["srht", "gauss", "sjlt"])
 def test_sketch_unbiased(kind):
     # E[S^T S] = I: average over independent sketch indices (Monte Carlo).
     n, m, reps = 16, 4, 600
@@ -111,3 +111,57 @@ def test_gaussian_embedding_theorem_statistical():
         ev = np.linalg.eigvalsh(Hm12 @ HS @ Hm12 - np.eye(d))
         ok += (ev.min() >= D2.max() * (-2 * np.sqrt(rho) + rho)) and (ev.max() <= D2.max() * (2 * np.sqrt(rho) + rho))
     assert ok / reps >= 1 - delta
+
+
+def test_sjlt_is_one_signed_entry_per_column():
+    # S built densely from the hash: one +-1 per column, S A by a dense product, and the
+    # bucket map equal to the high word of w0 * m in Python big-integer arithmetic.
+    n, m, d = 37, 5, 3
+    h, sgn = philox.sjlt_hash(11, 2, n, m)
+    k0, k1 = philox.stream_key(11, 2)
+    w0, w1, _, _ = philox.philox4x64(np.arange(n, dtype=np.uint64), philox.SJLT, 0, 0, k0, k1)
+    assert [int(v) for v in h] == [(int(a) * m) >> 64 for a in w0]
+    assert [float(v) for v in sgn] == [-1.0 if int(b) >> 63 else 1.0 for b in w1]
+    S = np.zeros((m, n))
+    S[h, np.arange(n)] = sgn
+    assert np.all(np.count_nonzero(S, axis=0) == 1) and set(np.unique(S)) <= {-1.0, 0.0, 1.0}
+    np.testing.assert_array_equal(np.diag(S.T @ S), np.ones(n))
+    A = np.random.default_rng(5).integers(-50, 50, size=(n, d)).astype(np.float64)
+    np.testing.assert_array_equal(sk.sjlt(A, m, 11, 2), S @ A)  # integers: exact
+
+
+def test_sjlt_sums_in_row_order():
+    # a small value followed by two opposite huge ones in one bucket: summed left to right
+    # from zero the small one is absorbed (0.0); any order that cancels the huge pair first
+    # would give 1.0
+    n = 40
+    h, sgn = philox.sjlt_hash(3, 0, n, 1)
+    A = np.zeros((n, 1))
+    A[0, 0], A[1, 0], A[2, 0] = 1.0 * sgn[0], 1e16 * sgn[1], -1e16 * sgn[2]
+    assert sk.sjlt(A, 1, 3, 0)[0, 0] == 0.0
+
+
+def test_sjlt_buckets_and_signs_uniform():
+    from scipy import stats
+    n, m = 200000, 7
+    h, sgn = philox.sjlt_hash(9, 4, n, m)
+    assert h.min() >= 0 and h.max() < m
+    counts = np.bincount(h, minlength=m)
+    expected = n / m
+    assert stats.chi2.sf(np.sum((counts - expected) ** 2 / expected), m - 1) > 1e-4
+    assert abs(sgn.mean()) < 5 / np.sqrt(n)
+
+
+def test_sjlt_second_moment_closed_form():
+    # M = U^T S^T S U - I = sum_{i != j} s_i s_j [h_i = h_j] u_i u_j^T, so for i.i.d. uniform
+    # buckets and signs E||M||_F^2 = (d^2 + d - 2 sum_i ||u_i||^4) / m.
+    rng = np.random.default_rng(8)
+    n, d, m, reps = 300, 4, 32, 400
+    U, _ = np.linalg.qr(rng.standard_normal((n, d)))
+    expect = (d * d + d - 2 * np.sum(np.sum(U * U, axis=1) ** 2)) / m
+    vals = []
+    for k in range(reps):
+        SU = sk.sjlt(U, m, 21, k)
+        vals.append(np.sum((SU.T @ SU - np.eye(d)) ** 2))
+    vals = np.array(vals)
+    assert abs(vals.mean() - expect) < 4 * vals.std() / np.sqrt(reps)
