@@ -170,7 +170,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="pcg_n65536_d2048")
     ap.add_argument("--method", default="pcg", choices=["pcg", "ihs"])
-    ap.add_argument("--sketch", default="srht", choices=["srht", "gauss"])
+    ap.add_argument("--sketch", default="srht", choices=["srht", "gauss", "sjlt"])
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--hv-only", action="store_true")

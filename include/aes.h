@@ -49,13 +49,14 @@ typedef enum {
 } aes_status;
 
 typedef enum { AES_PCG = 0, AES_IHS = 1 } aes_method;
-typedef enum { AES_SRHT = 0, AES_GAUSS = 1 } aes_sketch_kind;
+typedef enum { AES_SRHT = 0, AES_GAUSS = 1, AES_SJLT = 2 } aes_sketch_kind;
 typedef enum {
   AES_FP64 = 0,       /* every step in FP64 */
-  AES_MIXED = 1,      /* FP32-stored A for the PCG matvecs and the SRHT (FP32 transform, sketch
-                         rounded to BF16), BF16 MFMA Gram (FP32 accumulation), FP64 Cholesky,
-                         FP64 scalars and vectors, FP64 residual refinement */
-  AES_MIXED_FP32 = 2  /* as AES_MIXED with an FP32 SRHT and an FP64 MFMA Gram of it (for small
+  AES_MIXED = 1,      /* FP32-stored A for the PCG matvecs and the SRHT or SJLT (FP32 sums,
+                         sketch rounded to BF16), BF16 MFMA Gram (FP32 accumulation), FP64
+                         Cholesky, FP64 scalars and vectors, FP64 residual refinement (the
+                         Gaussian sketch stays FP64) */
+  AES_MIXED_FP32 = 2  /* as AES_MIXED with an FP32 sketch and an FP64 MFMA Gram of it (for small
                          nu, where a BF16 sketch or an FP32-accumulated Gram is too coarse) */
 } aes_precision;
 typedef enum {
@@ -214,7 +215,10 @@ aes_status aes_hv_multi(aes_handle h, void* stream, int64_t n, int64_t d, int64_
 /* SA for sketch index k of size m (Sec. 2.1).  kind AES_SRHT: SA = (1/sqrt m) R H E A_pad,
  * H the unnormalised Sylvester Walsh-Hadamard matrix of order n' = 2^ceil(log2 n), E the
  * signs of stream SIGN, R the m padded rows with the smallest ROW keys (ascending order);
- * kind AES_GAUSS: SA = G A / sqrt m with G from stream GAUSS by Box-Muller.
+ * kind AES_GAUSS: SA = G A / sqrt m with G from stream GAUSS by Box-Muller;
+ * kind AES_SJLT: the sparse embedding with one +-1 per column (s = 1): data row i goes, with
+ * its sign, into sketch row h_i, both from stream SJLT; each sketch row sums its rows in
+ * increasing order (n < 2^31; m may exceed n, leaving zero rows).
  *   SA: device, m x d output (ld = d).  1 <= m <= n'. */
 aes_status aes_sketch(aes_handle h, void* stream, int kind, int64_t n, int64_t d, const double* A,
                       int64_t lda, int64_t m, uint64_t seed, int32_t problem, int64_t k, double* SA);

@@ -62,7 +62,7 @@ __device__ __forceinline__ Rand4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_
   return out;
 }
 
-enum Stream : uint64_t { kStreamSign = 1, kStreamRow = 2, kStreamGauss = 3 };
+enum Stream : uint64_t { kStreamSign = 1, kStreamRow = 2, kStreamGauss = 3, kStreamSjlt = 4 };
 
 struct RngKey {
   uint64_t k0, k1;

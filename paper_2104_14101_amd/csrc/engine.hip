@@ -129,7 +129,8 @@ void validate(const ProblemDesc& P, double tol, const aes_options& o) {
   if (o.m_init < 1) bad("m_init must be >= 1");
   if (o.stop != AES_STOP_FIXED && !(tol > 0)) bad("tol must be > 0");
   if (o.method != AES_PCG && o.method != AES_IHS) bad("unknown method");
-  if (o.sketch != AES_SRHT && o.sketch != AES_GAUSS) bad("unknown sketch");
+  if (o.sketch != AES_SRHT && o.sketch != AES_GAUSS && o.sketch != AES_SJLT) bad("unknown sketch");
+  if (o.sketch == AES_SJLT && P.n >= (int64_t(1) << 31)) bad("the SJLT needs n < 2^31");
   if (o.precision < AES_FP64 || o.precision > AES_MIXED_FP32) bad("unknown precision");
   if (o.stop < 0 || o.stop > 3) bad("unknown stop rule");
   if (o.max_iter < 0) bad("max_iter must be >= 0");
@@ -305,8 +306,9 @@ class Solver {
       sk_ev_.push_back(ev);
       AES_HIP(hipEventRecord(ev.first, s_));
     }
-    const bool bf = mixed_ && !sketch32_ && o_.sketch == AES_SRHT;
-    const bool f32 = mixed_ && sketch32_ && o_.sketch == AES_SRHT;
+    const bool low = o_.sketch == AES_SRHT || o_.sketch == AES_SJLT;  // sketches of the FP32 copy
+    const bool bf = mixed_ && !sketch32_ && low;
+    const bool f32 = mixed_ && sketch32_ && low;
     woodbury_ = m_ < d_;
     if (bf) {
       SA16_ = B<__hip_bfloat16>("SA16", (size_t)m_ * d_);
@@ -337,6 +339,24 @@ class Solver {
         double* Y = B<double>("Y", srht_scratch_elems(npad_, d_));
         launch_srht_apply<double, double, double>(P_.A, n_, d_, P_.lda, eps, npad_, sc.pos, m_, Y, SA_, d_,
                                                   B<int32_t>("need", 512), s_);
+      }
+    } else if (o_.sketch == AES_SJLT) {
+      const SjltPlan sp = sjlt_plan(n_, m_);
+      SjltScratch sc;
+      sc.code = B<int32_t>("sj_code", n_);
+      sc.cnt = B<int32_t>("sj_cnt", sp.count_elems);
+      sc.csum = B<int32_t>("sj_csum", sp.csum_elems);
+      sc.perm = B<int32_t>("sj_perm", n_);
+      const size_t part = sp.Q > 1 ? (size_t)m_ * sp.Q * d_ : 0;
+      if (bf) {
+        sc.part = part ? B<float>("sj_part32", part) : nullptr;
+        launch_sjlt<float, __hip_bfloat16>(sp, A32_, n_, d_, d_, m_, o_.seed, o_.problem, k_, SA16_, sc, s_);
+      } else if (f32) {
+        sc.part = part ? B<float>("sj_part32", part) : nullptr;
+        launch_sjlt<float, float>(sp, A32_, n_, d_, d_, m_, o_.seed, o_.problem, k_, SA32_, sc, s_);
+      } else {
+        sc.part = part ? B<double>("sj_part", part) : nullptr;
+        launch_sjlt<double, double>(sp, P_.A, n_, d_, P_.lda, m_, o_.seed, o_.problem, k_, SA_, sc, s_);
       }
     } else {
       const GaussPlan gp = gauss_plan(h_->num_cu, n_, d_, m_);
@@ -1243,6 +1263,16 @@ aes_status aes_sketch(aes_handle h, void* stream, int kind, int64_t n, int64_t d
       double* Y = h->buf<double>("sk.Y", srht_scratch_elems(npad, d));
       launch_srht_apply<double, double, double>(A, n, d, lda, eps, npad, sc.pos, m, Y, SA, d,
                                                 h->buf<int32_t>("sk.need", 512), s);
+    } else if (kind == AES_SJLT) {
+      if (n >= (int64_t(1) << 31)) throw StatusError(AES_ERR_INVALID_ARG, "the SJLT needs n < 2^31");
+      const SjltPlan sp = sjlt_plan(n, m);
+      SjltScratch sc;
+      sc.code = h->buf<int32_t>("sk.sj_code", n);
+      sc.cnt = h->buf<int32_t>("sk.sj_cnt", sp.count_elems);
+      sc.csum = h->buf<int32_t>("sk.sj_csum", sp.csum_elems);
+      sc.perm = h->buf<int32_t>("sk.sj_perm", n);
+      sc.part = sp.Q > 1 ? h->buf<double>("sk.sj_part", (size_t)m * sp.Q * d) : nullptr;
+      launch_sjlt<double, double>(sp, A, n, d, lda, m, seed, problem, k, SA, sc, s);
     } else if (kind == AES_GAUSS) {
       const GaussPlan gp = gauss_plan(h->num_cu, n, d, m);
       launch_gauss_sketch(gp, A, n, d, lda, m, seed, problem, k, SA, h->buf<double>("sk.gt", gp.gt_elems),

@@ -118,6 +118,26 @@ void launch_gauss_sketch(const GaussPlan& p, const double* A, int64_t n, int64_t
                          uint64_t seed, int32_t problem, int64_t k, double* SA, double* gt, double* part,
                          hipStream_t s);
 
+// SJLT with one non-zero per column (k_sjlt.hip): SA (m x d, ld d) = S A.  n < 2^31.
+struct SjltPlan {
+  int64_t nblk;        // counting blocks of 1024 data rows
+  int Q;               // pieces per bucket (partial sums combined in order when Q > 1)
+  int G;               // output items per reduction workgroup
+  size_t count_elems;  // int32 elements of SjltScratch::cnt (m * nblk)
+  size_t csum_elems;   // int32 elements of SjltScratch::csum
+};
+struct SjltScratch {
+  int32_t* code;  // n
+  int32_t* cnt;   // count_elems: counts, then their exclusive scan (bucket-major offsets)
+  int32_t* csum;  // csum_elems
+  int32_t* perm;  // n: data rows sorted by bucket (stable), sign in bit 31
+  void* part;     // Q > 1: m * Q * d elements of the input type
+};
+SjltPlan sjlt_plan(int64_t n, int64_t m);
+template <typename TA, typename TO>
+void launch_sjlt(const SjltPlan& p, const TA* A, int64_t n, int64_t d, int64_t lda, int64_t m, uint64_t seed,
+                 int32_t problem, int64_t k, TO* SA, const SjltScratch& sc, hipStream_t s);
+
 // ---- dense linear algebra on MFMA (k_dense.hip) ------------------------------------------
 // C = alpha * opA(A) * opB(B) + beta * C, batched with element strides; tri = 1 writes only
 // elements with row >= col (and skips tiles strictly above the diagonal).

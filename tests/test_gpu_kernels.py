@@ -109,6 +109,51 @@ def test_gaussian_sampled_rows(n, d, m):
     assert np.max(np.abs(SA[rows] - ref)) <= 1e-13 * np.sqrt(n) * np.max(np.abs(ref)) + 1e-14
 
 
+def _sjlt_bound(A, h, m):
+    # |fl(sum) - sum| <= (k - 1) u sum |terms| for any order of k terms; k <= bucket size
+    absum = np.zeros((m, A.shape[1]))
+    np.add.at(absum, h, np.abs(A))
+    cnt = np.bincount(h, minlength=m)[:, None]
+    return cnt * 2.0 ** -53 * absum
+
+
+# one piece per bucket (Q = 1: the sums run in the oracle's order, bit for bit) and several
+# (Q > 1: pieces summed in order); odd d and lda (scalar loads), m > n (empty buckets), m = 1,
+# several counting blocks with a ragged last one
+@pytest.mark.parametrize("n,d,m,exact", [(300, 40, 70, True), (129, 7, 3, True), (3000, 257, 4096, True),
+                                         (70000, 64, 4096, True), (1000, 65, 7, False), (5000, 130, 1, False),
+                                         (70000, 33, 1024, False)])
+def test_sjlt_sketch(n, d, m, exact):
+    rng = np.random.default_rng(n + d + m)
+    A = rng.standard_normal((n, d))
+    SA = aes.sketch(to_dev(A), m, "sjlt", seed=8, k=2).cpu().numpy()
+    ref = osk.sjlt(A, m, 8, 2)
+    if exact:
+        np.testing.assert_array_equal(SA, ref)
+    else:
+        h, _ = philox.sjlt_hash(8, 2, n, m)
+        assert np.all(np.abs(SA - ref) <= _sjlt_bound(A, h, m))
+
+
+@pytest.mark.parametrize("m", [16384, 16])
+def test_sjlt_full_size_sampled_rows(m):
+    P = synth.make_problem(65536, 2048, "pow:1", 1e-3, seed=14, backend="torch", device="cuda")
+    A = P["A"]
+    SA = aes.sketch(A, m, "sjlt", seed=5, k=4).cpu().numpy()
+    An = A.cpu().numpy()
+    h, sgn = philox.sjlt_hash(5, 4, 65536, m)
+    for r in (0, 1, m // 2 + 1, m - 1):
+        idx = np.nonzero(h == r)[0]
+        acc = np.zeros(2048)
+        for i in idx:  # increasing row order from zero, as the definition sums
+            acc = acc + sgn[i] * An[i]
+        if m * 64 >= 65536:
+            np.testing.assert_array_equal(SA[r], acc)
+        else:
+            bound = len(idx) * 2.0 ** -53 * np.abs(An[idx]).sum(axis=0)
+            assert np.all(np.abs(SA[r] - acc) <= bound)
+
+
 @pytest.mark.parametrize("m,d", [(200, 100), (100, 100), (37, 100), (1, 5), (300, 257), (129, 130)])
 def test_factor_and_apply(m, d):
     rng = np.random.default_rng(m + d)
