@@ -158,9 +158,9 @@ def sketch_only(args):
     g.manual_seed(5)
     A = torch.randn((w.n, w.d), dtype=torch.float64, device="cuda", generator=g)
     for k in range(args.steps):
-        aes.sketch(A, args.sketch_only, kind="srht", seed=1, k=k)
+        aes.sketch(A, args.sketch_only, kind=args.sketch, seed=1, k=k)
     torch.cuda.synchronize()
-    print(json.dumps({"sketches": args.steps, "m": args.sketch_only, "n": w.n, "d": w.d}))
+    print(json.dumps({"sketches": args.steps, "kind": args.sketch, "m": args.sketch_only, "n": w.n, "d": w.d}))
 
 
 def main():

@@ -341,7 +341,7 @@ class Solver {
                                                   B<int32_t>("need", 512), s_);
       }
     } else if (o_.sketch == AES_SJLT) {
-      const SjltPlan sp = sjlt_plan(n_, m_);
+      const SjltPlan sp = sjlt_plan(n_, d_, m_, (bf || f32) ? sizeof(float) : sizeof(double));
       SjltScratch sc;
       sc.code = B<int32_t>("sj_code", n_);
       sc.cnt = B<int32_t>("sj_cnt", sp.count_elems);
@@ -1265,7 +1265,7 @@ aes_status aes_sketch(aes_handle h, void* stream, int kind, int64_t n, int64_t d
                                                 h->buf<int32_t>("sk.need", 512), s);
     } else if (kind == AES_SJLT) {
       if (n >= (int64_t(1) << 31)) throw StatusError(AES_ERR_INVALID_ARG, "the SJLT needs n < 2^31");
-      const SjltPlan sp = sjlt_plan(n, m);
+      const SjltPlan sp = sjlt_plan(n, d, m, sizeof(double));
       SjltScratch sc;
       sc.code = h->buf<int32_t>("sk.sj_code", n);
       sc.cnt = h->buf<int32_t>("sk.sj_cnt", sp.count_elems);

@@ -156,16 +156,18 @@ struct Vec16<float> {
 };
 
 // Workgroup (blockIdx.x, blockIdx.y) adds, for the items it0 .. it0 + G - 1, the signed rows of
-// their sorted ranges into columns [blockIdx.y * 256 * VE, +256 * VE) and writes one output row
-// per item (out row it).  The items' ranges are consecutive, so the workgroup streams one
-// contiguous stretch of perm, eight rows in flight per thread.
-template <typename TA, typename TO>
+// their sorted ranges into columns [blockIdx.y * 256 * VE * NV, +256 * VE * NV) and writes one
+// output row per item (out row it).  Thread t owns the VE-element vectors v * 256 + t (v < NV),
+// so each load instruction of a wave covers 1 KiB of a row.  The items' ranges are consecutive,
+// so the workgroup streams one contiguous stretch of perm, RW rows in flight per thread.
+template <typename TA, typename TO, int NV>
 __global__ __launch_bounds__(256) void sjlt_reduce_kernel(const TA* __restrict__ A, int64_t lda, int64_t d, int vec,
                                                           const int32_t* __restrict__ perm,
                                                           const int32_t* __restrict__ off, int64_t nblk, int64_t n,
                                                           int64_t m, int Q, int G, TO* __restrict__ out,
                                                           int64_t ldo) {
   constexpr int VE = 16 / sizeof(TA);
+  constexpr int RW = 16 / NV;
   using VT = typename Vec16<TA>::type;
   __shared__ int32_t iend[kSjItems + 1];
   __shared__ int32_t pl[256];
@@ -174,21 +176,31 @@ __global__ __launch_bounds__(256) void sjlt_reduce_kernel(const TA* __restrict__
   const int nit = (int)std::min<int64_t>(G, m * Q - it0);
   if (tid <= nit) iend[tid] = sjlt_item_begin(it0 + tid, Q, m, n, nblk, off);
   __syncthreads();
-  const int64_t c0 = (int64_t)blockIdx.y * 256 * VE + (int64_t)tid * VE;
-  const bool full = vec && c0 + VE <= d;
-  TA acc[VE];
+  int64_t c0[NV];
+  bool full[NV];
 #pragma unroll
-  for (int e = 0; e < VE; ++e) acc[e] = TA(0);
+  for (int v = 0; v < NV; ++v) {
+    c0[v] = (int64_t)blockIdx.y * 256 * VE * NV + (int64_t)(v * 256 + tid) * VE;
+    full[v] = vec && c0[v] + VE <= d;
+  }
+  TA acc[NV][VE];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int e = 0; e < VE; ++e) acc[v][e] = TA(0);
   int cur = 0;
   auto flush = [&]() {
-    if (c0 < d) {
-      TO* o = out + (it0 + cur) * ldo + c0;
 #pragma unroll
-      for (int e = 0; e < VE; ++e)
-        if (c0 + e < d) o[e] = sj_cvt<TO>(acc[e]);
+    for (int v = 0; v < NV; ++v) {
+      if (c0[v] < d) {
+        TO* o = out + (it0 + cur) * ldo + c0[v];
+#pragma unroll
+        for (int e = 0; e < VE; ++e)
+          if (c0[v] + e < d) o[e] = sj_cvt<TO>(acc[v][e]);
+      }
+#pragma unroll
+      for (int e = 0; e < VE; ++e) acc[v][e] = TA(0);
     }
-#pragma unroll
-    for (int e = 0; e < VE; ++e) acc[e] = TA(0);
     ++cur;
   };
   const int32_t start = iend[0], end = iend[nit];
@@ -197,35 +209,35 @@ __global__ __launch_bounds__(256) void sjlt_reduce_kernel(const TA* __restrict__
     pl[tid] = base + tid < end ? perm[base + tid] : 0;
     __syncthreads();
     const int cnt = std::min<int32_t>(256, end - base);
-    for (int u0 = 0; u0 < cnt; u0 += 8) {
-      TA v[8][VE];
+    for (int u0 = 0; u0 < cnt; u0 += RW) {
+      TA x[RW][NV][VE];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        if (u0 + u < cnt && c0 < d) {
-          // (the clamp keeps a corrupted entry inside A; a valid one is always < n)
-          const int64_t row = std::min<int64_t>(pl[u0 + u] & 0x7fffffff, n - 1);
-          const TA* p = A + row * lda + c0;
-          if (full) {
-            const VT x = __builtin_nontemporal_load(reinterpret_cast<const VT*>(p));
+      for (int u = 0; u < RW; ++u) {
+        // (the clamp keeps a corrupted entry inside A; a valid one is always < n)
+        const int64_t row = std::min<int64_t>(pl[u0 + u < cnt ? u0 + u : 0] & 0x7fffffff, n - 1);
 #pragma unroll
-            for (int e = 0; e < VE; ++e) v[u][e] = x[e];
+        for (int v = 0; v < NV; ++v) {
+          const TA* p = A + row * lda + c0[v];
+          if (u0 + u < cnt && full[v]) {
+            const VT y = __builtin_nontemporal_load(reinterpret_cast<const VT*>(p));
+#pragma unroll
+            for (int e = 0; e < VE; ++e) x[u][v][e] = y[e];
           } else {
 #pragma unroll
-            for (int e = 0; e < VE; ++e) v[u][e] = c0 + e < d ? p[e] : TA(0);
+            for (int e = 0; e < VE; ++e) x[u][v][e] = (u0 + u < cnt && c0[v] + e < d) ? p[e] : TA(0);
           }
-        } else {
-#pragma unroll
-          for (int e = 0; e < VE; ++e) v[u][e] = TA(0);
         }
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < RW; ++u) {
         if (u0 + u < cnt) {
           const int32_t j = base + u0 + u;
           while (j >= iend[cur + 1]) flush();
           const bool neg = pl[u0 + u] < 0;
 #pragma unroll
-          for (int e = 0; e < VE; ++e) acc[e] += neg ? -v[u][e] : v[u][e];
+          for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int e = 0; e < VE; ++e) acc[v][e] += neg ? -x[u][v][e] : x[u][v][e];
         }
       }
     }
@@ -246,15 +258,38 @@ __global__ __launch_bounds__(256) void sjlt_combine_kernel(const TA* __restrict_
   out[r * d + c] = sj_cvt<TO>(s);
 }
 
-SjltPlan sjlt_plan(int64_t n, int64_t m) {
+// Vectors per thread of a reduction workgroup: whole 16-byte vectors of up to 1024 x VE columns.
+static int sjlt_nv(int64_t d, int ve) {
+  const int64_t nvec = ceil_div(d, 256 * ve);
+  return nvec >= 4 ? 4 : (nvec >= 2 ? 2 : 1);
+}
+
+SjltPlan sjlt_plan(int64_t n, int64_t d, int64_t m, size_t elem) {
   SjltPlan p;
   p.nblk = (int64_t)sjlt_blocks(n);
   p.Q = (int)std::max<int64_t>(1, ceil_div(n, m * 64));
+  // about 256 / NV rows (256 KiB of A at d = 2048 in FP64) per workgroup
   const int64_t per_item = std::max<int64_t>(1, ceil_div(n, m * p.Q));
-  p.G = (int)std::min<int64_t>(kSjItems, std::max<int64_t>(1, 256 / per_item));
+  const int nv = sjlt_nv(d, (int)(16 / elem));
+  p.G = (int)std::min<int64_t>(kSjItems, std::max<int64_t>(1, 256 / nv / per_item));
   p.count_elems = (size_t)(m * p.nblk);
   p.csum_elems = (size_t)std::max<int64_t>(1, ceil_div(m * p.nblk, kScanChunk));
   return p;
+}
+
+template <typename TA, typename TO>
+static void launch_reduce(int nv, dim3 grid, hipStream_t s, const TA* A, int64_t lda, int64_t d, int vec,
+                          const SjltScratch& sc, const SjltPlan& p, int64_t n, int64_t m, TO* out) {
+  if (nv == 4)
+    hipLaunchKernelGGL((sjlt_reduce_kernel<TA, TO, 4>), grid, dim3(256), 0, s, A, lda, d, vec, sc.perm, sc.cnt, p.nblk,
+                       n, m, p.Q, p.G, out, d);
+  else if (nv == 2)
+    hipLaunchKernelGGL((sjlt_reduce_kernel<TA, TO, 2>), grid, dim3(256), 0, s, A, lda, d, vec, sc.perm, sc.cnt, p.nblk,
+                       n, m, p.Q, p.G, out, d);
+  else
+    hipLaunchKernelGGL((sjlt_reduce_kernel<TA, TO, 1>), grid, dim3(256), 0, s, A, lda, d, vec, sc.perm, sc.cnt, p.nblk,
+                       n, m, p.Q, p.G, out, d);
+  AES_LAUNCH_CHECK();
 }
 
 template <typename TA, typename TO>
@@ -280,16 +315,13 @@ void launch_sjlt(const SjltPlan& p, const TA* A, int64_t n, int64_t d, int64_t l
   constexpr int VE = 16 / sizeof(TA);
   const int vec = ((uintptr_t)A % 16 == 0) && lda % VE == 0;
   const int64_t items = m * p.Q;
-  dim3 grid((unsigned)ceil_div(items, p.G), (unsigned)ceil_div(d, 256 * VE));
+  const int nv = sjlt_nv(d, VE);
+  dim3 grid((unsigned)ceil_div(items, p.G), (unsigned)ceil_div(d, 256 * VE * nv));
   if (p.Q == 1) {
-    hipLaunchKernelGGL((sjlt_reduce_kernel<TA, TO>), grid, dim3(256), 0, s, A, lda, d, vec, sc.perm, sc.cnt, p.nblk,
-                       n, m, 1, p.G, SA, d);
-    AES_LAUNCH_CHECK();
+    launch_reduce(nv, grid, s, A, lda, d, vec, sc, p, n, m, SA);
   } else {
     TA* part = reinterpret_cast<TA*>(sc.part);
-    hipLaunchKernelGGL((sjlt_reduce_kernel<TA, TA>), grid, dim3(256), 0, s, A, lda, d, vec, sc.perm, sc.cnt, p.nblk,
-                       n, m, p.Q, p.G, part, d);
-    AES_LAUNCH_CHECK();
+    launch_reduce(nv, grid, s, A, lda, d, vec, sc, p, n, m, part);
     hipLaunchKernelGGL((sjlt_combine_kernel<TA, TO>), dim3((unsigned)ceil_div(d, 256), (unsigned)m), dim3(256), 0, s,
                        part, d, p.Q, SA);
     AES_LAUNCH_CHECK();

@@ -133,7 +133,7 @@ struct SjltScratch {
   int32_t* perm;  // n: data rows sorted by bucket (stable), sign in bit 31
   void* part;     // Q > 1: m * Q * d elements of the input type
 };
-SjltPlan sjlt_plan(int64_t n, int64_t m);
+SjltPlan sjlt_plan(int64_t n, int64_t d, int64_t m, size_t elem);  // elem: bytes per element of A
 template <typename TA, typename TO>
 void launch_sjlt(const SjltPlan& p, const TA* A, int64_t n, int64_t d, int64_t lda, int64_t m, uint64_t seed,
                  int32_t problem, int64_t k, TO* SA, const SjltScratch& sc, hipStream_t s);
