@@ -172,6 +172,7 @@ def main():
     ap.add_argument("--method", default="pcg", choices=["pcg", "ihs"])
     ap.add_argument("--sketch", default="srht", choices=["srht", "gauss", "sjlt"])
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip the Gaussian / SJLT / IHS solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--hv-only", action="store_true")
     ap.add_argument("--sketch-only", type=int, default=0, metavar="M")
@@ -243,6 +244,8 @@ def main():
                      "avg_launch_us": hv_avg_s * 1e6, "launches_timed": hv_n},
     }
 
+    if not args.no_variants:
+        out["variants"] = variants_leg(aes, torch, A, b, nu, lam, w, P_np, args)
     if not args.no_mixed:
         out["mixed_vs_fp64"] = mixed_leg(aes, torch, synth)
 
@@ -256,6 +259,22 @@ def main():
         cb["gpu_speedup"] = cb["value"] / sec
         out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
+
+
+def variants_leg(aes, torch, A, b, nu, lam, w, P_np, args):
+    """The same workload solved with the other sketches and the other method (3 timed solves)."""
+    res = {}
+    for method, sketch in (("pcg", "gauss"), ("pcg", "sjlt"), ("ihs", "srht"), ("ihs", "sjlt")):
+        if method == args.method and sketch == args.sketch:
+            continue
+        opts = dict(method=method, sketch=sketch, m_init=w.m_init, seed=1, tol=1e-10)
+        x, infos, sec = timed_solves(aes, torch, A, b, nu, lam, opts, 3, 1)
+        err = reference_error(P_np, x.cpu().numpy())
+        i = infos[-1]
+        res[f"{method}_{sketch}"] = {"s_per_solve": sec, "rel_err": err, "valid": bool(err <= 1e-10),
+                                     "iterations": i["iterations"], "final_m": i["final_m"],
+                                     "a_passes": i["a_passes"], "time_sketch_ms": i["time_sketch_ms"]}
+    return res
 
 
 def mixed_leg(aes, torch, synth):
