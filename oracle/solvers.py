@@ -36,12 +36,15 @@ Readings where the paper is silent (each also listed in the design notes):
     stop rule is frozen.  With c = 1 this is exactly Algorithm 2 / Algorithm 1.
   * ``max_iter`` bounds the number of accepted steps t (the loop "while t < T").
 
+``cg`` is the paper's unpreconditioned conjugate-gradient baseline (Sec. 5).
+
 Pins (tests/test_oracle_solvers.py): one-step convergence when m = n' (H_S = H); Krylov
 optimality of PCG (Theorem "rate cg") by brute-force least squares on tiny problems; the IHS
 error recursion (proof of Theorem "rate IHS"); the decrement bracket (proof of the decrement
 lemma); invariants of the adaptive control (accepted steps satisfy the test, m doubles, K
 bounded, forced rejections recompute r_t = b - H x_t); rel. error <= 1e-10 against the
-refined direct solution.
+refined direct solution; for ``cg``: termination in d steps, Krylov optimality in the
+H-norm by brute-force least squares, and the xrel bound on the true error.
 """
 import math
 from dataclasses import dataclass, field
@@ -54,7 +57,7 @@ from .factor import NotSPDError, SketchedHessian
 
 @dataclass
 class Options:
-    method: str = "pcg"          # 'pcg' | 'ihs'
+    method: str = "pcg"          # 'pcg' | 'ihs' | 'cg' (unpreconditioned baseline)
     sketch: str = "srht"         # 'srht' | 'gauss' | 'sjlt'
     rho: float = 0.125
     m_init: int = 1
@@ -360,6 +363,81 @@ def adaptive_ihs(A, b, nu, lam=None, opts=None):
     return (X[:, 0] if squeeze else X), info
 
 
+def cg(A, b, nu, lam=None, opts=None):
+    """Unpreconditioned conjugate gradient on H x = b: the baseline of the paper's numerical
+    section (Sec. 5), in its textbook (Hestenes-Stiefel) form:
+
+        q = H p,  alpha = r^T r / p^T q,  x += alpha p,  r -= alpha q,
+        beta = r+^T r+ / r^T r,  p = r+ + beta p.
+
+    Matrix variables: every column runs its own recurrence; a column that meets the stop rule
+    is frozen.  Stop rules (the same names as the adaptive solvers, with the identity in place
+    of H_S):
+      'xrel'       ||r||^2 <= (nu^2 min(lambda) tol)^2 ||x||^2, which bounds the relative error
+                   by tol since ||x - x*|| <= ||H^{-1}|| ||r|| <= ||r|| / (nu^2 min(lambda));
+      'dtilde_rel' r^T r <= tol^2 r_0^T r_0;
+      'fixed'      exactly max_iter steps;
+    and a column with r = 0 stops.  Returns (x, Info) with final_m = 0 (no sketch).
+    """
+    o = opts or Options()
+    A = np.asarray(A, dtype=np.float64)
+    n, d = A.shape
+    B, squeeze = _as2d(b)
+    lam = np.ones(d) if lam is None else np.asarray(lam, dtype=np.float64)
+    if n < 1 or d < 1 or B.shape[0] != d:
+        raise ValueError("bad shapes")
+    if not (np.isfinite(nu) and nu > 0):
+        raise ValueError("nu must be finite and > 0")
+    if o.stop not in ("xrel", "dtilde_rel", "fixed"):
+        raise ValueError("CG supports the stop rules 'xrel', 'dtilde_rel' and 'fixed'")
+    info = Info()
+    c = B.shape[1]
+    X = np.zeros((d, c)) if o.x0 is None else np.array(o.x0, dtype=np.float64).reshape(d, c)
+    if o.x0 is None:
+        R = B.copy()
+    else:
+        R = B - hess_apply(A, nu, lam, X)
+        info.a_passes += 1
+    P = R.copy()
+    g = np.sum(R * R, axis=0)
+    g0 = g.copy()
+    scale = (nu ** 2 * float(np.min(lam)) * o.tol) ** 2
+
+    def stopped(gam, Xc, t, J):
+        exact = gam <= 0
+        if o.stop == "xrel":
+            rule = gam <= scale * np.sum(Xc * Xc, axis=0)
+        elif o.stop == "dtilde_rel":
+            rule = gam <= (o.tol ** 2) * g0[J]
+        else:
+            rule = np.full(gam.shape, t >= o.max_iter)
+        return exact | rule
+
+    active = np.arange(c)
+    active = active[~stopped(g, X, 0, active)]
+    t = 0
+    while active.size and t < o.max_iter:
+        J = active
+        Q = hess_apply(A, nu, lam, P[:, J])
+        info.a_passes += 1
+        alpha = g[J] / np.sum(P[:, J] * Q, axis=0)
+        X[:, J] += alpha * P[:, J]
+        R[:, J] -= alpha * Q
+        gn = np.sum(R[:, J] * R[:, J], axis=0)
+        P[:, J] = R[:, J] + (gn / g[J]) * P[:, J]
+        g[J] = gn
+        t += 1
+        info.attempts += 1
+        info.iterations = t
+        info.trace.append({"t": t - 1, "m": 0, "accept": True})
+        active = J[~stopped(g[J], X[:, J], t, J)]
+    if active.size and o.stop != "fixed":
+        info.status = "max_iter"
+    return (X[:, 0] if squeeze else X), info
+
+
 def solve(A, b, nu, lam=None, opts=None):
     o = opts or Options()
+    if o.method == "cg":
+        return cg(A, b, nu, lam, o)
     return adaptive_ihs(A, b, nu, lam, o) if o.method == "ihs" else adaptive_pcg(A, b, nu, lam, o)

@@ -242,3 +242,50 @@ def test_validation():
                      ({"m_init": 0}, (A, b, nu, lam))]:
         with pytest.raises(ValueError):
             solvers.adaptive_pcg(*args, solvers.Options(**kw))
+
+
+def _spd_problem(n, d, seed, decay=0.7, nu=0.3):
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.standard_normal((n, d)))
+    V, _ = np.linalg.qr(rng.standard_normal((d, d)))
+    A = (U * decay ** np.arange(d)) @ V.T
+    lam = 1 + rng.random(d)
+    b = rng.standard_normal(d)
+    return A, b, nu, lam
+
+
+def test_cg_terminates_in_d_steps():
+    # in exact arithmetic CG on a d x d SPD system reaches x* after at most d steps
+    A, b, nu, lam = _spd_problem(40, 6, 1)
+    H = A.T @ A + nu ** 2 * np.diag(lam)
+    xs = np.linalg.solve(H, b)
+    x, info = solvers.cg(A, b, nu, lam, solvers.Options(stop="fixed", max_iter=6))
+    assert info.iterations == 6 and info.a_passes == 6
+    assert np.linalg.norm(x - xs) <= 1e-11 * np.linalg.norm(xs)
+
+
+def test_cg_krylov_optimality():
+    # x_t minimises the H-norm error over x_0 + span{r_0, H r_0, ..., H^{t-1} r_0}
+    A, b, nu, lam = _spd_problem(60, 9, 2, decay=0.8)
+    H = A.T @ A + nu ** 2 * np.diag(lam)
+    xs = np.linalg.solve(H, b)
+    x0 = np.random.default_rng(3).standard_normal(9)
+    r0 = b - H @ x0
+    w, V = np.linalg.eigh(H)
+    Hh = V @ np.diag(np.sqrt(w)) @ V.T
+    for t in range(1, 5):
+        K = np.stack([np.linalg.matrix_power(H, j) @ r0 for j in range(t)], axis=1)
+        coef, *_ = np.linalg.lstsq(Hh @ K, Hh @ (xs - x0), rcond=None)
+        best = x0 + K @ coef
+        x, _ = solvers.cg(A, b, nu, lam, solvers.Options(stop="fixed", max_iter=t, x0=x0))
+        assert np.linalg.norm(Hh @ (x - best)) <= 1e-9 * np.linalg.norm(Hh @ (xs - x0))
+
+
+def test_cg_xrel_bounds_the_error(small):
+    o = solvers.Options(method="cg", tol=1e-8, max_iter=5000)
+    x, info = solvers.solve(small["A"], small["b"], small["nu"], small["lam"], o)
+    assert info.status == "ok" and info.final_m == 0
+    assert reference.rel_error(x, small["xref"]) <= 1e-8
+    assert info.a_passes == info.iterations == len(info.trace)
+    with pytest.raises(ValueError):
+        solvers.cg(small["A"], small["b"], small["nu"], small["lam"], solvers.Options(stop="remark"))
