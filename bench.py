@@ -172,7 +172,7 @@ def main():
     ap.add_argument("--method", default="pcg", choices=["pcg", "ihs"])
     ap.add_argument("--sketch", default="srht", choices=["srht", "gauss", "sjlt"])
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--no-variants", action="store_true", help="skip the Gaussian / SJLT / IHS solves")
+    ap.add_argument("--no-variants", action="store_true", help="skip the Gaussian / SJLT / IHS / CG solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--hv-only", action="store_true")
     ap.add_argument("--sketch-only", type=int, default=0, metavar="M")
@@ -262,18 +262,24 @@ def main():
 
 
 def variants_leg(aes, torch, A, b, nu, lam, w, P_np, args):
-    """The same workload solved with the other sketches and the other method (3 timed solves)."""
+    """The same workload solved with the other sketches and methods (3 timed solves each) and by
+    the unpreconditioned CG baseline (one timed solve)."""
     res = {}
-    for method, sketch in (("pcg", "gauss"), ("pcg", "sjlt"), ("ihs", "srht"), ("ihs", "sjlt")):
+    for method, sketch in (("pcg", "gauss"), ("pcg", "sjlt"), ("ihs", "srht"), ("ihs", "sjlt"), ("cg", None)):
         if method == args.method and sketch == args.sketch:
             continue
-        opts = dict(method=method, sketch=sketch, m_init=w.m_init, seed=1, tol=1e-10)
-        x, infos, sec = timed_solves(aes, torch, A, b, nu, lam, opts, 3, 1)
+        opts = dict(method=method, m_init=w.m_init, seed=1, tol=1e-10)
+        if sketch:
+            opts["sketch"] = sketch
+        else:
+            opts["max_iter"] = 50000  # the unpreconditioned baseline: one timed solve
+        x, infos, sec = timed_solves(aes, torch, A, b, nu, lam, opts, 3 if sketch else 1, 1 if sketch else 0)
         err = reference_error(P_np, x.cpu().numpy())
         i = infos[-1]
-        res[f"{method}_{sketch}"] = {"s_per_solve": sec, "rel_err": err, "valid": bool(err <= 1e-10),
-                                     "iterations": i["iterations"], "final_m": i["final_m"],
-                                     "a_passes": i["a_passes"], "time_sketch_ms": i["time_sketch_ms"]}
+        res[f"{method}_{sketch}" if sketch else method] = {
+            "s_per_solve": sec, "rel_err": err, "valid": bool(err <= 1e-10), "status": i["status"],
+            "iterations": i["iterations"], "final_m": i["final_m"], "a_passes": i["a_passes"],
+            "time_sketch_ms": i["time_sketch_ms"]}
     return res
 
 

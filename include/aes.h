@@ -48,7 +48,10 @@ typedef enum {
   AES_ERR_NOT_IMPLEMENTED = 7
 } aes_status;
 
-typedef enum { AES_PCG = 0, AES_IHS = 1 } aes_method;
+/* AES_CG: the unpreconditioned conjugate-gradient baseline of the paper's numerical section
+ * (Sec. 5): no sketch, FP64 only, stop rules XREL (with the identity for H_S:
+ * r^T r <= (nu^2 min(lambda) tol)^2 ||x||^2), DTILDE_REL and FIXED. */
+typedef enum { AES_PCG = 0, AES_IHS = 1, AES_CG = 2 } aes_method;
 typedef enum { AES_SRHT = 0, AES_GAUSS = 1, AES_SJLT = 2 } aes_sketch_kind;
 typedef enum {
   AES_FP64 = 0,       /* every step in FP64 */

@@ -128,7 +128,9 @@ void validate(const ProblemDesc& P, double tol, const aes_options& o) {
   if (!(o.rho > 0.0 && o.rho < 1.0)) bad("rho must lie in (0, 1)");
   if (o.m_init < 1) bad("m_init must be >= 1");
   if (o.stop != AES_STOP_FIXED && !(tol > 0)) bad("tol must be > 0");
-  if (o.method != AES_PCG && o.method != AES_IHS) bad("unknown method");
+  if (o.method != AES_PCG && o.method != AES_IHS && o.method != AES_CG) bad("unknown method");
+  if (o.method == AES_CG && o.precision != AES_FP64) bad("the CG baseline runs in FP64");
+  if (o.method == AES_CG && o.stop == AES_STOP_REMARK) bad("the REMARK stop rule needs a sketch");
   if (o.sketch != AES_SRHT && o.sketch != AES_GAUSS && o.sketch != AES_SJLT) bad("unknown sketch");
   if (o.sketch == AES_SJLT && P.n >= (int64_t(1) << 31)) bad("the SJLT needs n < 2^31");
   if (o.precision < AES_FP64 || o.precision > AES_MIXED_FP32) bad("unknown precision");
@@ -158,6 +160,8 @@ class Solver {
     nu2_ = P.nu * P.nu;
     mixed_ = o.precision == AES_MIXED || o.precision == AES_MIXED_FP32;
     sketch32_ = o.precision == AES_MIXED_FP32;
+    cg_ = o.method == AES_CG;
+    if (cg_) o_.adaptive = 0;  // the baseline has no sketch, no test and no resketch
     pinned_ = h->pinned;
   }
   ~Solver() {
@@ -230,6 +234,12 @@ class Solver {
     stop_scale_ = nu2_ * min_lambda() * tol_ * tol_;
     if (o_.stop == AES_STOP_REMARK) stop_scale_ = tol_ / (remark_m_delta(n_, d_) + 1.0);
     stop_sr_ = 1.0 + std::sqrt(o_.rho);
+    if (cg_) {
+      // ||x - x*|| <= ||r|| / (nu^2 min lambda): r^T r <= (nu^2 min lambda tol)^2 ||x||^2
+      const double sc = nu2_ * min_lambda() * tol_;
+      stop_scale_ = sc * sc;
+      stop_sr_ = 1.0;
+    }
     tol2_ = tol_ * tol_;
   }
 
@@ -425,8 +435,12 @@ class Solver {
     launch_transpose(np, np, Linv_, np, LinvT_, np, s_);
   }
 
-  // v = H_S^{-1} z (z, v: d x C)
+  // v = H_S^{-1} z (z, v: d x C); the identity for the CG baseline
   void apply(const double* z, double* v, const int* gate = nullptr) {
+    if (cg_) {
+      launch_copy_cols(d_, C_, z, C_, C_, v, C_, s_, gate);
+      return;
+    }
     double* t1 = B<double>("ap_t1", (size_t)std::max(m_, d_) * C_);
     if (!woodbury_) {
       if (C_ >= 8) {
@@ -501,7 +515,7 @@ class Solver {
     // one; the host then reads them through an event on their own pinned slot.
     const bool spec = C_ == 1;
     int* gate = spec ? B<int>("gate", 1) : nullptr;
-    if (!reuse_factor) sketch_factor();
+    if (!reuse_factor && !cg_) sketch_factor();
     // initial residual / gradient
     if (ihs) {
       if (x_is_zero)
@@ -682,7 +696,7 @@ class Solver {
     try {
       setup_common();
       if (!reuse_factor) {
-        m_ = std::min<int64_t>(o_.m_init, mcap_);
+        m_ = cg_ ? 0 : std::min<int64_t>(o_.m_init, mcap_);
         k_ = 0;
       }
       const bool x0 = o_.x0 != nullptr;
@@ -883,6 +897,7 @@ class Solver {
   std::vector<int64_t> skip_events_;  // timing events of speculative steps that did not run
   hipEvent_t fev_[2] = {nullptr, nullptr};  // flag-copy events of the two pinned slots
   std::vector<std::pair<hipEvent_t, hipEvent_t>> sk_ev_;  // start / end of every sketch + factorisation
+  bool cg_ = false;
   const int* chol_flag_ = nullptr;
 };
 
@@ -1104,6 +1119,10 @@ aes_status aes_solve_keep(aes_handle h, void* stream, int64_t n, int64_t d, int6
     aes_default_options(&o);
   if (o.precision != AES_FP64) {
     h->err = "aes_solve_keep supports FP64";
+    return AES_ERR_INVALID_ARG;
+  }
+  if (o.method == AES_CG) {
+    h->err = "aes_solve_keep needs a sketched preconditioner (PCG or IHS)";
     return AES_ERR_INVALID_ARG;
   }
   auto c2 = std::make_unique<aes_ctx_s>();

@@ -388,7 +388,8 @@ void launch_rowdot(int64_t nrows, int64_t ncols, const double* M, int64_t ldm, i
 // Helpers.
 // ---------------------------------------------------------------------------------------
 __global__ void copy_cols_kernel(int64_t rows, int C, const double* __restrict__ src, int64_t lds, int csrc,
-                                 double* __restrict__ dst, int64_t ldd) {
+                                 double* __restrict__ dst, int64_t ldd, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= rows * C) return;
   const int64_t i = e / C;
@@ -397,10 +398,10 @@ __global__ void copy_cols_kernel(int64_t rows, int C, const double* __restrict__
 }
 
 void launch_copy_cols(int64_t rows, int C, const double* src, int64_t lds, int csrc, double* dst, int64_t ldd,
-                      hipStream_t s) {
+                      hipStream_t s, const int* gate) {
   if (rows * C <= 0) return;
   hipLaunchKernelGGL(copy_cols_kernel, dim3((unsigned)ceil_div(rows * C, 256)), dim3(256), 0, s, rows, C, src, lds, csrc,
-                     dst, ldd);
+                     dst, ldd, gate);
   AES_LAUNCH_CHECK();
 }
 

@@ -75,7 +75,7 @@ void launch_rowdot(int64_t nrows, int64_t ncols, const double* M, int64_t ldm, i
 
 // ---- misc (k_vec.hip) --------------------------------------------------------------------
 void launch_copy_cols(int64_t rows, int C, const double* src, int64_t lds, int csrc, double* dst,
-                      int64_t ldd, hipStream_t s);
+                      int64_t ldd, hipStream_t s, const int* gate = nullptr);
 void launch_fill(double* p, int64_t count, double v, hipStream_t s);
 void launch_transpose(int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst,
                       int64_t ldd, hipStream_t s);

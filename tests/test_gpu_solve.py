@@ -72,6 +72,34 @@ def test_sjlt_mixed_precision(small, precision):
     assert reference.rel_error(x.cpu().numpy(), small["xref"]) <= 1e-10
 
 
+def test_cg_baseline(small):
+    # the first steps follow the oracle's CG recurrence
+    kw = dict(method="cg", stop="fixed", max_iter=10, tol=1e-10)
+    x, info = aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], **kw)
+    xo, io = solvers.solve(small["A"], small["b"], small["nu"], small["lam"], solvers.Options(**kw))
+    assert info["iterations"] == io.iterations == 10 and info["final_m"] == 0 and info["resketches"] == 0
+    assert reference.rel_error(x.cpu().numpy(), xo) <= 1e-10
+    # to the stop rule: the error bound holds; the step count follows the oracle's closely (CG's
+    # recurrences drift apart in the last bits over ~200 steps)
+    kw = dict(method="cg", tol=1e-10, max_iter=5000)
+    x, info = aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], **kw)
+    xo, io = solvers.solve(small["A"], small["b"], small["nu"], small["lam"], solvers.Options(**kw))
+    assert info["status"] == "ok" and io.status == "ok"
+    assert abs(info["iterations"] - io.iterations) <= max(5, io.iterations // 10)
+    assert info["a_passes"] == info["iterations"]
+    assert reference.rel_error(x.cpu().numpy(), small["xref"]) <= 1e-10
+    # several right-hand sides (one recurrence per column)
+    rng = np.random.default_rng(6)
+    Bm = small["A"].T @ rng.standard_normal((4096, 3))
+    X, info = aes.solve(small["dA"], to_dev(Bm), small["nu"], small["dlam"], **kw)
+    Xr = reference.reference_solution(small["A"], Bm, small["nu"], small["lam"])
+    assert info["status"] == "ok" and np.all(reference.rel_error(X.cpu().numpy(), Xr) <= 1e-10)
+    with pytest.raises(aes.AesError, match="invalid_arg"):
+        aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], method="cg", precision="mixed")
+    with pytest.raises(aes.AesError, match="invalid_arg"):
+        aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], method="cg", stop="remark")
+
+
 def test_lambda_and_ragged_shape():
     P = synth.make_problem(3000, 77, "pow:1", 1e-3, lam="uniform1_10", seed=5)
     xr = reference.reference_solution(P["A"], P["b"], P["nu"], P["lam"])
