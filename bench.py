@@ -181,6 +181,10 @@ def main():
     ap.add_argument("--all", action="store_true")
     ap.add_argument("--skip-main", action="store_true", help="run only the selected extra legs (profiling)")
     ap.add_argument("--mixed", action="store_true", help="with --skip-main: the mixed-precision leg")
+    ap.add_argument("--paper", action="store_true",
+                    help="with --skip-main: the synthetic nu-sweep of Sec. 5 at n=16384, d=7000")
+    ap.add_argument("--paper-large", action="store_true",
+                    help="with --skip-main: the same at n=131072, d=7000 (nu = 1e-2, 1e-3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU sharding of the solver is a design "
@@ -199,6 +203,10 @@ def main():
 
     if args.skip_main:
         out = {}
+        if args.paper:
+            out["paper_e1"] = paper_leg(aes, torch, synth, 16384, 7000, (1e-1, 1e-2, 1e-3, 1e-4))
+        if args.paper_large:
+            out["paper_e2"] = paper_leg(aes, torch, synth, 131072, 7000, (1e-2, 1e-3))
         if args.mixed:
             out["mixed_vs_fp64"] = mixed_leg(aes, torch, synth)
         if args.batched or args.all:
@@ -281,6 +289,44 @@ def variants_leg(aes, torch, A, b, nu, lam, w, P_np, args):
             "iterations": i["iterations"], "final_m": i["final_m"], "a_passes": i["a_passes"],
             "time_sketch_ms": i["time_sketch_ms"]}
     return res
+
+
+def paper_leg(aes, torch, synth, n, d, nus):
+    """The synthetic experiments of Sec. 5 (sigma_j = 0.995^j, Lambda = I, b = A^T y) at n x d over
+    a sweep of nu, with the paper's comparison set: adaptive PCG and IHS from m = 1 (SRHT and
+    SJLT), PCG with the fixed size m = 2d, and unpreconditioned CG.  One timed solve each (the
+    first solve of each problem is repeated untimed), error against the refined reference."""
+    import numpy as np
+
+    from oracle import reference
+
+    P = synth.make_problem(n, d, "geo:0.995", nus[0], seed=0, backend="torch", device="cuda")
+    A, b = P["A"], P["b"]
+    P_np = to_numpy(P)
+    runs = [("adaptive_pcg_srht", dict(method="pcg", sketch="srht", m_init=1)),
+            ("adaptive_pcg_sjlt", dict(method="pcg", sketch="sjlt", m_init=1)),
+            ("adaptive_ihs_srht", dict(method="ihs", sketch="srht", m_init=1)),
+            ("adaptive_ihs_sjlt", dict(method="ihs", sketch="sjlt", m_init=1)),
+            ("pcg_m2d_srht", dict(method="pcg", sketch="srht", m_init=2 * d, adaptive=False)),
+            ("pcg_m2d_sjlt", dict(method="pcg", sketch="sjlt", m_init=2 * d, adaptive=False)),
+            ("cg", dict(method="cg", max_iter=20000))]
+    out = {"n": n, "d": d, "sigma": "0.995^j", "nu": {}}
+    for nu in nus:
+        xr = reference.reference_solution(P_np["A"], P_np["b"], nu, None, spectral=(P_np["V"], P_np["sigma"]))
+        res = {"d_e": reference.effective_dimension_closed(P_np["sigma"], nu)}
+        for name, kw in runs:
+            opts = dict(seed=1, tol=1e-10, max_iter=2000)
+            opts.update(kw)
+            x, infos, sec = timed_solves(aes, torch, A, b, nu, None, opts, 1, 1 if name == runs[0][0] else 0)
+            err = float(np.max(reference.rel_error(x.cpu().numpy(), xr)))
+            i = infos[-1]
+            res[name] = {"s_per_solve": sec, "rel_err": err, "valid": bool(err <= 1e-10), "status": i["status"],
+                         "iterations": i["iterations"], "final_m": i["final_m"], "a_passes": i["a_passes"],
+                         "time_sketch_ms": i["time_sketch_ms"]}
+            print(json.dumps({"paper": [n, d, nu, name, round(sec, 5), i["iterations"], i["final_m"]]}),
+                  file=sys.stderr, flush=True)
+        out["nu"][f"{nu:g}"] = res
+    return out
 
 
 def mixed_leg(aes, torch, synth):
