@@ -319,6 +319,20 @@ __device__ __forceinline__ void wht_reg_n(VT (&v)[8], int nb) {
   }
 }
 
+// Radix-16 butterflies over v[q], in the fixed bit order h = 1, 2, 4, 8.
+template <typename VT>
+__device__ __forceinline__ void wht_reg16(VT (&v)[16]) {
+#pragma unroll
+  for (int h = 1; h < 16; h <<= 1)
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if ((q & h) == 0) {
+        const VT x = v[q], y = v[q | h];
+        v[q] = x + y;
+        v[q | h] = x - y;
+      }
+}
+
 // One WHT pass over index bits [s, s+b).  MODE: 0 first pass (src = A with signs, rows >= n
 // are zero, dst = Y; tiles past n are skipped), 1 middle pass (Y -> Y), 2 last pass (Y -> SA,
 // rows selected by pos, scale), 3 single pass (A -> SA).
@@ -327,8 +341,9 @@ __device__ __forceinline__ void wht_reg_n(VT (&v)[8], int nb) {
 // A thread moves VW consecutive columns (16 bytes of the accumulation type) of 2^nf rows: the
 // lowest nf <= 3 tile bits are transformed in registers right after the loads, the highest
 // nl <= 3 bits in registers right before the stores, and only the bits between take LDS
-// round trips (3 bits each).
-template <typename TIN, typename TY, typename TOUT, int CW, int MODE>
+// round trips (3 bits each).  NF = 4 (b = 8 exactly): the low four bits after the loads and the
+// high four before the stores, sixteen rows per thread each time, so the tile crosses LDS once.
+template <typename TIN, typename TY, typename TOUT, int CW, int MODE, int NF>
 __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A, const TY* __restrict__ Ysrc,
                                                        TY* __restrict__ Ydst, TOUT* __restrict__ SA, int64_t ldsa,
                                                        int64_t n, int64_t d, int64_t lda, int64_t npad, int s, int b,
@@ -346,13 +361,15 @@ __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A
   };
   constexpr int VW = 16 / sizeof(TACC);  // columns per vector access
   constexpr int TPR = CW / VW;           // threads per row segment
+  static_assert(NF != 4 || TPR == 16, "the radix-16 path maps 256 threads onto 16 x 16 units");
+  if (NF == 4 && b != 8) return;  // launched only for 8-bit passes
   typedef TACC VT __attribute__((ext_vector_type(VW)));
   extern __shared__ unsigned char smem_raw[];
   TACC* tile = reinterpret_cast<TACC*>(smem_raw);
   const int tid = threadIdx.x;
   const int R = 1 << b;
-  const int nf = b < 3 ? b : 3;
-  const int nl = (b - nf) < 3 ? (b - nf) : 3;
+  const int nf = NF == 4 ? 4 : (b < 3 ? b : 3);
+  const int nl = NF == 4 ? 4 : ((b - nf) < 3 ? (b - nf) : 3);
   const int GF = 1 << nf, GL = 1 << nl;
   // column block fastest: concurrently resident workgroups cover whole rows of A / Y
   const int64_t tile_id = blockIdx.y;
@@ -390,6 +407,60 @@ __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A
   // All loads of a batch (2 units x 8 rows of 16 bytes, with their signs) are issued before
   // any of them is consumed, so that a workgroup keeps its tile in flight.
   const int units_in = (R / GF) * TPR;
+  if constexpr (NF == 4) {
+    // one unit per thread: 16 rows j0 .. j0 + 15 of one column vector (units_in = 256)
+    const int u = tid;
+    const int cv = (u % TPR) * VW, j0 = (u / TPR) * 16;
+    const int64_t col = c0 + cv;
+    VT v[16];
+    TACC sg[16];
+    // every load of the unit is issued before any is used (the branch on vec_in sits outside
+    // the row loops, so no row's load waits on another's use)
+    if (vec_in) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int64_t row = base + ((int64_t)(j0 + q) << s);
+        bool load = col < d;
+        if (FIRST) load = load && row < n;
+        else load = load && !(zero_bits > 0 && ((row >> zero_bits) << zero_bits) >= n);
+        sg[q] = TACC(1);
+        if (load) {
+          if (FIRST) {
+            v[q] = __builtin_nontemporal_load(
+                reinterpret_cast<const VT*>(reinterpret_cast<const TACC*>(A) + row * lda + col));
+            sg[q] = (TACC)eps[row];
+          } else {
+            v[q] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(Ysrc + ypos(row, col)));
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < VW; ++e) v[q][e] = TACC(0);
+        }
+      }
+    } else {
+      for (int q = 0; q < 16; ++q) {
+        const int64_t row = base + ((int64_t)(j0 + q) << s);
+        bool load = true;
+        if (FIRST) load = row < n;
+        else load = !(zero_bits > 0 && ((row >> zero_bits) << zero_bits) >= n);
+        sg[q] = TACC(1);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+          TACC x = TACC(0);
+          if (load && col + e < d) x = FIRST ? cvt<TACC>(A[row * lda + col + e]) : (TACC)Ysrc[ypos(row, col + e)];
+          v[q][e] = x;
+        }
+        if (FIRST && load) sg[q] = (TACC)eps[row];
+      }
+    }
+    if (FIRST) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v[q] = v[q] * sg[q];
+    }
+    wht_reg16(v);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) *reinterpret_cast<VT*>(&tile[(j0 + q) * CW + cv]) = v[q];
+  } else
   for (int u0 = 0; u0 < units_in; u0 += 256 * 2) {
     VT v[2][8];
     TACC sg[2][8];
@@ -473,6 +544,45 @@ __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A
   // ---- last nl bits + store: unit u = (row jl below bit b - nl, column vector) ---------------
   const int rl = R / GL;  // rows jl + q * rl, q < GL, form one group
   const int units_out = rl * TPR;
+  if constexpr (NF == 4) {
+    // one unit per thread: rows jl + 16 q (q < 16) of one column vector (units_out = 256)
+    const int u = tid;
+    const int cv = (u % TPR) * VW, jl = u / TPR;
+    const int64_t col = c0 + cv;
+    VT v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = *reinterpret_cast<const VT*>(&tile[(jl + q * 16) * CW + cv]);
+    wht_reg16(v);
+    if (col < d) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int j = jl + q * 16;
+        const int64_t row = base + ((int64_t)j << s);
+        if (LAST) {
+          const int32_t pr = rowflag[j];
+          if (pr < 0) continue;
+#pragma unroll
+          for (int e = 0; e < VW; ++e)
+            if (col + e < d) {
+              if constexpr (sizeof(TACC) == 8)
+                SA[(int64_t)pr * ldsa + col + e] = (TOUT)(v[q][e] * scale);
+              else
+                SA[(int64_t)pr * ldsa + col + e] = cvt<TOUT>((float)(v[q][e] * (float)scale));
+            }
+        } else {
+          if (MODE == 0 && need && !rowflag[j]) continue;
+          if ((d % VW) == 0) {
+            __builtin_nontemporal_store(v[q], reinterpret_cast<VT*>(Ydst + ypos(row, col)));
+          } else {
+#pragma unroll
+            for (int e = 0; e < VW; ++e)
+              if (col + e < d) Ydst[ypos(row, col + e)] = (TY)v[q][e];
+          }
+        }
+      }
+    }
+    return;
+  }
   for (int u = tid; u < units_out; u += 256) {
     const int cv = (u % TPR) * VW, jl = u / TPR;
     const int64_t col = c0 + cv;
@@ -512,14 +622,14 @@ __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A
   }
 }
 
-template <typename TIN, typename TY, typename TOUT, int CW, int MODE>
+template <typename TIN, typename TY, typename TOUT, int CW, int MODE, int NF>
 static void wht_launch_cw(int64_t npad, size_t shmem, hipStream_t st, const TIN* A, const TY* Ysrc, TY* Ydst, TOUT* SA,
                           int64_t ldsa, int64_t n, int64_t d, int64_t lda, int s, int b, int zero_bits,
                           const double* eps, const int32_t* pos, double scale, const int32_t* need,
                           int check_tiles, int pw) {
   const int a_aligned = ((uintptr_t)A % 16) == 0;
   const dim3 grid((unsigned)ceil_div(d, CW), (unsigned)(npad >> b));
-  hipLaunchKernelGGL((wht_pass_kernel<TIN, TY, TOUT, CW, MODE>), grid, dim3(256), shmem, st, A, Ysrc, Ydst, SA, ldsa, n,
+  hipLaunchKernelGGL((wht_pass_kernel<TIN, TY, TOUT, CW, MODE, NF>), grid, dim3(256), shmem, st, A, Ysrc, Ydst, SA, ldsa, n,
                      d, lda, npad, s, b, zero_bits, eps, pos, scale, a_aligned, need, check_tiles, pw);
   AES_LAUNCH_CHECK();
 }
@@ -532,12 +642,19 @@ static void wht_launch(int64_t npad, hipStream_t st, const TIN* A, const TY* Ysr
                        const int32_t* pos, double scale, const int32_t* need, int check_tiles, int pw) {
   using TACC = typename AccOf<TY>::type;
   constexpr int CW_WIDE = 256 / sizeof(TACC), CW_NARROW = 128 / sizeof(TACC);
-  if (b <= 8)
-    wht_launch_cw<TIN, TY, TOUT, CW_WIDE, MODE>(npad, (size_t)(1 << b) * CW_WIDE * sizeof(TACC), st, A, Ysrc, Ydst, SA,
-                                                ldsa, n, d, lda, s, b, zero_bits, eps, pos, scale, need, check_tiles,
-                                                pw);
+  // the radix-16 register path (one LDS crossing) measured faster for the last pass and for a
+  // pruned first pass; a first pass that writes all of Y is faster with the radix-8 path
+  const bool r16 = b == 8 && (MODE == 2 || (MODE == 0 && need != nullptr));
+  if (r16)
+    wht_launch_cw<TIN, TY, TOUT, CW_WIDE, MODE, 4>(npad, (size_t)(1 << b) * CW_WIDE * sizeof(TACC), st, A, Ysrc, Ydst,
+                                                   SA, ldsa, n, d, lda, s, b, zero_bits, eps, pos, scale, need,
+                                                   check_tiles, pw);
+  else if (b <= 8)
+    wht_launch_cw<TIN, TY, TOUT, CW_WIDE, MODE, 3>(npad, (size_t)(1 << b) * CW_WIDE * sizeof(TACC), st, A, Ysrc, Ydst,
+                                                   SA, ldsa, n, d, lda, s, b, zero_bits, eps, pos, scale, need,
+                                                   check_tiles, pw);
   else
-    wht_launch_cw<TIN, TY, TOUT, CW_NARROW, MODE>(npad, (size_t)(1 << b) * CW_NARROW * sizeof(TACC), st, A, Ysrc, Ydst,
+    wht_launch_cw<TIN, TY, TOUT, CW_NARROW, MODE, 3>(npad, (size_t)(1 << b) * CW_NARROW * sizeof(TACC), st, A, Ysrc, Ydst,
                                                   SA, ldsa, n, d, lda, s, b, zero_bits, eps, pos, scale, need,
                                                   check_tiles, pw);
 }
