@@ -19,10 +19,14 @@ Extra legs (outside the timed region of the headline value):
     batched driver in FP32 storage + FP64 refinement and in FP64, a stratified sample of four
     problems validated against the oracle;
   * --adjoint (or --all): forward + backward of the autograd Function on n = 131072, d = 1024
-    (sigma_j = j^-1/2, nu = 1e-2), gradients validated against the dense oracle.
+    (sigma_j = j^-1/2, nu = 1e-2), gradients validated against the dense oracle;
+  * variants (skip with --no-variants): the headline workload solved with the Gaussian and
+    SJLT sketches, by adaptive IHS, and by the unpreconditioned CG baseline;
+  * --skip-main --paper / --paper-large: the synthetic nu-sweeps of the paper's numerical
+    section (n = 16384 or 131072, d = 7000, sigma_j = 0.995^j) with its comparison set.
 
 --hv-only runs just fused H.v launches and a calibration copy (for rocprofv3 counter runs);
---sketch-only M runs just SRHT sketches of size M of the workload's A (WHT traffic counters).
+--sketch-only M runs just sketches (--sketch kind) of size M of the workload's A.
 """
 import argparse
 import hashlib
@@ -58,10 +62,13 @@ def load_traffic(n, d):
     return c.get("bytes_per_launch")
 
 
-def cpu_baseline(P_np, info):
-    """Oracle (numpy FP64) timed on the host: one H.v pass, one SRHT sketch at the final m and
-    one factorisation of H_S on the full workload; the per-solve time is these unit times
-    scaled by the solve's own counts (passes over A, sketches)."""
+def cpu_baseline(P_np, info, m_init):
+    """Oracle (numpy FP64) timed on the host on a bounded sample of the workload: three H.v passes
+    (median), SRHT sketches at the first, a middle and the final sketch size (the oracle's
+    transform costs about the same at every m), and the factorisation of H_S at every sketch size
+    of the solve (Woodbury below d, Cholesky from d on; timed on row blocks of the final sketch).
+    Per solve = passes x H.v + the sketches interpolated over the solve's m sequence + the
+    factorisations."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
@@ -72,24 +79,39 @@ def cpu_baseline(P_np, info):
     A, lam, nu = P_np["A"], P_np["lam"], P_np["nu"]
     d = A.shape[1]
     p = np.random.default_rng(0).standard_normal((d, 1))
-    t0 = time.perf_counter()
-    solvers.hess_apply(A, nu, lam, p)
-    t_hv = time.perf_counter() - t0
-    m = int(info["final_m"])
-    t0 = time.perf_counter()
-    SA = osk.srht(A, m, 1, 0)
-    t_sk = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    ofac.SketchedHessian(SA, nu, lam)
-    t_fac = time.perf_counter() - t0
-    sketches = int(info["resketches"]) + 1
-    est = int(info["a_passes"]) * t_hv + sketches * (t_sk + t_fac)
+    t_hv = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        solvers.hess_apply(A, nu, lam, p)
+        t_hv.append(time.perf_counter() - t0)
+    t_hv = float(np.median(t_hv))
+    K = int(info["resketches"])
+    ms = [min(m_init << k, int(info["final_m"])) for k in range(K + 1)]
+    picks = sorted({0, K // 2, K})
+    t_sk = {}
+    SA_hi = None
+    for k in picks:
+        t0 = time.perf_counter()
+        SA = osk.srht(A, ms[k], 1, k)
+        t_sk[k] = time.perf_counter() - t0
+        if k == K:
+            SA_hi = SA
+    sk_total = float(np.sum(np.interp(np.arange(K + 1), picks, [t_sk[k] for k in picks])))
+    fac_total = 0.0
+    for m in ms:
+        t0 = time.perf_counter()
+        ofac.SketchedHessian(SA_hi[:m], nu, lam)
+        fac_total += time.perf_counter() - t0
+    est = int(info["a_passes"]) * t_hv + sk_total + fac_total
     threads = max([x.get("num_threads", 1) for x in threadpool_info()] + [1])
+    sample = 3 * t_hv + sum(t_sk.values()) + fac_total
     return {"value": est, "unit": "s", "cores": int(threads), "kind": "oracle",
-            "sample": (f"one H.v pass ({t_hv:.3f} s), one SRHT sketch at m={m} ({t_sk:.2f} s) and one H_S "
-                       f"factorisation ({t_fac:.2f} s) on the full workload; per solve = {info['a_passes']} passes "
-                       f"+ {sketches} sketches+factorisations (the solve's counts)"),
-            "sample_seconds": t_hv + t_sk + t_fac}
+            "sample": (f"3 H.v passes (median {t_hv:.3f} s), SRHT sketches at m = "
+                       f"{', '.join(str(ms[k]) for k in picks)} ({', '.join(f'{t_sk[k]:.2f}' for k in picks)} s) and "
+                       f"the {len(ms)} factorisations of the solve's m sequence ({fac_total:.2f} s) on the full "
+                       f"workload; per solve = {info['a_passes']} passes + {len(ms)} sketches (interpolated) + "
+                       f"{len(ms)} factorisations"),
+            "sample_seconds": sample}
 
 
 def reference_error(P_np, x, spectral=None):
@@ -263,7 +285,7 @@ def main():
         out["adjoint"] = adjoint_leg(aes, torch, synth)
 
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(P_np, info)
+        cb = cpu_baseline(P_np, info, w.m_init)
         cb["gpu_speedup"] = cb["value"] / sec
         out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
