@@ -134,8 +134,10 @@ void aes_default_options(aes_options* o);
  * H_S = (SA)^T SA + nu^2 Lambda, factorised as in Sec. 4.1 (Cholesky of H_S for m >= d,
  * Woodbury form with the Cholesky of W_S for m < d).  When the improvement test of the
  * algorithm fails, m doubles, a fresh S is drawn and the method restarts at x_t.
- *   A       device, n x d, row-major, lda >= d
- *   b       device, d x c, ldb >= c
+ *   A       device, n x d, row-major, lda >= d; 1 <= d <= 32768 (the single-pass fused
+ *           H.v serves d <= 8192 with one right-hand side; wider problems and several
+ *           right-hand sides use two MFMA products A v and A^T (A v) per step)
+ *   b       device, d x c, ldb >= c, 1 <= c <= 32
  *   lambda  device, length d, all > 0; NULL means Lambda = I
  *   x       device, d x c output, ldx >= c
  *   info    host, output (may be NULL)
@@ -203,7 +205,7 @@ void aes_ctx_free(aes_ctx ctx);
 
 /* q = A^T (A p) + nu^2 lambda .* p  and  pHp = ||A p||^2 + nu^2 p^T Lambda p   (single pass
  * over A; the per-iteration product of Sec. 4.1 "Per-iteration cost").
- *   p, q: device length d.  pHp: device, 1 double.  lambda: device or NULL. */
+ *   p, q: device length d <= 8192.  pHp: device, 1 double.  lambda: device or NULL. */
 aes_status aes_hv(aes_handle h, void* stream, int64_t n, int64_t d, const double* A, int64_t lda,
                   double nu, const double* lambda, const double* p, double* q, double* pHp);
 

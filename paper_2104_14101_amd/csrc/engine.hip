@@ -116,11 +116,16 @@ struct ProblemDesc {
   int64_t ldx;
 };
 
+// Widest d: the fused single-pass H.v keeps a d-vector slice per thread and takes d <= 8192;
+// wider problems (and several right-hand sides) use the two-product MFMA path.
+constexpr int64_t kMaxFusedD = 8192;
+constexpr int64_t kMaxD = 32768;
+
 void validate(const ProblemDesc& P, double tol, const aes_options& o) {
   auto bad = [](const char* m) { throw StatusError(AES_ERR_INVALID_ARG, m); };
   if (P.n < 1 || P.d < 1 || P.c < 1) bad("n, d and c must be >= 1");
   if (P.c > 32) bad("at most 32 right-hand sides per problem");
-  if (P.d > 8192) bad("d > 8192 is not supported");
+  if (P.d > kMaxD) bad("d > 32768 is not supported");
   if (P.lda < P.d) bad("lda < d");
   if (P.ldb < P.c || P.ldx < P.c) bad("ldb and ldx must be >= c");
   if (!P.A || !P.b || !P.x) bad("A, b and x must be non-null");
@@ -161,6 +166,7 @@ class Solver {
     mixed_ = o.precision == AES_MIXED || o.precision == AES_MIXED_FP32;
     sketch32_ = o.precision == AES_MIXED_FP32;
     cg_ = o.method == AES_CG;
+    fused_ = C_ == 1 && d_ <= kMaxFusedD;
     if (cg_) o_.adaptive = 0;  // the baseline has no sketch, no test and no resketch
     pinned_ = h->pinned;
   }
@@ -203,7 +209,7 @@ class Solver {
     scal_ = B<double>("scal", 8 * C_ + 8);
     active_ = B<int>("active", C_);
     nwg_ = hv_num_blocks(h_->num_cu, n_);
-    if (C_ == 1) {
+    if (fused_) {
       part_ = B<double>("part", (size_t)nwg_ * d_);
       spart_ = B<double>("spart", nwg_);
     } else {
@@ -225,7 +231,7 @@ class Solver {
       // the FP32 copy feeds the inner products and every sketch of the mixed modes
       A32_ = B<float>("A32", (size_t)n_ * d_);
       launch_cast<float>(n_, d_, P_.A, P_.lda, A32_, s_);
-      if (C_ > 1) {
+      if (!fused_) {
         V32_ = B<float>("V32", (size_t)d_ * C_);
         Z32_ = B<float>("Z32", (size_t)n_ * C_);
         part32_ = B<float>("part32", (size_t)msplit_ * d_ * C_);
@@ -259,7 +265,7 @@ class Solver {
   // out = sgn * (H v) + bsgn * b    (H = A^T A + nu^2 Lambda); A in FP64 or (inner) FP32.
   void hv(const double* v, double* out, double sgn, const double* bb, double bsgn, bool use32,
           const int* gate = nullptr) {
-    if (C_ == 1) {
+    if (fused_) {
       const bool prof = o_.profile && !use32;
       if (prof) AES_HIP(hipEventRecord(h_->event(2 * n_events_), s_));
       if (use32)
@@ -513,7 +519,7 @@ class Solver {
     // previous step's finish (or the initialisation) sets when it accepted and has active
     // columns, so the next step is enqueued before the host has read the flags of the current
     // one; the host then reads them through an event on their own pinned slot.
-    const bool spec = C_ == 1;
+    const bool spec = fused_;
     int* gate = spec ? B<int>("gate", 1) : nullptr;
     if (!reuse_factor && !cg_) sketch_factor();
     // initial residual / gradient
@@ -561,7 +567,7 @@ class Solver {
     auto enqueue_step = [&](int64_t tt, int force, int slot) -> Step {
       const double thr = thr_of(lc, lphi, tt, I);
       const int at_cap = m_ >= mcap_ ? 1 : 0;
-      const int64_t ev = (o_.profile && !use32 && C_ == 1) ? n_events_ : -1;
+      const int64_t ev = (o_.profile && !use32 && fused_) ? n_events_ : -1;
       const double seq = spec ? (seq_ctr += 1.0) : -1.0;
       if (ihs) {
         launch_ihs_candidate(d_, C_, x, Pv_, mu, XP_, active_, s_, gate);
@@ -571,7 +577,7 @@ class Solver {
                           stop_rule, stop_scale, stop_sr_, tol2_, s_, seq);
       } else {
         hv(Pv_, Q_, 1.0, nullptr, 0.0, use32, gate);
-        launch_pcg_candidate(d_, C_, C_ == 1 ? spart_ : nullptr, nwg_, lam_, nu2_, x, R_, Pv_, Q_, XP_, RP_, scal_,
+        launch_pcg_candidate(d_, C_, fused_ ? spart_ : nullptr, nwg_, lam_, nu2_, x, R_, Pv_, Q_, XP_, RP_, scal_,
                              active_, s_, gate);
         apply(RP_, RTP_, gate);
         launch_pcg_finish(d_, C_, x, R_, Pv_, XP_, RP_, RTP_, scal_, active_, gate, thr, force, o_.adaptive, at_cap,
@@ -897,6 +903,7 @@ class Solver {
   std::vector<int64_t> skip_events_;  // timing events of speculative steps that did not run
   hipEvent_t fev_[2] = {nullptr, nullptr};  // flag-copy events of the two pinned slots
   std::vector<std::pair<hipEvent_t, hipEvent_t>> sk_ev_;  // start / end of every sketch + factorisation
+  bool fused_ = true;  // single-RHS fused H.v (and the speculative step pipeline)
   bool cg_ = false;
   const int* chol_flag_ = nullptr;
 };

@@ -100,6 +100,19 @@ def test_cg_baseline(small):
         aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], method="cg", stop="remark")
 
 
+def test_wide_problem_two_product_path():
+    # d > 8192: the steps use the two-product MFMA H.v (and no speculative enqueueing)
+    P = synth.make_problem(12000, 8300, "geo:0.995", 1e-2, seed=17, backend="torch", device="cuda")
+    Pn = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in P.items()}
+    xr = reference.reference_solution(Pn["A"], Pn["b"], Pn["nu"], None, spectral=(Pn["V"], Pn["sigma"]))
+    for method in ("pcg", "cg"):
+        x, info = aes.solve(P["A"], P["b"], P["nu"], None, method=method, m_init=64, seed=3, tol=1e-10,
+                            max_iter=3000)
+        assert info["status"] == "ok", (method, info)
+        assert reference.rel_error(x.cpu().numpy(), xr) <= 1e-10
+        assert info["a_passes"] >= info["iterations"]
+
+
 def test_lambda_and_ragged_shape():
     P = synth.make_problem(3000, 77, "pow:1", 1e-3, lam="uniform1_10", seed=5)
     xr = reference.reference_solution(P["A"], P["b"], P["nu"], P["lam"])
