@@ -207,6 +207,9 @@ def main():
                     help="with --skip-main: the synthetic nu-sweep of Sec. 5 at n=16384, d=7000")
     ap.add_argument("--paper-large", action="store_true",
                     help="with --skip-main: the same at n=131072, d=7000 (nu = 1e-2, 1e-3)")
+    ap.add_argument("--paper-e3", action="store_true",
+                    help="with --skip-main: the same at n=524288, d=14000 (A is 58.7 GB; nu = 1e-2 .. 1e-4; "
+                         "CG capped at 2000 steps; errors against PCG at m = 2d to 1e-12)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU sharding of the solver is a design "
@@ -229,6 +232,9 @@ def main():
             out["paper_e1"] = paper_leg(aes, torch, synth, 16384, 7000, (1e-1, 1e-2, 1e-3, 1e-4))
         if args.paper_large:
             out["paper_e2"] = paper_leg(aes, torch, synth, 131072, 7000, (1e-2, 1e-3))
+        if args.paper_e3:
+            out["paper_e3"] = paper_leg(aes, torch, synth, 524288, 14000, (1e-2, 1e-3, 1e-4), cross=True,
+                                        cg_iters=2000)
         if args.mixed:
             out["mixed_vs_fp64"] = mixed_leg(aes, torch, synth)
         if args.batched or args.all:
@@ -313,29 +319,41 @@ def variants_leg(aes, torch, A, b, nu, lam, w, P_np, args):
     return res
 
 
-def paper_leg(aes, torch, synth, n, d, nus):
+def paper_leg(aes, torch, synth, n, d, nus, cross=False, cg_iters=20000):
     """The synthetic experiments of Sec. 5 (sigma_j = 0.995^j, Lambda = I, b = A^T y) at n x d over
     a sweep of nu, with the paper's comparison set: adaptive PCG and IHS from m = 1 (SRHT and
     SJLT), PCG with the fixed size m = 2d, and unpreconditioned CG.  One timed solve each (the
-    first solve of each problem is repeated untimed), error against the refined reference."""
+    first solve of each problem is repeated untimed).  Error against the oracle's refined
+    reference; with cross=True (sizes the host oracle cannot take) against a PCG solve at
+    m = 2d to 1e-12 instead."""
     import numpy as np
 
     from oracle import reference
 
-    P = synth.make_problem(n, d, "geo:0.995", nus[0], seed=0, backend="torch", device="cuda")
+    print(json.dumps({"paper": [n, d, "generating"]}), file=sys.stderr, flush=True)
+    P = synth.make_problem(n, d, "geo:0.995", nus[0], seed=0, backend="torch", device="cuda",
+                           ortho="cholqr" if cross else "qr")
     A, b = P["A"], P["b"]
-    P_np = to_numpy(P)
+    torch.cuda.empty_cache()
+    print(json.dumps({"paper": [n, d, "generated"]}), file=sys.stderr, flush=True)
+    P_np = None if cross else to_numpy(P)
     runs = [("adaptive_pcg_srht", dict(method="pcg", sketch="srht", m_init=1)),
             ("adaptive_pcg_sjlt", dict(method="pcg", sketch="sjlt", m_init=1)),
             ("adaptive_ihs_srht", dict(method="ihs", sketch="srht", m_init=1)),
             ("adaptive_ihs_sjlt", dict(method="ihs", sketch="sjlt", m_init=1)),
             ("pcg_m2d_srht", dict(method="pcg", sketch="srht", m_init=2 * d, adaptive=False)),
             ("pcg_m2d_sjlt", dict(method="pcg", sketch="sjlt", m_init=2 * d, adaptive=False)),
-            ("cg", dict(method="cg", max_iter=20000))]
-    out = {"n": n, "d": d, "sigma": "0.995^j", "nu": {}}
+            ("cg", dict(method="cg", max_iter=cg_iters))]
+    out = {"n": n, "d": d, "sigma": "0.995^j", "nu": {},
+           "reference": "PCG at m = 2d to 1e-12" if cross else "oracle refined reference"}
     for nu in nus:
-        xr = reference.reference_solution(P_np["A"], P_np["b"], nu, None, spectral=(P_np["V"], P_np["sigma"]))
-        res = {"d_e": reference.effective_dimension_closed(P_np["sigma"], nu)}
+        if cross:
+            xr_t, _ = aes.solve(A, b, nu, None, method="pcg", sketch="srht", m_init=2 * d, adaptive=False, seed=7,
+                                tol=1e-12, max_iter=2000)
+            xr = xr_t.cpu().numpy()
+        else:
+            xr = reference.reference_solution(P_np["A"], P_np["b"], nu, None, spectral=(P_np["V"], P_np["sigma"]))
+        res = {"d_e": reference.effective_dimension_closed(P["sigma"], nu)}
         for name, kw in runs:
             opts = dict(seed=1, tol=1e-10, max_iter=2000)
             opts.update(kw)

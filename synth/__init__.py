@@ -69,12 +69,31 @@ def make_matrix_numpy(n, d, sigma, rng):
     return np.ascontiguousarray(A), V
 
 
+def _lower_inverse(torch, L, leaf=512):
+    """Inverse of a lower-triangular matrix by 2 x 2 blocks (products only; small triangular
+    solves at the leaves): inv([[L11, 0], [L21, L22]]) = [[X11, 0], [-X22 L21 X11, X22]]."""
+    d = L.shape[0]
+    if d <= leaf:
+        return torch.linalg.solve_triangular(L, torch.eye(d, device=L.device, dtype=L.dtype), upper=False)
+    h = d // 2
+    X11 = _lower_inverse(torch, L[:h, :h].contiguous(), leaf)
+    X22 = _lower_inverse(torch, L[h:, h:].contiguous(), leaf)
+    X = torch.zeros_like(L)
+    X[:h, :h] = X11
+    X[h:, h:] = X22
+    X[h:, :h] = -(X22 @ (L[h:, :h].contiguous() @ X11))
+    return X
+
+
 def make_problem(n, d, decay, nu, lam="identity", nrhs=1, seed=0, backend="numpy", device=None,
-                 with_xt=False, dtype=np.float64):
+                 with_xt=False, dtype=np.float64, ortho="qr"):
     """Draw one problem.  Returns a dict with A, b, nu, lam, sigma, V (and y, xt).
 
     backend 'numpy' returns numpy arrays; backend 'torch' returns torch tensors on `device`
-    (A, b, lam, V, xt) with sigma as numpy.
+    (A, b, lam, V, xt) with sigma as numpy.  ortho (torch backend): how U is made orthonormal
+    from the Gaussian matrix G — 'qr' (Householder QR) or 'cholqr' (U = G R^{-1} with
+    R^T R = G^T G, two large products instead of a QR; accurate for the tall Gaussian G, whose
+    condition number is about (sqrt n + sqrt d) / (sqrt n - sqrt d)).
     """
     sigma = singular_values(d, decay)
     if backend == "numpy":
@@ -100,7 +119,14 @@ def make_problem(n, d, decay, nu, lam="identity", nrhs=1, seed=0, backend="numpy
         g = torch.Generator(device=dev)
         g.manual_seed(SEED_BASE * 1000003 + int(seed))
         G = torch.randn((n, d), generator=g, device=dev, dtype=torch.float64)
-        U, _ = torch.linalg.qr(G, mode="reduced")
+        if ortho == "cholqr":
+            L = torch.linalg.cholesky(G.T @ G)
+            Rinv = _lower_inverse(torch, L).T.contiguous()
+            del L
+            U = G @ Rinv
+            del Rinv
+        else:
+            U, _ = torch.linalg.qr(G, mode="reduced")
         del G
         Gv = torch.randn((d, d), generator=g, device=dev, dtype=torch.float64)
         V, _ = torch.linalg.qr(Gv, mode="reduced")
