@@ -422,7 +422,11 @@ def batched_leg(aes, torch, synth):
         sec = (time.perf_counter() - t0) / steps
         outs[prec] = r
         res[prec] = {"s_per_batch": sec, "statuses_ok": sum(1 for _, i in r if i["status"] == "ok"),
-                     "max_final_m": max(i["final_m"] for _, i in r)}
+                     "max_final_m": max(i["final_m"] for _, i in r),
+                     "sum_problem_ms": sum(i["time_total_ms"] for _, i in r),
+                     "sum_sketch_ms": sum(i["time_sketch_ms"] for _, i in r),
+                     "sum_a_passes": sum(i["a_passes"] for _, i in r),
+                     "sum_resketches": sum(i["resketches"] for _, i in r)}
     order = sorted(range(64), key=lambda i: specs[i]["n"] * specs[i]["d"])
     pick = sorted({order[0], order[-1], min(range(64), key=lambda i: specs[i]["nu"]), order[32]})
     errs = {"mixed_fp32": [], "fp64": []}

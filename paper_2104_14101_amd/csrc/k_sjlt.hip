@@ -21,8 +21,6 @@ constexpr int kScanChunk = 4096;
 
 size_t sjlt_blocks(int64_t n) { return (size_t)ceil_div(n, kSjBlk); }
 
-size_t sjlt_scan_chunks(int64_t m, int64_t n) { return (size_t)ceil_div(m * (int64_t)sjlt_blocks(n), kScanChunk); }
-
 __global__ void sjlt_zero_kernel(int32_t* __restrict__ p, int64_t count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) p[i] = 0;
