@@ -205,7 +205,8 @@ void aes_ctx_free(aes_ctx ctx);
 
 /* q = A^T (A p) + nu^2 lambda .* p  and  pHp = ||A p||^2 + nu^2 p^T Lambda p   (single pass
  * over A; the per-iteration product of Sec. 4.1 "Per-iteration cost").
- *   p, q: device length d <= 8192.  pHp: device, 1 double.  lambda: device or NULL. */
+ *   For d > 8192 (up to 32768) two streaming passes, z = A p then A^T z, and pHp = p . q.
+ *   p, q: device length d.  pHp: device, 1 double.  lambda: device or NULL. */
 aes_status aes_hv(aes_handle h, void* stream, int64_t n, int64_t d, const double* A, int64_t lda,
                   double nu, const double* lambda, const double* p, double* q, double* pHp);
 

@@ -221,6 +221,10 @@ class Solver {
       msplit_rows_ = split_rows;
       part_ = B<double>("part", (size_t)msplit_ * d_ * C_);
       Z_ = B<double>("Z", (size_t)n_ * C_);
+      if (C_ == 1) {
+        atz_nrb_ = atz_blocks(h_->num_cu, n_, d_, &atz_rows_);
+        atz_part_ = B<double>("atz_part", (size_t)atz_nrb_ * d_);
+      }
     }
     AES_HIP(hipMemsetAsync(scal_, 0, (8 * C_ + 8) * sizeof(double), s_));
     launch_copy_cols(d_, C_, P_.b, P_.ldb, (int)c_, Bv_, C_, s_);
@@ -277,6 +281,12 @@ class Solver {
         ++n_events_;
       }
       launch_hv_colsum(part_, nwg_, d_, 1, v, lam_, nu2_, sgn, bb, bsgn, out, s_, gate);
+    } else if (C_ == 1 && !use32) {
+      // wider than the fused pass: z = A v, then the row-block partials of A^T z (two streaming
+      // passes over A), summed in a fixed order
+      launch_rowdot(n_, d_, P_.A, P_.lda, 0, v, 1, nullptr, 1.0, nullptr, nullptr, 1.0, Z_, s_);
+      launch_atz(P_.A, n_, d_, P_.lda, Z_, atz_part_, atz_nrb_, atz_rows_, s_);
+      launch_hv_colsum(atz_part_, atz_nrb_, d_, 1, v, lam_, nu2_, sgn, bb, bsgn, out, s_);
     } else if (use32) {
       // FP32 storage and MFMA: Z = A V (n x C), partial Q_w = A_w^T Z_w over row blocks
       narrow_f64(d_ * C_, v, V32_, s_);
@@ -903,6 +913,9 @@ class Solver {
   std::vector<int64_t> skip_events_;  // timing events of speculative steps that did not run
   hipEvent_t fev_[2] = {nullptr, nullptr};  // flag-copy events of the two pinned slots
   std::vector<std::pair<hipEvent_t, hipEvent_t>> sk_ev_;  // start / end of every sketch + factorisation
+  double* atz_part_ = nullptr;
+  int atz_nrb_ = 0;
+  int64_t atz_rows_ = 0;
   bool fused_ = true;  // single-RHS fused H.v (and the speculative step pipeline)
   bool cg_ = false;
   const int* chol_flag_ = nullptr;
@@ -1229,14 +1242,25 @@ aes_status aes_hv(aes_handle h, void* stream, int64_t n, int64_t d, const double
   if (!h) return AES_ERR_INVALID_ARG;
   return guard(h, [&] {
     if (n < 1 || d < 1 || lda < d || !A || !p || !q || !(nu >= 0)) throw StatusError(AES_ERR_INVALID_ARG, "bad arguments");
-    if (d > 8192) throw StatusError(AES_ERR_INVALID_ARG, "d > 8192 is not supported");
+    if (d > kMaxD) throw StatusError(AES_ERR_INVALID_ARG, "d > 32768 is not supported");
     set_device(h);
     hipStream_t s = (hipStream_t)stream;
     const int nwg = hv_num_blocks(h->num_cu, n);
-    double* part = h->buf<double>("hv.part", (size_t)nwg * d);
-    double* spart = h->buf<double>("hv.spart", nwg);
-    launch_hv_fused<double>(A, n, d, lda, p, part, spart, nwg, s);
-    launch_hv_colsum(part, nwg, d, 1, p, lambda, nu * nu, 1.0, nullptr, 0.0, q, s);
+    double* spart = nullptr;  // wide problems: pHp = p . q
+    if (d <= kMaxFusedD) {
+      double* part = h->buf<double>("hv.part", (size_t)nwg * d);
+      spart = h->buf<double>("hv.spart", nwg);
+      launch_hv_fused<double>(A, n, d, lda, p, part, spart, nwg, s);
+      launch_hv_colsum(part, nwg, d, 1, p, lambda, nu * nu, 1.0, nullptr, 0.0, q, s);
+    } else {
+      int64_t rows = 0;
+      const int nrb = atz_blocks(h->num_cu, n, d, &rows);
+      double* z = h->buf<double>("hv.z", n);
+      double* part = h->buf<double>("hv.atz", (size_t)nrb * d);
+      launch_rowdot(n, d, A, lda, 0, p, 1, nullptr, 1.0, nullptr, nullptr, 1.0, z, s);
+      launch_atz(A, n, d, lda, z, part, nrb, rows, s);
+      launch_hv_colsum(part, nrb, d, 1, p, lambda, nu * nu, 1.0, nullptr, 0.0, q, s);
+    }
     if (pHp) {
       // ||A p||^2 + nu^2 p^T Lambda p: the candidate kernel's reduction with a zero state
       double* scal = h->buf<double>("hv.scal", 16);

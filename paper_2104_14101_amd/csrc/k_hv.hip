@@ -183,6 +183,76 @@ void launch_hv_fused<float>(const float* A, int64_t n, int64_t d, int64_t lda, c
   throw std::invalid_argument("hv_fused: d > 8192 is not supported");
 }
 
+// Second pass of the two-pass H.v for problems wider than the fused kernel takes (d > 8192):
+// part[w][j] = sum over the rows i of row block w, in order, of z_i A[i, j] (z = A v from the
+// first pass).  Workgroup (cb, w) covers columns [2048 cb, 2048 cb + 2048) of row block w;
+// thread t owns the 16-byte vectors 256 v + t (v < 4) of that column block, so every load
+// instruction of a wave covers 1 KiB of a row, and keeps four rows' loads in flight.
+__global__ __launch_bounds__(256) void atz_kernel(const double* __restrict__ A, int64_t n, int64_t d, int64_t lda,
+                                                  int vec, const double* __restrict__ z, int64_t rows,
+                                                  double* __restrict__ part) {
+  typedef double d2v __attribute__((ext_vector_type(2)));
+  const int tid = threadIdx.x;
+  const int64_t w = blockIdx.y;
+  const int64_t i0 = w * rows;
+  const int64_t i1 = i0 + rows < n ? i0 + rows : n;
+  int64_t c0[4];
+  bool full[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    c0[v] = (int64_t)blockIdx.x * 2048 + (int64_t)(v * 256 + tid) * 2;
+    full[v] = vec && c0[v] + 2 <= d;
+  }
+  double acc[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+  for (int64_t i = i0; i < i1; i += 4) {
+    double x[4][4][2], zi[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t r = i + u;
+      const bool ok = r < i1;
+      zi[u] = ok ? z[r] : 0.0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (ok && full[v]) {
+          const d2v y = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(A + r * lda + c0[v]));
+          x[u][v][0] = y[0];
+          x[u][v][1] = y[1];
+        } else {
+#pragma unroll
+          for (int e = 0; e < 2; ++e) x[u][v][e] = (ok && c0[v] + e < d) ? A[r * lda + c0[v] + e] : 0.0;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) acc[v][e] = fma(zi[u], x[u][v][e], acc[v][e]);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+      if (c0[v] + e < d) part[w * d + c0[v] + e] = acc[v][e];
+}
+
+int atz_blocks(int num_cu, int64_t n, int64_t d, int64_t* rows) {
+  const int64_t cb = ceil_div(d, 2048);
+  int64_t nrb = std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 4), 4 * (int64_t)num_cu / cb));
+  const int64_t r = round_up(ceil_div(n, nrb), 4);
+  *rows = r;
+  return (int)ceil_div(n, r);
+}
+
+void launch_atz(const double* A, int64_t n, int64_t d, int64_t lda, const double* z, double* part, int nrb,
+                int64_t rows, hipStream_t s) {
+  const int vec = ((uintptr_t)A % 16 == 0) && (lda % 2 == 0);
+  hipLaunchKernelGGL(atz_kernel, dim3((unsigned)ceil_div(d, 2048), (unsigned)nrb), dim3(256), 0, s, A, n, d, lda, vec, z,
+                     rows, part);
+  AES_LAUNCH_CHECK();
+}
+
 // out[j, c] = sgn * (sum_w part[w][j][c] + nu2 * lam[j] * v[j, c]) + bsgn * b[j, c]
 // 256 threads = 16 (j,c)-elements x 16 partial groups; a thread keeps 8 loads in flight and
 // the groups are combined in a fixed order (deterministic).

@@ -28,6 +28,12 @@ void launch_hv_colsum(const double* part, int nwg, int64_t d, int C, const doubl
 
 void launch_hv_colsum_f32(const float* part, int nwg, int64_t d, int C, const double* v, const double* lam,
                           double nu2, double sgn, const double* b, double bsgn, double* out, hipStream_t s);
+// Two-pass H.v for wide problems (d > 8192): z = A v by launch_rowdot, then
+// part[w][j] = sum_{i in row block w} z_i A[i, j] for the nrb row blocks of `rows` rows that
+// atz_blocks chooses, then launch_hv_colsum over the nrb partials.
+int atz_blocks(int num_cu, int64_t n, int64_t d, int64_t* rows);
+void launch_atz(const double* A, int64_t n, int64_t d, int64_t lda, const double* z, double* part, int nrb,
+                int64_t rows, hipStream_t s);
 // out[c] = ||e[:, c]||^2, out[C + c] = ||x[:, c]||^2
 void launch_colnorm2(int64_t d, int C, const double* e, const double* x, double* out, hipStream_t s);
 

@@ -14,8 +14,9 @@ from _helpers import hv_bound, to_dev
 pytestmark = pytest.mark.gpu
 
 
+# d > 8192: the two-pass form (odd d: scalar loads; 9000: ragged last column block)
 @pytest.mark.parametrize("n,d", [(1, 1), (37, 5), (1000, 256), (777, 300), (3001, 1024), (1500, 2048), (513, 4096),
-                                 (64, 4097)])
+                                 (64, 4097), (700, 9000), (333, 8193)])
 def test_hv_matches_oracle(n, d):
     rng = np.random.default_rng(n * 7 + d)
     A = rng.standard_normal((n, d))
