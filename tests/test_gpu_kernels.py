@@ -136,6 +136,17 @@ def test_sjlt_sketch(n, d, m, exact):
         assert np.all(np.abs(SA - ref) <= _sjlt_bound(A, h, m))
 
 
+@pytest.mark.parametrize("kind", ["sjlt", "gauss", "srht"])
+def test_sketch_strided_rows(kind):
+    # A as a column slice of a wider matrix: lda = 300 > d = 257 (odd: scalar loads)
+    rng = np.random.default_rng(21)
+    big = rng.standard_normal((1200, 300))
+    A = to_dev(big)[:, :257]
+    SA = aes.sketch(A, 100, kind, seed=4, k=1).cpu().numpy()
+    ref = osk.sketch(big[:, :257], 100, kind, 4, 1)
+    assert np.max(np.abs(SA - ref)) <= 1e-13 * np.sqrt(1200) * np.max(np.abs(ref))
+
+
 @pytest.mark.parametrize("m", [16384, 16])
 def test_sjlt_full_size_sampled_rows(m):
     P = synth.make_problem(65536, 2048, "pow:1", 1e-3, seed=14, backend="torch", device="cuda")
