@@ -85,7 +85,7 @@ typedef struct {
   int32_t sketch;        /* aes_sketch_kind, default AES_SRHT */
   int32_t precision;     /* aes_precision, default AES_FP64 */
   int32_t stop;          /* aes_stop_rule, default AES_STOP_XREL */
-  double rho;            /* in (0,1), default 1/8 */
+  double rho;            /* in (0,1), default 1/8 (the adaptive guarantee assumes rho < 1/4) */
   int64_t m_init;        /* >= 1, default 1 */
   int64_t m_max;         /* cap on m; <= 0 means n' = 2^ceil(log2 n) */
   int64_t max_iter;      /* cap on accepted steps, default 200 */

@@ -47,6 +47,7 @@ refined direct solution; for ``cg``: termination in d steps, Krylov optimality i
 H-norm by brute-force least squares, and the xrel bound on the true error.
 """
 import math
+import warnings
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -124,6 +125,10 @@ def _validate(A, b, nu, lam, o):
         raise ValueError("Lambda must have finite positive entries")
     if not 0.0 < o.rho < 1.0:
         raise ValueError("rho must lie in (0, 1)")
+    if o.rho >= 0.25 and o.adaptive:
+        # the adaptive methods are defined for rho in (0, 1); their guarantee (Theorem
+        # "adaptive") is stated for rho < 1/4
+        warnings.warn("rho >= 1/4: outside the range of the adaptive guarantee", stacklevel=3)
     if o.m_init < 1:
         raise ValueError("m_init must be >= 1")
     if o.tol <= 0 and o.stop != "fixed":

@@ -289,3 +289,9 @@ def test_cg_xrel_bounds_the_error(small):
     assert info.a_passes == info.iterations == len(info.trace)
     with pytest.raises(ValueError):
         solvers.cg(small["A"], small["b"], small["nu"], small["lam"], solvers.Options(stop="remark"))
+
+
+def test_rho_outside_the_guarantee_warns(small):
+    o = solvers.Options(rho=0.3, m_init=8, max_iter=2, stop="fixed")
+    with pytest.warns(UserWarning, match="rho >= 1/4"):
+        solvers.adaptive_pcg(small["A"], small["b"], small["nu"], small["lam"], o)
