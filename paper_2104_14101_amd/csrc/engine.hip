@@ -207,6 +207,7 @@ class Solver {
     RTP_ = B<double>("RTP", dc);
     Bv_ = B<double>("B", dc);
     scal_ = B<double>("scal", 8 * C_ + 8);
+    vw_ = B<double>("vec_work", vec_work_elems());
     active_ = B<int>("active", C_);
     nwg_ = hv_num_blocks(h_->num_cu, n_);
     if (fused_) {
@@ -540,7 +541,7 @@ class Solver {
         hv(x, R_, 1.0, rhs, -1.0, use32);  // g = H x - b
       apply(R_, Pv_);
       launch_ihs_init(d_, C_, R_, Pv_, scal_, active_, gate, stop_rule, stop_scale, stop_sr_, tol2_, x, 1, s_,
-                      chol_flag_);
+                      chol_flag_, vw_);
     } else {
       if (x_is_zero)
         AES_HIP(hipMemcpyAsync(R_, rhs, d_ * C_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
@@ -548,7 +549,7 @@ class Solver {
         hv(x, R_, -1.0, rhs, 1.0, use32);  // r = b - H x
       apply(R_, RTP_);
       launch_pcg_init(d_, C_, R_, RTP_, Pv_, scal_, active_, gate, stop_rule, stop_scale, stop_sr_, tol2_, x, 1, s_,
-                      chol_flag_);
+                      chol_flag_, vw_);
     }
     // Flags of an initialisation: read at once without speculation; with it, the first step is
     // enqueued behind the initialisation and its flags tell whether it ran (flag 7 = its
@@ -584,14 +585,14 @@ class Solver {
         hv(XP_, RP_, 1.0, rhs, -1.0, use32, gate);
         apply(RP_, RTP_, gate);
         launch_ihs_finish(d_, C_, x, R_, Pv_, XP_, RP_, RTP_, scal_, active_, gate, thr, force, o_.adaptive, at_cap,
-                          stop_rule, stop_scale, stop_sr_, tol2_, s_, seq);
+                          stop_rule, stop_scale, stop_sr_, tol2_, s_, seq, vw_);
       } else {
         hv(Pv_, Q_, 1.0, nullptr, 0.0, use32, gate);
         launch_pcg_candidate(d_, C_, fused_ ? spart_ : nullptr, nwg_, lam_, nu2_, x, R_, Pv_, Q_, XP_, RP_, scal_,
-                             active_, s_, gate);
+                             active_, s_, gate, vw_);
         apply(RP_, RTP_, gate);
         launch_pcg_finish(d_, C_, x, R_, Pv_, XP_, RP_, RTP_, scal_, active_, gate, thr, force, o_.adaptive, at_cap,
-                          stop_rule, stop_scale, stop_sr_, tol2_, s_, seq);
+                          stop_rule, stop_scale, stop_sr_, tol2_, s_, seq, vw_);
       }
       if (spec) {
         AES_HIP(hipMemcpyAsync(pinned_ + 8 * slot, scal_ + 7 * C_, 8 * sizeof(double), hipMemcpyDeviceToHost, s_));
@@ -678,7 +679,7 @@ class Solver {
       if (ihs) {
         apply(R_, Pv_);
         launch_ihs_init(d_, C_, R_, Pv_, scal_, active_, gate, stop_rule, stop_scale, stop_sr_, tol2_, x, 0, s_,
-                        chol_flag_);
+                        chol_flag_, vw_);
       } else {
         if (x_is_zero && t == 0)
           AES_HIP(hipMemcpyAsync(R_, rhs, d_ * C_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
@@ -686,7 +687,7 @@ class Solver {
           hv(x, R_, -1.0, rhs, 1.0, use32);  // explicit r_t = b - H x_t
         apply(R_, RTP_);
         launch_pcg_init(d_, C_, R_, RTP_, Pv_, scal_, active_, gate, stop_rule, stop_scale, stop_sr_, tol2_, x, 0, s_,
-                        chol_flag_);
+                        chol_flag_, vw_);
       }
       if (!spec) {
         read_flags();
@@ -916,6 +917,7 @@ class Solver {
   double* atz_part_ = nullptr;
   int atz_nrb_ = 0;
   int64_t atz_rows_ = 0;
+  double* vw_ = nullptr;  // work buffer of the wide vector kernels
   bool fused_ = true;  // single-RHS fused H.v (and the speculative step pipeline)
   bool cg_ = false;
   const int* chol_flag_ = nullptr;

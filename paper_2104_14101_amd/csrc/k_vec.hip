@@ -35,19 +35,86 @@ __device__ __forceinline__ void col_reduce(double* buf, double v, int C) {
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// Wide form of the vector kernels (d * C >= kSplitElems, no device gate): the column sums
+// are formed by a grid of G workgroups into partials, the single workgroup only combines the
+// partials (fixed order) and decides, and the elementwise updates run on the grid again.
+// Work buffer: 3 * G * C partials, then the commit record (accept, beta[C], active before[C]).
+// ---------------------------------------------------------------------------------------
+constexpr int64_t kSplitElems = 8192;
+constexpr int kSplitMaxG = 256;
+
+size_t vec_work_elems() { return (size_t)3 * kSplitMaxG * 64 + 2 * 64 + 1; }
+
+static int split_groups(int64_t d, int C, const double* work, const int* gate) {
+  const int64_t total = d * C;
+  if (!work || gate || total < kSplitElems) return 0;
+  return (int)std::min<int64_t>(kSplitMaxG, ceil_div(total, 2048));
+}
+
+// partials of NQ column sums over the flat d x C range; thread t of every workgroup only
+// meets elements of column t % C (the grid stride is a multiple of 256 and C divides 256).
+//   MODE 0: a.b               (PCG candidate: p.q)
+//   MODE 1: a.b, x.x, |a|     (finish: rp.rtp, xp.xp, |rp|; init: r.rt, x.x, |r|)
+// pcopy (init of PCG): pcopy = b on the active columns.
+template <int MODE>
+__global__ __launch_bounds__(256) void vec_partials_kernel(int64_t total, int C, const double* __restrict__ a,
+                                                           const double* __restrict__ b, const double* __restrict__ x,
+                                                           double* __restrict__ pcopy, const int* __restrict__ active,
+                                                           double* __restrict__ part) {
+  constexpr int NQ = MODE == 0 ? 1 : 3;
+  __shared__ double sh[256];
+  const int tid = threadIdx.x, G = gridDim.x, col = tid % C;
+  double l[3] = {0.0, 0.0, 0.0};
+  if (active[col]) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + tid; e < total; e += (int64_t)G * 256) {
+      const double av = a[e], bv = b[e];
+      l[0] = fma(av, bv, l[0]);
+      if (MODE == 1) {
+        if (x) l[1] = fma(x[e], x[e], l[1]);
+        l[2] += fabs(av);
+      }
+      if (pcopy) pcopy[e] = bv;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    sh[tid] = l[q];
+    __syncthreads();
+    for (int st = 128; st >= C; st >>= 1) {
+      if (tid < st) sh[tid] += sh[tid + st];
+      __syncthreads();
+    }
+    if (tid < C) part[((int64_t)q * G + blockIdx.x) * C + tid] = sh[tid];
+    __syncthreads();
+  }
+}
+
+// thread t of the single workgroup: sum of partials q of column t % C over the workgroups
+// t / C, t / C + 1024 / C, ... (then col_reduce combines them in a fixed tree)
+__device__ __forceinline__ double part_sum(const double* part, int q, int G, int C) {
+  const int tid = threadIdx.x, col = tid % C, tpc = kVT / C;
+  double v = 0.0;
+  for (int w = tid / C; w < G; w += tpc) v += part[((int64_t)q * G + w) * C + col];
+  return v;
+}
+
 __global__ __launch_bounds__(kVT) void pcg_candidate_kernel(int64_t d, int C, const double* __restrict__ spart, int nwg,
                                                             const double* __restrict__ lam, double nu2,
                                                             const double* __restrict__ x, const double* __restrict__ r,
                                                             const double* __restrict__ p, const double* __restrict__ q,
                                                             double* __restrict__ xp, double* __restrict__ rp,
                                                             double* __restrict__ scal, const int* __restrict__ active,
-                                                            const int* __restrict__ gate) {
+                                                            const int* __restrict__ gate,
+                                                            const double* __restrict__ part, int G) {
   if (gate && *gate == 0) return;
   __shared__ double buf[kVT];
   __shared__ double alpha_s[64];
   const int tid = threadIdx.x, col = tid % C, tpc = kVT / C;
   double loc = 0.0;
-  if (spart) {
+  if (part) {
+    if (active[col]) loc = part_sum(part, 0, G, C);
+  } else if (spart) {
 #pragma unroll 4
     for (int64_t i = tid / C; i < d; i += tpc) {
       const double pv = p[i * C + col];
@@ -68,6 +135,7 @@ __global__ __launch_bounds__(kVT) void pcg_candidate_kernel(int64_t d, int C, co
     alpha_s[tid] = a;
   }
   __syncthreads();
+  if (part) return;  // the grid applies the step
   const double a = alpha_s[col];
   if (active[col])
 #pragma unroll 4
@@ -78,12 +146,36 @@ __global__ __launch_bounds__(kVT) void pcg_candidate_kernel(int64_t d, int C, co
     }
 }
 
+__global__ void pcg_step_apply_kernel(int64_t total, int C, const double* __restrict__ x, const double* __restrict__ r,
+                                      const double* __restrict__ p, const double* __restrict__ q,
+                                      double* __restrict__ xp, double* __restrict__ rp,
+                                      const double* __restrict__ scal, const int* __restrict__ active) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int c = (int)(e % C);
+  if (!active[c]) return;
+  const double a = scal[2 * C + c];
+  xp[e] = x[e] + a * p[e];
+  rp[e] = r[e] - a * q[e];
+}
+
 void launch_pcg_candidate(int64_t d, int C, const double* spart, int nwg, const double* lam, double nu2, const double* x,
                           const double* r, const double* p, const double* q, double* xp, double* rp, double* scal,
-                          const int* active, hipStream_t s, const int* gate) {
+                          const int* active, hipStream_t s, const int* gate, double* work) {
+  const int G = spart ? 0 : split_groups(d, C, work, gate);
+  const int64_t total = d * C;
+  if (G) {
+    hipLaunchKernelGGL(vec_partials_kernel<0>, dim3(G), dim3(256), 0, s, total, C, p, q, nullptr, nullptr, active, work);
+    AES_LAUNCH_CHECK();
+  }
   hipLaunchKernelGGL(pcg_candidate_kernel, dim3(1), dim3(kVT), 0, s, d, C, spart, nwg, lam, nu2, x, r, p, q, xp, rp, scal,
-                     active, gate);
+                     active, gate, G ? work : nullptr, G);
   AES_LAUNCH_CHECK();
+  if (G) {
+    hipLaunchKernelGGL(pcg_step_apply_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, total, C, x, r, p, q,
+                       xp, rp, scal, active);
+    AES_LAUNCH_CHECK();
+  }
 }
 
 // Stop rule of one column after a commit (see oracle docs / design notes for the readings).
@@ -110,7 +202,9 @@ __global__ __launch_bounds__(kVT) void finish_kernel(int64_t d, int C, double* _
                                                      double* __restrict__ scal, int* __restrict__ active,
                                                      int* __restrict__ gate, double thr, int force_reject,
                                                      int adaptive, int at_cap, int stop_rule, double stop_scale,
-                                                     double stop_sr, double tol2, double seq) {
+                                                     double stop_sr, double tol2, double seq,
+                                                     const double* __restrict__ part, int G,
+                                                     double* __restrict__ rec) {
   if (gate && *gate == 0) return;
   __shared__ double buf[kVT];
   __shared__ double dp_s[64], xn_s[64], rz_s[64];
@@ -118,7 +212,11 @@ __global__ __launch_bounds__(kVT) void finish_kernel(int64_t d, int C, double* _
   const int tid = threadIdx.x, col = tid % C, tpc = kVT / C;
   const bool act = active[col] != 0;
   double l1 = 0.0, l2 = 0.0, l3 = 0.0;
-  if (act)
+  if (act && part) {
+    l1 = part_sum(part, 0, G, C);
+    l2 = part_sum(part, 1, G, C);
+    l3 = part_sum(part, 2, G, C);
+  } else if (act)
 #pragma unroll 4
     for (int64_t i = tid / C; i < d; i += tpc) {
       const int64_t e = i * C + col;
@@ -159,6 +257,7 @@ __global__ __launch_bounds__(kVT) void finish_kernel(int64_t d, int C, double* _
     accept_s = accept;
   }
   __syncthreads();
+  if (rec && tid == 0) rec[0] = accept_s ? 1.0 : 0.0;
   if (!accept_s) {
     if (tid == 0) {
       int na = 0;
@@ -169,7 +268,13 @@ __global__ __launch_bounds__(kVT) void finish_kernel(int64_t d, int C, double* _
     }
     return;
   }
-  if (act) {
+  if (rec) {
+    // the grid commits: beta and the active set before this step's stop test
+    if (tid < C) {
+      rec[1 + tid] = IHS ? 0.0 : dp_s[tid] / scal[tid];
+      rec[1 + C + tid] = active[tid] ? 1.0 : 0.0;
+    }
+  } else if (act) {
     const double beta = IHS ? 0.0 : dp_s[col] / scal[col];
 #pragma unroll 4
     for (int64_t i = tid / C; i < d; i += tpc) {
@@ -201,22 +306,60 @@ __global__ __launch_bounds__(kVT) void finish_kernel(int64_t d, int C, double* _
   }
 }
 
+// Commit of an accepted step on the grid (wide form): x = xp, r = rp, p = rtp + beta p (IHS:
+// p = rtp) on the columns that were active when the step was tested.
+template <bool IHS>
+__global__ void finish_commit_kernel(int64_t total, int C, double* __restrict__ x, double* __restrict__ r,
+                                     double* __restrict__ p, const double* __restrict__ xp,
+                                     const double* __restrict__ rp, const double* __restrict__ rtp,
+                                     const double* __restrict__ rec) {
+  if (rec[0] == 0.0) return;  // rejected: nothing to commit
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int c = (int)(e % C);
+  if (rec[1 + C + c] == 0.0) return;
+  x[e] = xp[e];
+  r[e] = rp[e];
+  p[e] = IHS ? rtp[e] : rtp[e] + rec[1 + c] * p[e];
+}
+
+template <bool IHS>
+static void launch_finish(int64_t d, int C, double* x, double* r, double* p, const double* xp, const double* rp,
+                          const double* rtp, double* scal, int* active, int* gate, double thr, int force_reject,
+                          int adaptive, int at_cap, int stop_rule, double stop_scale, double stop_sr, double tol2,
+                          hipStream_t s, double seq, double* work) {
+  const int G = split_groups(d, C, work, gate);
+  const int64_t total = d * C;
+  double* rec = G ? work + (size_t)3 * kSplitMaxG * 64 : nullptr;
+  if (G) {
+    hipLaunchKernelGGL(vec_partials_kernel<1>, dim3(G), dim3(256), 0, s, total, C, rp, rtp, xp, nullptr, active, work);
+    AES_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(finish_kernel<IHS>, dim3(1), dim3(kVT), 0, s, d, C, x, r, p, xp, rp, rtp, scal, active, gate, thr,
+                     force_reject, adaptive, at_cap, stop_rule, stop_scale, stop_sr, tol2, seq, G ? work : nullptr, G,
+                     rec);
+  AES_LAUNCH_CHECK();
+  if (G) {
+    hipLaunchKernelGGL(finish_commit_kernel<IHS>, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, total, C, x, r,
+                       p, xp, rp, rtp, rec);
+    AES_LAUNCH_CHECK();
+  }
+}
+
 void launch_pcg_finish(int64_t d, int C, double* x, double* r, double* p, const double* xp, const double* rp,
                        const double* rtp, double* scal, int* active, int* gate, double thr, int force_reject,
                        int adaptive, int at_cap, int stop_rule, double stop_scale, double stop_sr, double tol2,
-                       hipStream_t s, double seq) {
-  hipLaunchKernelGGL(finish_kernel<false>, dim3(1), dim3(kVT), 0, s, d, C, x, r, p, xp, rp, rtp, scal, active, gate, thr,
-                     force_reject, adaptive, at_cap, stop_rule, stop_scale, stop_sr, tol2, seq);
-  AES_LAUNCH_CHECK();
+                       hipStream_t s, double seq, double* work) {
+  launch_finish<false>(d, C, x, r, p, xp, rp, rtp, scal, active, gate, thr, force_reject, adaptive, at_cap, stop_rule,
+                       stop_scale, stop_sr, tol2, s, seq, work);
 }
 
 void launch_ihs_finish(int64_t d, int C, double* x, double* g, double* sd, const double* xp, const double* gp,
                        const double* sp, double* scal, int* active, int* gate, double thr, int force_reject,
                        int adaptive, int at_cap, int stop_rule, double stop_scale, double stop_sr, double tol2,
-                       hipStream_t s, double seq) {
-  hipLaunchKernelGGL(finish_kernel<true>, dim3(1), dim3(kVT), 0, s, d, C, x, g, sd, xp, gp, sp, scal, active, gate, thr,
-                     force_reject, adaptive, at_cap, stop_rule, stop_scale, stop_sr, tol2, seq);
-  AES_LAUNCH_CHECK();
+                       hipStream_t s, double seq, double* work) {
+  launch_finish<true>(d, C, x, g, sd, xp, gp, sp, scal, active, gate, thr, force_reject, adaptive, at_cap, stop_rule,
+                      stop_scale, stop_sr, tol2, s, seq, work);
 }
 
 // (Re)initialisation after a factorisation: p = rt (PCG), D = r.rt (x 1/2 for the IHS),
@@ -227,13 +370,18 @@ __global__ __launch_bounds__(kVT) void init_kernel(int64_t d, int C, const doubl
                                                    double* __restrict__ scal, int* __restrict__ active,
                                                    int stop_rule, double stop_scale, double stop_sr, double tol2,
                                                    const double* __restrict__ x, int set_d0, int* __restrict__ gate,
-                                                   const int* __restrict__ chol_flag) {
+                                                   const int* __restrict__ chol_flag, const double* __restrict__ part,
+                                                   int G) {
   __shared__ double buf[kVT];
   __shared__ double dd[64], xn[64], rz[64];
   const int tid = threadIdx.x, col = tid % C, tpc = kVT / C;
   const bool act = active[col] != 0;
   double l1 = 0.0, l2 = 0.0, l3 = 0.0;
-  if (act)
+  if (act && part) {  // sums (and the copy p = rt) formed by the grid
+    l1 = part_sum(part, 0, G, C);
+    l2 = part_sum(part, 1, G, C);
+    l3 = part_sum(part, 2, G, C);
+  } else if (act)
     for (int64_t i = tid / C; i < d; i += tpc) {
       const int64_t e = i * C + col;
       l1 += r[e] * rt[e];
@@ -278,17 +426,27 @@ __global__ __launch_bounds__(kVT) void init_kernel(int64_t d, int C, const doubl
 
 void launch_pcg_init(int64_t d, int C, const double* r, const double* rt, double* p, double* scal, int* active,
                      int* gate, int stop_rule, double stop_scale, double stop_sr, double tol2, const double* x,
-                     int set_d0, hipStream_t s, const int* chol_flag) {
+                     int set_d0, hipStream_t s, const int* chol_flag, double* work) {
+  const int G = split_groups(d, C, work, gate);
+  if (G) {
+    hipLaunchKernelGGL(vec_partials_kernel<1>, dim3(G), dim3(256), 0, s, d * C, C, r, rt, x, p, active, work);
+    AES_LAUNCH_CHECK();
+  }
   hipLaunchKernelGGL(init_kernel<false>, dim3(1), dim3(kVT), 0, s, d, C, r, rt, p, scal, active, stop_rule, stop_scale,
-                     stop_sr, tol2, x, set_d0, gate, chol_flag);
+                     stop_sr, tol2, x, set_d0, gate, chol_flag, G ? work : nullptr, G);
   AES_LAUNCH_CHECK();
 }
 
 void launch_ihs_init(int64_t d, int C, const double* g, const double* sd, double* scal, int* active, int* gate,
                      int stop_rule, double stop_scale, double stop_sr, double tol2, const double* x, int set_d0,
-                     hipStream_t s, const int* chol_flag) {
+                     hipStream_t s, const int* chol_flag, double* work) {
+  const int G = split_groups(d, C, work, gate);
+  if (G) {
+    hipLaunchKernelGGL(vec_partials_kernel<1>, dim3(G), dim3(256), 0, s, d * C, C, g, sd, x, nullptr, active, work);
+    AES_LAUNCH_CHECK();
+  }
   hipLaunchKernelGGL(init_kernel<true>, dim3(1), dim3(kVT), 0, s, d, C, g, sd, nullptr, scal, active, stop_rule,
-                     stop_scale, stop_sr, tol2, x, set_d0, gate, chol_flag);
+                     stop_scale, stop_sr, tol2, x, set_d0, gate, chol_flag, G ? work : nullptr, G);
   AES_LAUNCH_CHECK();
 }
 

@@ -44,7 +44,7 @@ struct StepScalars;  // defined in k_vec.hip
 void launch_pcg_candidate(int64_t d, int C, const double* spart, int nwg, const double* lam, double nu2,
                           const double* x, const double* r, const double* p, const double* q,
                           double* xp, double* rp, double* scal, const int* active, hipStream_t s,
-                          const int* gate = nullptr);
+                          const int* gate = nullptr, double* work = nullptr);
 // PCG finish: Dp = rp . rtp per column; test; commit if accepted; stop rule.  See k_vec.hip.
 // gate (optional): read first (0: do nothing), then set to 1 iff the step was accepted, is
 // finite and a column is still active — the gate of the next, speculatively enqueued step.
@@ -52,23 +52,30 @@ void launch_pcg_candidate(int64_t d, int C, const double* spart, int nwg, const 
 void launch_pcg_finish(int64_t d, int C, double* x, double* r, double* p, const double* xp,
                        const double* rp, const double* rtp, double* scal, int* active, int* gate,
                        double thr, int force_reject, int adaptive, int at_cap, int stop_rule,
-                       double stop_scale, double stop_sr, double tol2, hipStream_t s, double seq = -1.0);
+                       double stop_scale, double stop_sr, double tol2, hipStream_t s, double seq = -1.0,
+                       double* work = nullptr);
 // PCG (re)initialisation after a factorisation: rt = H_S^{-1} r given; p = rt; D = r.rt; DI = D.
 // gate (optional): set to 1 iff finite and a column is active.  chol_flag (optional): the
 // factorisation's failure flag, copied to flag 6 of the flag block (and closing the gate).
 void launch_pcg_init(int64_t d, int C, const double* r, const double* rt, double* p, double* scal,
                      int* active, int* gate, int stop_rule, double stop_scale, double stop_sr,
-                     double tol2, const double* x, int set_d0, hipStream_t s, const int* chol_flag = nullptr);
+                     double tol2, const double* x, int set_d0, hipStream_t s, const int* chol_flag = nullptr,
+                     double* work = nullptr);
 // IHS: xp = x - mu s
 void launch_ihs_candidate(int64_t d, int C, const double* x, const double* sd, double mu, double* xp,
                           const int* active, hipStream_t s, const int* gate = nullptr);
 void launch_ihs_finish(int64_t d, int C, double* x, double* g, double* sd, const double* xp,
                        const double* gp, const double* sp, double* scal, int* active, int* gate,
                        double thr, int force_reject, int adaptive, int at_cap, int stop_rule,
-                       double stop_scale, double stop_sr, double tol2, hipStream_t s, double seq = -1.0);
+                       double stop_scale, double stop_sr, double tol2, hipStream_t s, double seq = -1.0,
+                       double* work = nullptr);
 void launch_ihs_init(int64_t d, int C, const double* g, const double* sd, double* scal, int* active,
                      int* gate, int stop_rule, double stop_scale, double stop_sr, double tol2,
-                     const double* x, int set_d0, hipStream_t s, const int* chol_flag = nullptr);
+                     const double* x, int set_d0, hipStream_t s, const int* chol_flag = nullptr,
+                     double* work = nullptr);
+// Wide form of the vector kernels (d * C >= 8192 without a device gate): a work buffer of
+// vec_work_elems() doubles for the grid's partial column sums and the commit record.
+size_t vec_work_elems();
 
 // ---- triangular / dense GEMV (k_vec.hip) ------------------------------------------------
 // y[i, c] = (ysgn * sum_{j in tri(i)} M[i, j] * xs[j] * x[j, c] + (zadd ? zadd[i, c] : 0))

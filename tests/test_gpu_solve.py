@@ -134,6 +134,21 @@ def test_multiple_rhs(small):
     assert np.all(reference.rel_error(X.cpu().numpy(), Xr) <= 1e-10)
 
 
+@pytest.mark.parametrize("method", ["pcg", "ihs"])
+def test_many_rhs_wide_vector_kernels(small, method):
+    # 32 right-hand sides at d = 256: d * C = 8192, the grid form of the vector kernels
+    rng = np.random.default_rng(11)
+    Bm = small["A"].T @ rng.standard_normal((4096, 32))
+    kw = dict(method=method, m_init=8, seed=6, tol=1e-10)
+    X, info = aes.solve(small["dA"], to_dev(Bm), small["nu"], small["dlam"], trace_cap=256, **kw)
+    Xo, io = solvers.solve(small["A"], Bm, small["nu"], small["lam"], solvers.Options(**kw))
+    Xr = reference.reference_solution(small["A"], Bm, small["nu"], small["lam"])
+    assert info["status"] == "ok"
+    assert _traj_gpu(info) == _traj_cpu(io)
+    assert np.all(reference.rel_error(X.cpu().numpy(), Xr) <= 1e-10)
+    assert np.all(reference.rel_error(X.cpu().numpy(), Xo) <= 1e-9)
+
+
 def test_forced_rejection_and_max_iter(small):
     kw = dict(m_init=512, seed=2, tol=1e-10, force_reject_at=3)
     x, info = aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], trace_cap=256, **kw)
