@@ -37,6 +37,7 @@ Readings where the paper is silent (each also listed in the design notes):
   * ``max_iter`` bounds the number of accepted steps t (the loop "while t < T").
 
 ``cg`` is the paper's unpreconditioned conjugate-gradient baseline (Sec. 5).
+``dual_solve`` takes the dual route of Sec. 1 for n < d (eq. "dual optimization problem").
 
 Pins (tests/test_oracle_solvers.py): one-step convergence when m = n' (H_S = H); Krylov
 optimality of PCG (Theorem "rate cg") by brute-force least squares on tiny problems; the IHS
@@ -44,7 +45,8 @@ error recursion (proof of Theorem "rate IHS"); the decrement bracket (proof of t
 lemma); invariants of the adaptive control (accepted steps satisfy the test, m doubles, K
 bounded, forced rejections recompute r_t = b - H x_t); rel. error <= 1e-10 against the
 refined direct solution; for ``cg``: termination in d steps, Krylov optimality in the
-H-norm by brute-force least squares, and the xrel bound on the true error.
+H-norm by brute-force least squares, and the xrel bound on the true error; for
+``dual_solve``: the primal x* of the refined direct solve and A x* = w*.
 """
 import math
 import warnings
@@ -446,3 +448,36 @@ def solve(A, b, nu, lam=None, opts=None):
     if o.method == "cg":
         return cg(A, b, nu, lam, o)
     return adaptive_ihs(A, b, nu, lam, o) if o.method == "ihs" else adaptive_pcg(A, b, nu, lam, o)
+
+
+def dual_solve(A, b, nu, lam=None, opts=None):
+    """Solve H x = b through the dual problem (eq. "dual optimization problem", Sec. 1): n < d.
+
+    With B = Lambda^{-1/2} A^T (d x n), the dual variable w in R^n minimises
+    1/2 w^T (B^T B + nu^2 I_n) w - (A Lambda^{-1} b)^T w: the same problem class with data matrix
+    B (d rows, n columns), Lambda = I_n and right-hand side A Lambda^{-1} b, solved here by
+    ``solve`` with the options unchanged.  The paper does not write the map back; from the
+    primal optimality condition H x* = b one gets x* = Lambda^{-1} (b - A^T w*) / nu^2 (and then
+    A x* = w*), computed as Lambda^{-1/2} (Lambda^{-1/2} b - B w) / nu^2.
+
+    Returns (x, w, info); info is the dual solve's (its a_passes count passes over B).  A start
+    point is not accepted (opts.x0 must be None).
+    """
+    o = opts or Options()
+    if o.x0 is not None:
+        raise ValueError("the dual form takes no start point")
+    A = np.asarray(A, dtype=np.float64)
+    n, d = A.shape
+    b2, squeeze = _as2d(b)
+    if b2.shape[0] != d:
+        raise ValueError("b must have d rows")
+    lam_v = np.ones(d) if lam is None else np.asarray(lam, dtype=np.float64)
+    if np.any(~np.isfinite(lam_v)) or np.any(lam_v <= 0):
+        raise ValueError("Lambda must have finite positive entries")
+    isl = 1.0 / np.sqrt(lam_v)
+    Bm = np.ascontiguousarray(A.T * isl[:, None])           # Lambda^{-1/2} A^T, d x n
+    bd = A @ (b2 / lam_v[:, None])                           # A Lambda^{-1} b, n x c
+    W, info = solve(Bm, bd, nu, None, o)
+    W = W.reshape(n, -1)
+    X = isl[:, None] * (isl[:, None] * b2 - Bm @ W) / nu ** 2
+    return (X[:, 0] if squeeze else X), (W[:, 0] if squeeze else W), info

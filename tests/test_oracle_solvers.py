@@ -295,3 +295,36 @@ def test_rho_outside_the_guarantee_warns(small):
     o = solvers.Options(rho=0.3, m_init=8, max_iter=2, stop="fixed")
     with pytest.warns(UserWarning, match="rho >= 1/4"):
         solvers.adaptive_pcg(small["A"], small["b"], small["nu"], small["lam"], o)
+
+
+@pytest.mark.parametrize("n,d,c,with_lam", [(40, 1500, 1, True), (64, 3000, 3, True), (48, 200, 2, False)])
+def test_dual_form_matches_the_primal_solution(n, d, c, with_lam):
+    # The dual route (eq. "dual optimization problem") must land on the primal x* = H^{-1} b,
+    # computed here by the refined direct solve of the primal: a wrong sign or a dropped
+    # Lambda in the map back, or a wrong dual right-hand side, fails this.
+    rng = np.random.default_rng(n + d)
+    A = rng.standard_normal((n, d)) / math.sqrt(d) * (0.9 ** np.arange(n))[:, None]
+    lam = 1.0 + rng.random(d) if with_lam else None
+    b = rng.standard_normal((d, c))
+    nu = 0.05
+    x, w, info = solvers.dual_solve(A, b, nu, lam, solvers.Options(tol=1e-12))
+    assert info.status == "ok"
+    xr = reference.reference_solution(A, b, nu, lam)
+    assert np.max(reference.rel_error(x, xr)) <= 1e-10
+    # at the solution the dual variable is A x*
+    assert np.linalg.norm(A @ x - w) <= 1e-9 * np.linalg.norm(w)
+    # the dual problem has n unknowns: the sketch never exceeds the padded size of its d rows
+    assert info.final_m <= 1 << (d - 1).bit_length()
+
+
+def test_dual_form_vector_rhs_and_validation():
+    rng = np.random.default_rng(11)
+    A = rng.standard_normal((16, 300))
+    b = rng.standard_normal(300)
+    x, w, _ = solvers.dual_solve(A, b, 1.0, None, solvers.Options(tol=1e-12))
+    assert x.shape == (300,) and w.shape == (16,)
+    assert np.linalg.norm(x - reference.direct_solve(A, b, 1.0)) <= 1e-10 * np.linalg.norm(x)
+    with pytest.raises(ValueError):
+        solvers.dual_solve(A, b, 1.0, None, solvers.Options(x0=np.zeros(16)))
+    with pytest.raises(ValueError):
+        solvers.dual_solve(A, b[:10], 1.0)
