@@ -148,6 +148,25 @@ aes_status aes_solve(aes_handle h, void* stream, int64_t n, int64_t d, int64_t c
                      const double* lambda, double tol, const aes_options* opt, double* x,
                      int64_t ldx, aes_info* info);
 
+/*
+ * aes_solve_dual -- the same problem H x = b through its dual (Sec. 1, eq. "dual optimization
+ * problem"), for n < d: with B = Lambda^{-1/2} A^T (d x n) the dual variable w in R^n solves
+ * (B^T B + nu^2 I_n) w = A Lambda^{-1} b, which aes_solve's algorithm handles with data matrix B
+ * (d rows, n columns) and Lambda = I; then x = Lambda^{-1} (b - A^T w) / nu^2 (from H x = b;
+ * at the solution A x = w).  Arguments and layouts as in aes_solve, except:
+ *   n       1 <= n <= 32768 (the dual has n unknowns); d is not limited
+ *   opt     as in aes_solve; x0 must be NULL; the stop rule and tol apply to w, so the
+ *           error of x is bounded through x - x* = -Lambda^{-1} A^T (w - w*) / nu^2
+ *   info    of the dual solve: iterations, m and a_passes refer to B; the call adds one pass
+ *           over A for A Lambda^{-1} b, one read of A and one write of B (d x n, kept in the
+ *           handle's workspace) and one pass over B for x
+ * Returns as aes_solve; on AES_ERR_MAX_ITER, x is mapped from the last accepted w.
+ */
+aes_status aes_solve_dual(aes_handle h, void* stream, int64_t n, int64_t d, int64_t c,
+                          const double* A, int64_t lda, const double* b, int64_t ldb, double nu,
+                          const double* lambda, double tol, const aes_options* opt, double* x,
+                          int64_t ldx, aes_info* info);
+
 /* One problem of a batch (all pointers device, layouts as in aes_solve). */
 typedef struct {
   int64_t n, d, c;

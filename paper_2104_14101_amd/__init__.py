@@ -18,7 +18,7 @@ import torch
 
 from . import _binding as B
 
-__all__ = ["solve", "solve_batched", "hv", "hv_multi", "sketch", "factor", "precond_apply", "SketchSolve", "AesError"]
+__all__ = ["solve", "solve_dual", "solve_batched", "hv", "hv_multi", "sketch", "factor", "precond_apply", "SketchSolve", "AesError"]
 
 AesError = B.AesError
 _handles = {}
@@ -135,6 +135,38 @@ def solve(A, b, nu, lam=None, tol=1e-10, x=None, check=True, **opts):
     h = _handle(A.device)
     st = _lib().aes_solve(h, _stream(A.device), n, d, c, _ptr(A), lda, _ptr(b2), ldb, float(nu), _ptr(lam), float(tol),
                           ctypes.byref(o), _ptr(x), x.stride(0), ctypes.byref(info))
+    out = _info_dict(info, buf)
+    if check and st not in (B.AES_OK, B.AES_ERR_MAX_ITER):
+        _check(h, st)
+    return (x.reshape(d) if squeeze else x), out
+
+
+def solve_dual(A, b, nu, lam=None, tol=1e-10, x=None, check=True, **opts):
+    """H x = b through the dual problem in R^n (n < d, n <= 32768).  Returns (x, info dict).
+
+    Same arguments as ``solve`` (no x0); info describes the dual solve over Lambda^{-1/2} A^T.
+    """
+    _req(A, "A", (2,))
+    _req(b, "b", (1, 2))
+    A, lda = _rowmajor(A)
+    n, d = A.shape
+    squeeze = b.dim() == 1
+    b2 = b.reshape(d, 1) if squeeze else b
+    b2, ldb = _rowmajor(b2)
+    c = b2.shape[1]
+    if lam is not None:
+        _req(lam, "lam", (1,))
+        lam = lam.contiguous()
+    if opts.get("x0") is not None:
+        raise ValueError("the dual form takes no start point")
+    opts.pop("x0", None)
+    o, buf = make_options(**opts)
+    if x is None:
+        x = torch.empty((d, c), dtype=torch.float64, device=A.device)
+    info = B.Info()
+    h = _handle(A.device)
+    st = _lib().aes_solve_dual(h, _stream(A.device), n, d, c, _ptr(A), lda, _ptr(b2), ldb, float(nu), _ptr(lam),
+                               float(tol), ctypes.byref(o), _ptr(x), x.stride(0), ctypes.byref(info))
     out = _info_dict(info, buf)
     if check and st not in (B.AES_OK, B.AES_ERR_MAX_ITER):
         _check(h, st)

@@ -57,6 +57,8 @@ _PROTOS = {
     "aes_default_options": (None, [POINTER(Options)]),
     "aes_solve": (c_int, [c_void_p, c_void_p, c_int64, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_int64, c_double,
                           c_void_p, c_double, POINTER(Options), c_void_p, c_int64, POINTER(Info)]),
+    "aes_solve_dual": (c_int, [c_void_p, c_void_p, c_int64, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_int64,
+                               c_double, c_void_p, c_double, POINTER(Options), c_void_p, c_int64, POINTER(Info)]),
     "aes_solve_batched": (c_int, [c_void_p, c_void_p, c_int64, POINTER(Problem), c_double, POINTER(Options),
                                   POINTER(Info)]),
     "aes_solve_keep": (c_int, [c_void_p, c_void_p, c_int64, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_int64,

@@ -1048,6 +1048,69 @@ aes_status aes_solve(aes_handle h, void* stream, int64_t n, int64_t d, int64_t c
   return st;
 }
 
+aes_status aes_solve_dual(aes_handle h, void* stream, int64_t n, int64_t d, int64_t c, const double* A, int64_t lda,
+                          const double* b, int64_t ldb, double nu, const double* lambda, double tol,
+                          const aes_options* opt, double* x, int64_t ldx, aes_info* info) {
+  // Dual problem of Sec. 1: with B = Lambda^{-1/2} A^T (d x n), solve
+  // (B^T B + nu^2 I_n) w = A Lambda^{-1} b by the primal solver, then
+  // x = Lambda^{-1/2} (Lambda^{-1/2} b - B w) / nu^2 (primal optimality: H x = b, A x = w).
+  if (!h) return AES_ERR_INVALID_ARG;
+  aes_options o;
+  if (opt)
+    o = *opt;
+  else
+    aes_default_options(&o);
+  hipStream_t s = (hipStream_t)stream;
+  const int C = (int)next_pow2(std::max<int64_t>(c, 1));
+  double *Bm = nullptr, *w = nullptr, *bd = nullptr, *isl = nullptr, *u = nullptr, *v = nullptr, *xp = nullptr;
+  aes_status st = guard(h, [&] {
+    set_device(h);
+    auto bad = [](const char* m) { throw StatusError(AES_ERR_INVALID_ARG, m); };
+    if (n < 1 || d < 1 || c < 1) bad("n, d and c must be >= 1");
+    if (n > kMaxD) bad("the dual form needs n <= 32768");
+    if (c > 32) bad("at most 32 right-hand sides per problem");
+    if (lda < d) bad("lda < d");
+    if (ldb < c || ldx < c) bad("ldb and ldx must be >= c");
+    if (!A || !b || !x) bad("A, b and x must be non-null");
+    if (o.x0) bad("the dual form takes no start point");
+    // the dual problem as the primal solver will see it (placeholder pointers)
+    validate(ProblemDesc{d, n, c, A, n, b, C, nu, nullptr, x, C}, tol, o);
+    Bm = h->buf<double>("dual.B", (size_t)d * n);
+    w = h->buf<double>("dual.w", (size_t)n * C);
+    bd = h->buf<double>("dual.bd", (size_t)n * C);
+    isl = h->buf<double>("dual.isl", d);
+    u = h->buf<double>("dual.u", (size_t)d * C);
+    v = h->buf<double>("dual.v", (size_t)d * C);
+    xp = h->buf<double>("dual.x", (size_t)d * C);
+    launch_dual_prep(d, C, (int)c, b, ldb, lambda, isl, u, v, s);
+    launch_rowdot(n, d, A, lda, 0, v, C, nullptr, 1.0, nullptr, nullptr, 1.0, bd, s);  // A Lambda^{-1} b
+    launch_transpose(n, d, A, lda, Bm, n, s, isl);                                    // Lambda^{-1/2} A^T
+    launch_fill(w, n * C, 0.0, s);
+  });
+  if (st != AES_OK) {
+    if (info) {
+      std::memset(info, 0, sizeof(*info));
+      info->status = st;
+    }
+    return st;
+  }
+  try {
+    st = solve_impl(h, stream, ProblemDesc{d, n, c, Bm, n, bd, C, nu, nullptr, w, C}, tol, &o, info, "s.", nullptr);
+  } catch (const StatusError& e) {
+    h->err = e.what();
+    st = e.st;
+  }
+  if (st != AES_OK && st != AES_ERR_MAX_ITER) return st;
+  const aes_status st2 = guard(h, [&] {
+    set_device(h);
+    launch_rowdot(d, n, Bm, n, 0, w, C, nullptr, -1.0, u, isl, 1.0 / (nu * nu), xp, s);
+    launch_copy_cols(d, (int)c, xp, C, (int)c, x, ldx, s);
+    AES_HIP(hipStreamSynchronize(s));
+  });
+  if (st2 != AES_OK && info) info->status = st2;
+  return st2 != AES_OK ? st2 : st;
+}
+
 aes_status aes_solve_batched(aes_handle h, void* stream, int64_t nprob, const aes_problem* probs, double tol,
                              const aes_options* opt, aes_info* infos) {
   if (!h || nprob < 0 || (nprob > 0 && !probs)) return AES_ERR_INVALID_ARG;

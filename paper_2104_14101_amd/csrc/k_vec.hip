@@ -574,14 +574,16 @@ void launch_fill(double* p, int64_t count, double v, hipStream_t s) {
   AES_LAUNCH_CHECK();
 }
 
+// dst[c, r] = src[r, c] * (colscale ? colscale[c] : 1)
 __global__ void transpose_kernel(int64_t rows, int64_t cols, const double* __restrict__ src, int64_t lds,
-                                 double* __restrict__ dst, int64_t ldd) {
+                                 double* __restrict__ dst, int64_t ldd, const double* __restrict__ colscale) {
   __shared__ double t[32][33];
   const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 32 x 8
+  const double cs = (colscale && c0 + tx < cols) ? colscale[c0 + tx] : 1.0;
   for (int k = ty; k < 32; k += 8) {
     const int64_t r = r0 + k, c = c0 + tx;
-    t[k][tx] = (r < rows && c < cols) ? src[r * lds + c] : 0.0;
+    t[k][tx] = (r < rows && c < cols) ? src[r * lds + c] * cs : 0.0;
   }
   __syncthreads();
   for (int k = ty; k < 32; k += 8) {
@@ -591,9 +593,36 @@ __global__ void transpose_kernel(int64_t rows, int64_t cols, const double* __res
 }
 
 void launch_transpose(int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst, int64_t ldd,
-                      hipStream_t s) {
+                      hipStream_t s, const double* colscale) {
+  if (rows <= 0 || cols <= 0) return;
+  if (ceil_div(rows, 32) > 65535) throw std::invalid_argument("transpose: more than 2^21 rows");
   dim3 g((unsigned)ceil_div(cols, 32), (unsigned)ceil_div(rows, 32));
-  hipLaunchKernelGGL(transpose_kernel, g, dim3(256), 0, s, rows, cols, src, lds, dst, ldd);
+  hipLaunchKernelGGL(transpose_kernel, g, dim3(256), 0, s, rows, cols, src, lds, dst, ldd, colscale);
+  AES_LAUNCH_CHECK();
+}
+
+// Dual-form inputs: isl[j] = lambda_j^{-1/2} (1 without lambda); for column k < c
+// u[j, k] = b[j, k] * isl[j] and v[j, k] = b[j, k] * isl[j]^2, columns c..C-1 zero.
+__global__ void dual_prep_kernel(int64_t d, int C, int c, const double* __restrict__ b, int64_t ldb,
+                                 const double* __restrict__ lambda, double* __restrict__ isl,
+                                 double* __restrict__ u, double* __restrict__ v) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= d * C) return;
+  const int64_t j = e / C;
+  const int k = (int)(e % C);
+  const double l = lambda ? lambda[j] : 1.0;
+  const double is = 1.0 / sqrt(l);
+  if (k == 0) isl[j] = is;
+  const double bj = k < c ? b[j * ldb + k] : 0.0;
+  u[e] = bj * is;
+  v[e] = bj / l;
+}
+
+void launch_dual_prep(int64_t d, int C, int c, const double* b, int64_t ldb, const double* lambda, double* isl,
+                      double* u, double* v, hipStream_t s) {
+  if (d * C <= 0) return;
+  hipLaunchKernelGGL(dual_prep_kernel, dim3((unsigned)ceil_div(d * C, 256)), dim3(256), 0, s, d, C, c, b, ldb, lambda,
+                     isl, u, v);
   AES_LAUNCH_CHECK();
 }
 

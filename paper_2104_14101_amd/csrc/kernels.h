@@ -90,8 +90,13 @@ void launch_rowdot(int64_t nrows, int64_t ncols, const double* M, int64_t ldm, i
 void launch_copy_cols(int64_t rows, int C, const double* src, int64_t lds, int csrc, double* dst,
                       int64_t ldd, hipStream_t s, const int* gate = nullptr);
 void launch_fill(double* p, int64_t count, double v, hipStream_t s);
+// dst[c, r] = src[r, c] * (colscale ? colscale[c] : 1)
 void launch_transpose(int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst,
-                      int64_t ldd, hipStream_t s);
+                      int64_t ldd, hipStream_t s, const double* colscale = nullptr);
+// Dual form (n < d): isl = Lambda^{-1/2}; u = Lambda^{-1/2} b and v = Lambda^{-1} b as d x C
+// (C >= c, the extra columns zero).
+void launch_dual_prep(int64_t d, int C, int c, const double* b, int64_t ldb, const double* lambda, double* isl,
+                      double* u, double* v, hipStream_t s);
 void launch_inv(int64_t count, const double* src, double* dst, hipStream_t s);
 template <typename TO>
 void launch_cast(int64_t n, int64_t d, const double* A, int64_t lda, TO* out, hipStream_t s);
