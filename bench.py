@@ -130,15 +130,16 @@ def to_numpy(P):
     return out
 
 
-def timed_solves(aes, torch, A, b, nu, lam, opts, steps, warmup, profile=False):
+def timed_solves(aes, torch, A, b, nu, lam, opts, steps, warmup, profile=False, fn=None):
+    fn = fn or aes.solve
     for _ in range(warmup):
-        aes.solve(A, b, nu, lam, **opts)
+        fn(A, b, nu, lam, **opts)
     torch.cuda.synchronize()
     infos = []
     t0 = time.perf_counter()
     x = None
     for _ in range(steps):
-        x, info = aes.solve(A, b, nu, lam, profile=profile, **opts)
+        x, info = fn(A, b, nu, lam, profile=profile, **opts)
         infos.append(info)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -207,6 +208,11 @@ def main():
                     help="with --skip-main: the synthetic nu-sweep of Sec. 5 at n=16384, d=7000")
     ap.add_argument("--paper-large", action="store_true",
                     help="with --skip-main: the same at n=131072, d=7000 (nu = 1e-2, 1e-3)")
+    ap.add_argument("--dual", action="store_true",
+                    help="with --skip-main: n < d through the dual (n=1545, d=10936, c=2; n=8192, d=32768) "
+                         "next to the primal solve")
+    ap.add_argument("--dual-wide", action="store_true",
+                    help="with --skip-main: only the dual solve at n=8192, d=32768, nu=1e-2 (kernel profiles)")
     ap.add_argument("--paper-e3", action="store_true",
                     help="with --skip-main: the same at n=524288, d=14000 (A is 58.7 GB; nu = 1e-2 .. 1e-4; "
                          "CG capped at 2000 steps; errors against PCG at m = 2d to 1e-12)")
@@ -237,6 +243,12 @@ def main():
                                         cg_iters=2000)
         if args.mixed:
             out["mixed_vs_fp64"] = mixed_leg(aes, torch, synth)
+        if args.dual:
+            # the OVA-Lung shape of Sec. 5 (n = 1545, d = 10936, c = 2), then a wider one
+            out["dual_ova_lung_shape"] = dual_leg(aes, torch, synth, 1545, 10936, (1e-1, 1e-2), nrhs=2)
+            out["dual_n8192_d32768"] = dual_leg(aes, torch, synth, 8192, 32768, (1e-1, 1e-2), ref="primal")
+        if args.dual_wide:
+            out["dual_n8192_d32768"] = dual_leg(aes, torch, synth, 8192, 32768, (1e-2,), ref="none", forms=("dual",))
         if args.batched or args.all:
             out["batched"] = batched_leg(aes, torch, synth)
         if args.adjoint or args.all:
@@ -365,6 +377,45 @@ def paper_leg(aes, torch, synth, n, d, nus, cross=False, cg_iters=20000):
                          "time_sketch_ms": i["time_sketch_ms"]}
             print(json.dumps({"paper": [n, d, nu, name, round(sec, 5), i["iterations"], i["final_m"]]}),
                   file=sys.stderr, flush=True)
+        out["nu"][f"{nu:g}"] = res
+    return out
+
+
+def dual_leg(aes, torch, synth, n, d, nus, nrhs=1, ref="oracle", forms=("dual", "primal")):
+    """n < d through the dual problem of Sec. 1 (aes_solve_dual) next to the primal solve of the
+    same problem, adaptive PCG with the SRHT from m = 1, tol 1e-10, Lambda = I,
+    sigma_j = 0.995^j over the n directions, b = A^T y.  Errors of x against the oracle's
+    refined reference (ref="oracle"), against a primal PCG solve to 1e-12 (ref="primal"), or
+    not at all (ref="none": the dual solve alone, for kernel profiles)."""
+    import numpy as np
+
+    from oracle import reference
+
+    P = synth.make_wide_problem(n, d, "geo:0.995", nus[0], nrhs=nrhs, seed=0, backend="torch", device="cuda")
+    A, b = P["A"], P["b"]
+    P_np = to_numpy(P) if ref == "oracle" else None
+    out = {"n": n, "d": d, "c": nrhs, "sigma": "0.995^j", "nu": {},
+           "reference": {"oracle": "oracle refined reference", "primal": "primal PCG to 1e-12", "none": None}[ref]}
+    for nu in nus:
+        xr = None
+        if ref == "primal":
+            xr_t, _ = aes.solve(A, b, nu, None, method="pcg", sketch="srht", m_init=1, seed=7, tol=1e-12)
+            xr = xr_t.cpu().numpy()
+        elif ref == "oracle":
+            xr = reference.reference_solution(P_np["A"], P_np["b"], nu, None)
+        res = {"d_e": reference.effective_dimension_closed(P["sigma"], nu)}
+        for name in forms:
+            fn = aes.solve_dual if name == "dual" else aes.solve
+            opts = dict(method="pcg", sketch="srht", m_init=1, seed=1, tol=1e-10)
+            x, infos, sec = timed_solves(aes, torch, A, b, nu, None, opts, 3, 1, fn=fn)
+            i = infos[-1]
+            err = float(np.max(reference.rel_error(x.cpu().numpy(), xr))) if xr is not None else None
+            res[name] = {"s_per_solve": sec, "rel_err": err, "status": i["status"], "iterations": i["iterations"],
+                         "final_m": i["final_m"], "a_passes": i["a_passes"], "time_sketch_ms": i["time_sketch_ms"]}
+            print(json.dumps({"dual_leg": [n, d, nu, name, round(sec, 5), i["iterations"], i["final_m"], err]}),
+                  file=sys.stderr, flush=True)
+        if len(forms) == 2:
+            res["primal_over_dual"] = res["primal"]["s_per_solve"] / res["dual"]["s_per_solve"]
         out["nu"][f"{nu:g}"] = res
     return out
 

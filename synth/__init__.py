@@ -151,6 +151,37 @@ def make_problem(n, d, decay, nu, lam="identity", nrhs=1, seed=0, backend="numpy
     raise ValueError(backend)
 
 
+def make_wide_problem(n, d, decay, nu, lam="identity", nrhs=1, seed=0, backend="numpy", device=None):
+    """A problem with n < d (the dual form's shape, e.g. the paper's OVA-Lung n = 1545,
+    d = 10936): A is the transpose of the matrix ``make_problem`` draws at d x n, so its n
+    singular values follow ``decay``; Lambda (length d) and b = A^T y with y ~ N(0, I_n) are drawn
+    afterwards.  Returns a dict with A (n x d), b, nu, lam, sigma, y."""
+    if n > d:
+        raise ValueError("make_wide_problem needs n <= d")
+    if lam not in ("identity", "uniform1_10"):
+        raise ValueError(lam)
+    P = make_problem(d, n, decay, nu, "identity", 1, seed, backend, device)
+    if backend == "numpy":
+        A = np.ascontiguousarray(P["A"].T)
+        rng = np.random.default_rng(np.random.SeedSequence([SEED_BASE, seed, 1]))
+        lv = np.ones(d) if lam == "identity" else 1.0 + 9.0 * rng.random(d)
+        Y = rng.standard_normal((n, nrhs))
+        B = A.T @ Y
+    else:
+        import torch
+
+        A = P["A"].T.contiguous()
+        del P["A"]
+        g = torch.Generator(device=A.device)
+        g.manual_seed(SEED_BASE * 1000003 + int(seed) + 7919)
+        lv = (torch.ones(d, device=A.device, dtype=torch.float64) if lam == "identity"
+              else 1.0 + 9.0 * torch.rand(d, generator=g, device=A.device, dtype=torch.float64))
+        Y = torch.randn((n, nrhs), generator=g, device=A.device, dtype=torch.float64)
+        B = (A.T @ Y).contiguous()
+    return dict(A=A, b=B[:, 0] if nrhs == 1 else B, nu=float(nu), lam=lv, sigma=P["sigma"],
+                y=Y[:, 0] if nrhs == 1 else Y)
+
+
 def make_workload(name, seed=0, backend="numpy", device=None, **kw):
     w = WORKLOADS[name]
     return make_problem(w.n, w.d, w.decay, w.nu, w.lam, w.nrhs, seed=seed, backend=backend, device=device, **kw)

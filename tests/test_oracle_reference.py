@@ -43,3 +43,14 @@ def test_residual_extended_matches_float_residual():
     lam = 1 + rng.random(20)
     r = reference.residual_extended(A, b, 0.1, lam, x, chunk=64).astype(np.float64)
     np.testing.assert_allclose(r, b - A.T @ (A @ x) - 0.01 * lam[:, None] * x, rtol=1e-10, atol=1e-10)
+
+
+def test_wide_problem_recipe():
+    # n < d inputs of the dual form: A has exactly the prescribed n singular values, b = A^T y
+    P = synth.make_wide_problem(200, 900, "geo:0.99", 1e-2, lam="uniform1_10", nrhs=2, seed=4)
+    A = P["A"]
+    assert A.shape == (200, 900) and P["b"].shape == (900, 2) and P["lam"].shape == (900,)
+    s = np.linalg.svd(A, compute_uv=False)
+    assert np.max(np.abs(s - P["sigma"]) / P["sigma"]) <= 1e-12
+    assert np.allclose(P["b"], A.T @ P["y"], rtol=0, atol=1e-12)
+    assert np.all((P["lam"] >= 1.0) & (P["lam"] <= 10.0))
