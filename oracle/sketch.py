@@ -21,7 +21,9 @@ Pins (tests/test_oracle_sketch.py): FWHT == scipy.linalg.hadamard(n') @ X, H^2 =
 bit-exact on integer data; m = n' SRHT gives (SA)^T SA = A^T A; Monte-Carlo E[S^T S] = I for
 the three embeddings; uniform marginals of the row sample; Gaussian moments; the SJLT as a dense
 S with one +-1 per column, its hash against big-integer arithmetic, uniform buckets and the
-closed-form second moment of U^T S^T S U - I.
+closed-form second moment of U^T S^T S U - I; for ``srht_reuse``: its dense matrix form
+from scipy's Hadamard matrix with the signs of index 0, equality with the SRHT at k = 0, the
+isometry at m = n' and the Monte-Carlo mean over k of S_k^T S_k with E_0 fixed.
 """
 import numpy as np
 
@@ -81,6 +83,23 @@ def srht(A, m, seed, k, problem=0):
     return Y[R] / np.sqrt(m)
 
 
+def srht_reuse(A, m, seed, k, problem=0):
+    """S_k A for the transform-reuse variant of the SRHT (not the paper's method).
+
+    S_k = sqrt(n'/m) R_k (H / sqrt(n')) E_0: the signs of sketch index 0 for every k, the row
+    sample R_k of index k.  Each S_k on its own is an SRHT, so a bound that holds for one SRHT
+    holds for every S_k (a union bound over the resizes still applies), but the S_k share E_0
+    and are not independent.  Computed from the normalised transform of A itself,
+    Y = (H / sqrt(n')) E_0 A_pad (the SRHT of index 0 at m = n', which keeps every row in
+    order), as sqrt(n'/m) Y[R_k]: the transform is the same for every resize.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    npad = padded_size(A.shape[0])
+    Y = srht(A, npad, seed, 0, problem)
+    R = srht_rows(seed, k, A.shape[0], m, problem)
+    return Y[R] * np.sqrt(npad / m)
+
+
 def srht_row(A, m, seed, k, j, problem=0):
     """Row j of S A computed directly from H's closed form, for spot checks at large n."""
     A = np.asarray(A, dtype=np.float64)
@@ -134,6 +153,8 @@ def gaussian_cols(seed, k, rows, i0, i1, problem=0):
 def sketch(A, m, kind, seed, k, problem=0):
     if kind == "srht":
         return srht(A, m, seed, k, problem)
+    if kind == "srht_reuse":
+        return srht_reuse(A, m, seed, k, problem)
     if kind == "gauss":
         return gaussian(A, m, seed, k, problem)
     if kind == "sjlt":

@@ -53,11 +53,29 @@ def test_srht_matrix_form_and_rows():
         np.testing.assert_allclose(sk.srht_row(A, m, 11, 3, j), SA[j], rtol=1e-13, atol=1e-13)
 
 
+def test_srht_reuse_matrix_form():
+    # S_k = H[R_k] E_0 / sqrt(m): rows of sketch index k, signs of index 0 (a sign draw keyed by
+    # k, or rows keyed by 0, fails this)
+    rng = np.random.default_rng(3)
+    n, d, m = 37, 4, 9
+    A = rng.standard_normal((n, d))
+    for k in (1, 3):
+        SA = sk.srht_reuse(A, m, seed=11, k=k)
+        R = sk.srht_rows(11, k, n, m)
+        eps0 = philox.signs(11, 0, n)
+        S = sla.hadamard(64)[R][:, :n] * eps0[None, :] / np.sqrt(m)
+        np.testing.assert_allclose(SA, S @ A, rtol=1e-13, atol=1e-13)
+    # index 0 is the SRHT of index 0; m = n' is an isometry for every k
+    np.testing.assert_allclose(sk.srht_reuse(A, m, 11, 0), sk.srht(A, m, 11, 0), rtol=1e-14, atol=1e-14)
+    SA = sk.srht_reuse(A, 64, 11, 5)
+    np.testing.assert_allclose(SA.T @ SA, A.T @ A, rtol=1e-12, atol=1e-12)
+
+
 def _sts(kind, n, m, seed, k):
     return np.array(sk.sketch(np.eye(n), m, kind, seed, k)).T @ np.array(sk.sketch(np.eye(n), m, kind, seed, k))
 
 
-@pytest.mark.parametrize("kind", ["srht", "gauss", "sjlt"])
+@pytest.mark.parametrize("kind", ["srht", "gauss", "sjlt", "srht_reuse"])
 def test_sketch_unbiased(kind):
     # E[S^T S] = I: average over independent sketch indices (Monte Carlo).
     n, m, reps = 16, 4, 600
