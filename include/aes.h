@@ -52,7 +52,13 @@ typedef enum {
  * (Sec. 5): no sketch, FP64 only, stop rules XREL (with the identity for H_S:
  * r^T r <= (nu^2 min(lambda) tol)^2 ||x||^2), DTILDE_REL and FIXED. */
 typedef enum { AES_PCG = 0, AES_IHS = 1, AES_CG = 2 } aes_method;
-typedef enum { AES_SRHT = 0, AES_GAUSS = 1, AES_SJLT = 2 } aes_sketch_kind;
+/* AES_SRHT_REUSE: transform-reuse variant of the SRHT (not the paper's method; FP64 only).
+ * S_k = sqrt(n'/m) R_k (H / sqrt(n')) E_0: the signs of index 0 for every sketch index k and the
+ * row sample of index k.  Each S_k alone is an SRHT (Sec. 2.1), so a guarantee stated for one
+ * SRHT holds for each of them and a union bound over the resizes applies, but the S_k share E_0
+ * and H and are not independent.  A solve transforms A once (n' x d doubles kept in the handle's
+ * workspace); every resize then only draws rows of the stored transform. */
+typedef enum { AES_SRHT = 0, AES_GAUSS = 1, AES_SJLT = 2, AES_SRHT_REUSE = 3 } aes_sketch_kind;
 typedef enum {
   AES_FP64 = 0,       /* every step in FP64 */
   AES_MIXED = 1,      /* FP32-stored A for the PCG matvecs and the SRHT or SJLT (FP32 sums,
@@ -243,7 +249,9 @@ aes_status aes_hv_multi(aes_handle h, void* stream, int64_t n, int64_t d, int64_
  * kind AES_GAUSS: SA = G A / sqrt m with G from stream GAUSS by Box-Muller;
  * kind AES_SJLT: the sparse embedding with one +-1 per column (s = 1): data row i goes, with
  * its sign, into sketch row h_i, both from stream SJLT; each sketch row sums its rows in
- * increasing order (n < 2^31; m may exceed n, leaving zero rows).
+ * increasing order (n < 2^31; m may exceed n, leaving zero rows);
+ * kind AES_SRHT_REUSE: SA = sqrt(n'/m) R_k Y with Y = (1/sqrt n') H E_0 A_pad (signs of index 0,
+ * rows of index k), computed from scratch on every call.
  *   SA: device, m x d output (ld = d).  1 <= m <= n'. */
 aes_status aes_sketch(aes_handle h, void* stream, int kind, int64_t n, int64_t d, const double* A,
                       int64_t lda, int64_t m, uint64_t seed, int32_t problem, int64_t k, double* SA);

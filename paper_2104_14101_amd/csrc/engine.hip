@@ -136,7 +136,9 @@ void validate(const ProblemDesc& P, double tol, const aes_options& o) {
   if (o.method != AES_PCG && o.method != AES_IHS && o.method != AES_CG) bad("unknown method");
   if (o.method == AES_CG && o.precision != AES_FP64) bad("the CG baseline runs in FP64");
   if (o.method == AES_CG && o.stop == AES_STOP_REMARK) bad("the REMARK stop rule needs a sketch");
-  if (o.sketch != AES_SRHT && o.sketch != AES_GAUSS && o.sketch != AES_SJLT) bad("unknown sketch");
+  if (o.sketch != AES_SRHT && o.sketch != AES_GAUSS && o.sketch != AES_SJLT && o.sketch != AES_SRHT_REUSE)
+    bad("unknown sketch");
+  if (o.sketch == AES_SRHT_REUSE && o.precision != AES_FP64) bad("the transform-reuse SRHT runs in FP64");
   if (o.sketch == AES_SJLT && P.n >= (int64_t(1) << 31)) bad("the SJLT needs n < 2^31");
   if (o.precision < AES_FP64 || o.precision > AES_MIXED_FP32) bad("unknown precision");
   if (o.stop < 0 || o.stop > 3) bad("unknown stop rule");
@@ -344,7 +346,28 @@ class Solver {
     } else {
       SA_ = B<double>("SA", (size_t)m_ * d_);
     }
-    if (o_.sketch == AES_SRHT) {
+    if (o_.sketch == AES_SRHT_REUSE) {
+      // transform-reuse variant: Y = (H / sqrt(n')) E_0 A_pad once per solve (the SRHT of
+      // index 0 at m = n', every row kept in order), then rows R_k of Y scaled by sqrt(n'/m)
+      SelectScratch sc;
+      sc.keys = B<uint64_t>("sel_keys", npad_);
+      sc.pos = B<int32_t>("sel_pos", npad_);
+      sc.hist = B<uint32_t>("sel_hist", 256 * 8);
+      sc.state = B<uint64_t>("sel_state", 4);
+      sc.blk = B<uint32_t>("sel_blk", 2 * select_blocks(npad_));
+      if (!yr_ready_) {
+        double* eps = B<double>("eps", n_);
+        launch_signs(o_.seed, o_.problem, 0, n_, eps, s_);
+        launch_srht_select(o_.seed, o_.problem, 0, npad_, npad_, sc, s_);
+        yr_ = B<double>("Yreuse", (size_t)npad_ * d_);
+        launch_srht_apply<double, double, double>(P_.A, n_, d_, P_.lda, eps, npad_, sc.pos, npad_,
+                                                  B<double>("Y", srht_scratch_elems(npad_, d_)), yr_, d_,
+                                                  B<int32_t>("need", 512), s_);
+        yr_ready_ = true;
+      }
+      launch_srht_select(o_.seed, o_.problem, k_, npad_, m_, sc, s_);
+      launch_gather_rows(npad_, d_, yr_, sc.pos, std::sqrt((double)npad_ / (double)m_), SA_, d_, s_);
+    } else if (o_.sketch == AES_SRHT) {
       double* eps = B<double>("eps", n_);
       launch_signs(o_.seed, o_.problem, k_, n_, eps, s_);
       SelectScratch sc;
@@ -892,6 +915,8 @@ class Solver {
   int64_t n_, d_, c_;
   int C_;
   int64_t npad_, mcap_, m_ = 1, k_ = 0, fp_ = 64;
+  double* yr_ = nullptr;   // transform-reuse SRHT: the stored normalised transform of A
+  bool yr_ready_ = false;
   double nu2_;
   bool mixed_ = false, woodbury_ = false;
   double *lam_ = nullptr, *invlam_ = nullptr, *X_ = nullptr, *R_ = nullptr, *Pv_ = nullptr, *Q_ = nullptr,
@@ -1378,6 +1403,22 @@ aes_status aes_sketch(aes_handle h, void* stream, int kind, int64_t n, int64_t d
       double* Y = h->buf<double>("sk.Y", srht_scratch_elems(npad, d));
       launch_srht_apply<double, double, double>(A, n, d, lda, eps, npad, sc.pos, m, Y, SA, d,
                                                 h->buf<int32_t>("sk.need", 512), s);
+    } else if (kind == AES_SRHT_REUSE) {
+      double* eps = h->buf<double>("sk.eps", n);
+      launch_signs(seed, problem, 0, n, eps, s);
+      SelectScratch sc;
+      sc.keys = h->buf<uint64_t>("sk.keys", npad);
+      sc.pos = h->buf<int32_t>("sk.pos", npad);
+      sc.hist = h->buf<uint32_t>("sk.hist", 256 * 8);
+      sc.state = h->buf<uint64_t>("sk.state", 4);
+      sc.blk = h->buf<uint32_t>("sk.blk", 2 * select_blocks(npad));
+      launch_srht_select(seed, problem, 0, npad, npad, sc, s);
+      double* Yr = h->buf<double>("sk.Yreuse", (size_t)npad * d);
+      launch_srht_apply<double, double, double>(A, n, d, lda, eps, npad, sc.pos, npad,
+                                                h->buf<double>("sk.Y", srht_scratch_elems(npad, d)), Yr, d,
+                                                h->buf<int32_t>("sk.need", 512), s);
+      launch_srht_select(seed, problem, k, npad, m, sc, s);
+      launch_gather_rows(npad, d, Yr, sc.pos, std::sqrt((double)npad / (double)m), SA, d, s);
     } else if (kind == AES_SJLT) {
       if (n >= (int64_t(1) << 31)) throw StatusError(AES_ERR_INVALID_ARG, "the SJLT needs n < 2^31");
       const SjltPlan sp = sjlt_plan(n, d, m, sizeof(double));

@@ -731,4 +731,41 @@ template void launch_srht_apply<float, float, __hip_bfloat16>(const float*, int6
                                                               int64_t, const int32_t*, int64_t, float*, __hip_bfloat16*,
                                                               int64_t, int32_t*, hipStream_t);
 
+// ---------------------------------------------------------------------------------------
+// Transform-reuse SRHT: SA[pos[i], :] = scale * Y[i, :] for the padded rows i with
+// pos[i] >= 0 (Y is the stored normalised transform, npad x d, ld d).  One wave per padded row,
+// four 8-byte loads in flight per lane.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void gather_rows_kernel(int64_t npad, int64_t d, const double* __restrict__ Y,
+                                                          const int32_t* __restrict__ pos, double scale,
+                                                          double* __restrict__ SA, int64_t ldsa) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i = wave; i < npad; i += nwaves) {
+    const int32_t r = pos[i];
+    if (r < 0) continue;
+    const double* src = Y + i * d;
+    double* dst = SA + (int64_t)r * ldsa;
+    int64_t j = lane;
+    for (; j + 3 * 64 < d; j += 4 * 64) {
+      double v[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] = src[j + 64 * k];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) dst[j + 64 * k] = v[k] * scale;
+    }
+    for (; j < d; j += 64) dst[j] = src[j] * scale;
+  }
+}
+
+void launch_gather_rows(int64_t npad, int64_t d, const double* Y, const int32_t* pos, double scale, double* SA,
+                        int64_t ldsa, hipStream_t s) {
+  if (npad <= 0 || d <= 0) return;
+  int64_t blocks = ceil_div(npad, 4);
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, npad, d, Y, pos, scale, SA, ldsa);
+  AES_LAUNCH_CHECK();
+}
+
 }  // namespace aes

@@ -122,6 +122,10 @@ size_t srht_scratch_elems(int64_t npad, int64_t d);
 template <typename TIN, typename TY, typename TOUT>
 void launch_srht_apply(const TIN* A, int64_t n, int64_t d, int64_t lda, const double* eps, int64_t npad,
                        const int32_t* pos, int64_t m, TY* Y, TOUT* SA, int64_t ldsa, int32_t* need, hipStream_t s);
+// Transform-reuse SRHT: SA[pos[i], :] = scale * Y[i, :] for the padded rows with pos[i] >= 0
+// (Y: the stored normalised transform, npad x d, ld d; pos from launch_srht_select).
+void launch_gather_rows(int64_t npad, int64_t d, const double* Y, const int32_t* pos, double scale, double* SA,
+                        int64_t ldsa, hipStream_t s);
 // Gaussian sketch SA (m x d, ld d) = G A / sqrt(m): the plan sizes the generated slab of G
 // (gt_elems doubles) and the split-K partials (part_elems doubles, none with one split).
 struct GaussPlan {

@@ -75,6 +75,24 @@ def test_srht_float_data(n, d, m):
     np.testing.assert_allclose(SA, ref, rtol=4.5e-16, atol=0)
 
 
+@pytest.mark.parametrize("n,d,m,k", [(4000, 33, 1024, 3), (16384, 64, 256, 0), (16384, 64, 256, 5)])
+def test_srht_reuse_bit_exact_on_integers(n, d, m, k):
+    # n' and n'/m powers of 4: the normalised transform and the rescale by sqrt(n'/m) are exact
+    rng = np.random.default_rng(n + d + m + k)
+    A = rng.integers(-50, 51, size=(n, d)).astype(np.float64)
+    SA = aes.sketch(to_dev(A), m, "srht_reuse", seed=21, k=k).cpu().numpy()
+    np.testing.assert_array_equal(SA, osk.srht_reuse(A, m, 21, k))
+
+
+@pytest.mark.parametrize("n,d,m,k", [(3000, 70, 100, 2), (20000, 129, 1000, 1)])
+def test_srht_reuse_float_data(n, d, m, k):
+    rng = np.random.default_rng(6)
+    A = rng.standard_normal((n, d))
+    SA = aes.sketch(to_dev(A), m, "srht_reuse", seed=4, k=k).cpu().numpy()
+    # identical transform; the two scalings may each round differently
+    np.testing.assert_allclose(SA, osk.srht_reuse(A, m, 4, k), rtol=1e-15, atol=0)
+
+
 def test_srht_full_size_sampled_rows():
     P = synth.make_problem(65536, 2048, "pow:1", 1e-3, seed=12, backend="torch", device="cuda")
     A = P["A"]

@@ -64,6 +64,21 @@ def test_sjlt_trajectory_and_accuracy(small, method):
     assert reference.rel_error(x.cpu().numpy(), xo) <= 1e-9
 
 
+@pytest.mark.parametrize("method", ["pcg", "ihs"])
+def test_srht_reuse_trajectory_and_accuracy(small, method):
+    kw = dict(method=method, sketch="srht_reuse", m_init=8, seed=1, tol=1e-10)
+    x, info = aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], trace_cap=256, **kw)
+    xo, io = solvers.solve(small["A"], small["b"], small["nu"], small["lam"], solvers.Options(**kw))
+    assert info["status"] == "ok"
+    assert _traj_gpu(info) == _traj_cpu(io)
+    assert info["final_m"] == io.final_m and info["a_passes"] == io.a_passes
+    assert reference.rel_error(x.cpu().numpy(), small["xref"]) <= 1e-10
+    assert reference.rel_error(x.cpu().numpy(), xo) <= 1e-9
+    # FP64 only
+    with pytest.raises(aes.AesError, match="invalid_arg"):
+        aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], sketch="srht_reuse", precision="mixed")
+
+
 @pytest.mark.parametrize("precision", ["mixed", "mixed_fp32"])
 def test_sjlt_mixed_precision(small, precision):
     x, info = aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], precision=precision, sketch="sjlt",
