@@ -38,6 +38,10 @@ Readings where the paper is silent (each also listed in the design notes):
 
 ``cg`` is the paper's unpreconditioned conjugate-gradient baseline (Sec. 5).
 ``dual_solve`` takes the dual route of Sec. 1 for n < d (eq. "dual optimization problem").
+Method 'polyak' of ``adaptive_ihs`` is the heavy-ball (Polyak-IHS) update of the appendix
+"Heavy-ball Acceleration and Adaptivity" with the corollary's mu_rho, beta_rho and, for the
+adaptive form, its finite-time factor alpha(t, rho) beta_rho^omega(t) in the test (the paper
+describes this adaptive version but calls it impractical; readings in ``adaptive_ihs``).
 
 Pins (tests/test_oracle_solvers.py): one-step convergence when m = n' (H_S = H); Krylov
 optimality of PCG (Theorem "rate cg") by brute-force least squares on tiny problems; the IHS
@@ -46,7 +50,10 @@ lemma); invariants of the adaptive control (accepted steps satisfy the test, m d
 bounded, forced rejections recompute r_t = b - H x_t); rel. error <= 1e-10 against the
 refined direct solution; for ``cg``: termination in d steps, Krylov optimality in the
 H-norm by brute-force least squares, and the xrel bound on the true error; for
-``dual_solve``: the primal x* of the refined direct solve and A x* = w*.
+``dual_solve``: the primal x* of the refined direct solve and A x* = w*; for 'polyak': the
+paper's printed table of the finite-time factor (tests/golden/polyak_bound_table.txt), mu_rho
+and beta_rho as the heavy-ball lemma's choice, the heavy-ball error recursion, the momentum
+restart at a resize.
 """
 import math
 import warnings
@@ -103,6 +110,23 @@ def ihs_constants(rho):
     return rho, c, 1.0 - rho
 
 
+def polyak_constants(rho):
+    """(mu_rho, beta_rho) of the Polyak-IHS corollary (heavy-ball appendix):
+    mu = 2 (1 - rho) / (1 + sqrt(1 - rho)), beta = (1 - sqrt(1 - rho)) / (1 + sqrt(1 - rho))."""
+    q = math.sqrt(1.0 - rho)
+    return 2.0 * (1.0 - rho) / (1.0 + q), (1.0 - q) / (1.0 + q)
+
+
+def polyak_log_bound(t, rho):
+    """log of alpha(t, rho) * beta_rho^omega(t), the finite-time factor of the Polyak-IHS
+    corollary: nu(t) = log2(t) + 1 (real-valued), omega(t) = t - 2 nu(t),
+    alpha(t, rho) = 3^(nu (nu + 1)) (1 + 4 beta + beta^2)^(2 nu).  t >= 1."""
+    _, beta = polyak_constants(rho)
+    nu_t = math.log(t) / math.log(2.0) + 1.0
+    log_alpha = nu_t * (nu_t + 1.0) * math.log(3.0) + 2.0 * nu_t * math.log(1.0 + 4.0 * beta + beta * beta)
+    return log_alpha + (t - 2.0 * nu_t) * math.log(beta)
+
+
 def remark_m_delta(n, d, delta=None):
     """m_delta of the SRHT concentration theorem with d_e := d (Remark on termination)."""
     de = float(d)
@@ -135,8 +159,8 @@ def _validate(A, b, nu, lam, o):
         raise ValueError("m_init must be >= 1")
     if o.tol <= 0 and o.stop != "fixed":
         raise ValueError("tol must be > 0")
-    if o.method not in ("pcg", "ihs"):
-        raise ValueError("method must be 'pcg' or 'ihs'")
+    if o.method not in ("pcg", "ihs", "polyak"):
+        raise ValueError("method must be 'pcg', 'ihs' or 'polyak'")
 
 
 class _Stopper:
@@ -286,8 +310,16 @@ def adaptive_pcg(A, b, nu, lam=None, opts=None):
 
 
 def adaptive_ihs(A, b, nu, lam=None, opts=None):
-    """Adaptive IHS (Algorithm 1 with psi = IHS, mu = 1 - rho).  Returns (x, Info)."""
+    """Adaptive IHS (Algorithm 1 with psi = IHS, mu = 1 - rho).  Returns (x, Info).
+
+    With method 'polyak' the update is the heavy-ball (Polyak-IHS) step of the appendix,
+    x+ = x - mu_rho H_S^{-1} g + beta_rho (x - x_prev), with x_prev = x_0 at the start and
+    x_prev = x_t after a resize (the momentum restarts with the new sketch), and the test of
+    Algorithm 1 takes the corollary's finite-time factor: reject when
+    D+/D_I > (1+sqrt rho)/(1-sqrt rho) * alpha(tau, rho) beta_rho^omega(tau), tau = t+1-I.
+    """
     o = opts or Options(method="ihs")
+    polyak = o.method == "polyak"
     A = np.asarray(A, dtype=np.float64)
     n, d = A.shape
     B, squeeze = _as2d(b)
@@ -296,6 +328,9 @@ def adaptive_ihs(A, b, nu, lam=None, opts=None):
     _validate(A, B, nu, lam, o)
     info = Info()
     phi, cc, mu = ihs_constants(o.rho)
+    beta = 0.0
+    if polyak:
+        mu, beta = polyak_constants(o.rho)
     log_phi, log_c = math.log(phi), math.log(cc)
     m_cap = sk.max_sketch_size(n, o.sketch) if o.m_max <= 0 else min(o.m_max, sk.max_sketch_size(n, o.sketch))
     m = min(o.m_init, m_cap)
@@ -312,6 +347,7 @@ def adaptive_ihs(A, b, nu, lam=None, opts=None):
         info.a_passes += 1
     else:
         G = -B.copy()
+    Xprev = X.copy()
     Sd = P.apply(G)
     Dt = 0.5 * np.sum(G * Sd, axis=0)
     DI = Dt.copy()
@@ -326,6 +362,8 @@ def adaptive_ihs(A, b, nu, lam=None, opts=None):
             break
         J = np.flatnonzero(active)
         Xp = X[:, J] - mu * Sd[:, J]
+        if polyak:
+            Xp = Xp + beta * (X[:, J] - Xprev[:, J])
         Gp = hess_apply(A, nu, lam, Xp) - B[:, J]
         info.a_passes += 1
         Sp = P.apply(Gp)
@@ -334,7 +372,7 @@ def adaptive_ihs(A, b, nu, lam=None, opts=None):
         if not np.all(np.isfinite(Dp)):
             info.status = "nonfinite"
             break
-        thr = log_c + (t + 1 - I) * log_phi
+        thr = log_c + (polyak_log_bound(t + 1 - I, o.rho) if polyak else (t + 1 - I) * log_phi)
         with np.errstate(divide="ignore"):
             lr = np.where(Dp > 0, np.log(np.maximum(Dp, 1e-300)) - np.log(DI[J]), -np.inf)
         fail = bool(np.any(lr > thr))
@@ -355,9 +393,11 @@ def adaptive_ihs(A, b, nu, lam=None, opts=None):
             Sd[:, J] = P.apply(G[:, J])
             Dt[J] = 0.5 * np.sum(G[:, J] * Sd[:, J], axis=0)
             DI[J] = Dt[J]
+            Xprev[:, J] = X[:, J]
             continue
         if fail and o.adaptive:
             info.m_cap_reached = True
+        Xprev[:, J] = X[:, J]
         X[:, J], G[:, J], Sd[:, J], Dt[J] = Xp, Gp, Sp, Dp
         t += 1
         if o.keep_iterates:
@@ -447,7 +487,7 @@ def solve(A, b, nu, lam=None, opts=None):
     o = opts or Options()
     if o.method == "cg":
         return cg(A, b, nu, lam, o)
-    return adaptive_ihs(A, b, nu, lam, o) if o.method == "ihs" else adaptive_pcg(A, b, nu, lam, o)
+    return adaptive_ihs(A, b, nu, lam, o) if o.method in ("ihs", "polyak") else adaptive_pcg(A, b, nu, lam, o)
 
 
 def dual_solve(A, b, nu, lam=None, opts=None):

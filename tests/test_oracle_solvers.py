@@ -114,10 +114,10 @@ def small():
     return P
 
 
-@pytest.mark.parametrize("method", ["pcg", "ihs"])
+@pytest.mark.parametrize("method", ["pcg", "ihs", "polyak"])
 @pytest.mark.parametrize("kind", ["srht", "gauss", "sjlt", "srht_reuse"])
 def test_solution_accuracy(small, method, kind):
-    if kind not in ("srht", "srht_reuse") and method == "ihs":
+    if kind not in ("srht", "srht_reuse") and method != "pcg":
         pytest.skip("covered by the PCG case of the same sketch; keeps the CPU suite short")
     o = solvers.Options(method=method, sketch=kind, m_init=8, tol=1e-10, seed=1)
     x, info = solvers.solve(small["A"], small["b"], small["nu"], small["lam"], o)
@@ -328,3 +328,80 @@ def test_dual_form_vector_rhs_and_validation():
         solvers.dual_solve(A, b, 1.0, None, solvers.Options(x0=np.zeros(16)))
     with pytest.raises(ValueError):
         solvers.dual_solve(A, b[:10], 1.0)
+
+
+def _golden_polyak_table():
+    import os
+
+    rows = []
+    path = os.path.join(os.path.dirname(__file__), "golden", "polyak_bound_table.txt")
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        rows.append((float(f[0]), f[1], f[2], len(f) > 3 and f[3] == "exp_typo"))
+    return rows
+
+
+def test_polyak_bound_matches_the_printed_table():
+    # The paper's table of (alpha(t, rho) beta_rho^omega(t))^(1/t) (heavy-ball appendix): every
+    # entry within one unit of its last printed digit (two entries after the exponent reading).
+    rows = _golden_polyak_table()
+    assert len(rows) == 28
+    for rho, t, txt, typo in rows:
+        mant, _, ex = txt.partition("e")
+        digits = len(mant.split(".")[1]) if "." in mant else 0
+        unit = 10.0 ** ((int(ex) if ex else 0) - digits)
+        printed = float(txt)
+        if typo:
+            printed, unit = printed / 10.0, unit / 10.0
+        if t == "inf":
+            v = solvers.polyak_constants(rho)[1]
+        else:
+            v = math.exp(solvers.polyak_log_bound(int(t), rho) / int(t))
+        assert abs(v - printed) <= unit, (rho, t, v, txt)
+
+
+@pytest.mark.parametrize("rho", [0.3, 0.125, 0.01])
+def test_polyak_constants_are_the_heavy_ball_lemma_choice(rho):
+    # mu_rho, beta_rho of the corollary are the lemma's mu = 4/(sqrt(l)+sqrt(L))^2 and
+    # beta = ((sqrt(L)-sqrt(l))/(sqrt(L)+sqrt(l)))^2 for the spectrum of C_S^{-1} in
+    # [1/(1+sqrt rho), 1/(1-sqrt rho)]
+    lo, hi = 1.0 / (1.0 + math.sqrt(rho)), 1.0 / (1.0 - math.sqrt(rho))
+    mu, beta = solvers.polyak_constants(rho)
+    assert mu == pytest.approx(4.0 / (math.sqrt(lo) + math.sqrt(hi)) ** 2, rel=1e-13)
+    assert beta == pytest.approx(((math.sqrt(hi) - math.sqrt(lo)) / (math.sqrt(hi) + math.sqrt(lo))) ** 2, rel=1e-12)
+
+
+def test_polyak_error_recursion():
+    # Heavy-ball appendix: x_{t+1} - x* = (I - mu H_S^{-1} H)(x_t - x*) + beta (x_t - x_{t-1}),
+    # starting with x_{-1} = x_0 = 0.
+    A, b, nu, lam = _tiny(n=64, d=8, nu=0.2, seed=2)
+    rho, m, seed = 0.2, 16, 4
+    mu, beta = solvers.polyak_constants(rho)
+    H = _H(A, nu, lam)
+    HS = SketchedHessian(sk.srht(A, m, seed, 0), nu, lam).matrix()
+    xs = np.linalg.solve(H, b)
+    T = np.eye(8) - mu * np.linalg.solve(HS, H)
+    e_prev = e = -xs
+    for t in range(1, 6):
+        o = solvers.Options(method="polyak", rho=rho, m_init=m, adaptive=False, stop="fixed", max_iter=t, seed=seed)
+        x, _ = solvers.adaptive_ihs(A, b, nu, lam, o)
+        e, e_prev = T @ e + beta * (e - e_prev), e
+        np.testing.assert_allclose(x - xs, e, rtol=1e-8, atol=1e-11)
+
+
+def test_polyak_resize_restarts_the_momentum(small):
+    # a rejection at t = 3 (forced) restarts at x_3 with x_prev = x_3: the accepted step that
+    # follows is a plain step of size mu_rho (no momentum term) with the new sketch
+    o = solvers.Options(method="polyak", m_init=64, seed=3, stop="fixed", max_iter=4, force_reject_at=(3,),
+                        keep_iterates=True)
+    x, info = solvers.solve(small["A"], small["b"], small["nu"], small["lam"], o)
+    acc = [e for e in info.trace if e["accept"]]
+    last = info.trace[-1]
+    assert last["accept"] and last["t"] == 3 and not info.trace[-2]["accept"] and info.trace[-2]["t"] == 3
+    x3 = acc[2]["x"][:, 0]
+    mu, _ = solvers.polyak_constants(o.rho)
+    HS = SketchedHessian(sk.srht(small["A"], last["m"], 3, last["k"]), small["nu"], small["lam"])
+    g3 = solvers.hess_apply(small["A"], small["nu"], small["lam"], x3[:, None])[:, 0] - small["b"]
+    np.testing.assert_allclose(x, x3 - mu * HS.apply(g3[:, None])[:, 0], rtol=1e-9, atol=1e-12)
