@@ -311,14 +311,14 @@ def main():
 
 def variants_leg(aes, torch, A, b, nu, lam, w, P_np, args):
     """The same workload solved with the other sketches and methods (3 timed solves each; srht_reuse
-    is the transform-reuse variant, not the paper's method) and by the unpreconditioned CG
-    baseline (one timed solve)."""
+    is the transform-reuse variant, not the paper's method; polyak the adaptive heavy-ball IHS of
+    the appendix) and by the unpreconditioned CG baseline (one timed solve)."""
     res = {}
     for method, sketch in (("pcg", "gauss"), ("pcg", "sjlt"), ("pcg", "srht_reuse"), ("ihs", "srht"), ("ihs", "sjlt"),
-                           ("cg", None)):
+                           ("polyak", "srht"), ("cg", None)):
         if method == args.method and sketch == args.sketch:
             continue
-        opts = dict(method=method, m_init=w.m_init, seed=1, tol=1e-10)
+        opts = dict(method=method, m_init=w.m_init, seed=1, tol=1e-10, max_iter=2000)
         if sketch:
             opts["sketch"] = sketch
         else:

@@ -51,7 +51,14 @@ typedef enum {
 /* AES_CG: the unpreconditioned conjugate-gradient baseline of the paper's numerical section
  * (Sec. 5): no sketch, FP64 only, stop rules XREL (with the identity for H_S:
  * r^T r <= (nu^2 min(lambda) tol)^2 ||x||^2), DTILDE_REL and FIXED. */
-typedef enum { AES_PCG = 0, AES_IHS = 1, AES_CG = 2 } aes_method;
+/* AES_POLYAK: the heavy-ball (Polyak-IHS) update of the appendix "Heavy-ball Acceleration and
+ * Adaptivity", x+ = x - mu_rho H_S^{-1} grad f(x) + beta_rho (x - x_prev) with the corollary's
+ * mu_rho = 2(1-rho)/(1+sqrt(1-rho)), beta_rho = (1-sqrt(1-rho))/(1+sqrt(1-rho)).  With
+ * adaptive = 0 it is the fixed-m method; the adaptive form tests D+/D_I against
+ * (1+sqrt rho)/(1-sqrt rho) alpha(tau, rho) beta_rho^omega(tau), tau = t+1-I (the corollary's
+ * finite-time factor), and restarts the momentum (x_prev = x_t) after a resize.  The paper notes
+ * that this factor is too loose for the adaptive form to be practical. */
+typedef enum { AES_PCG = 0, AES_IHS = 1, AES_CG = 2, AES_POLYAK = 3 } aes_method;
 /* AES_SRHT_REUSE: transform-reuse variant of the SRHT (not the paper's method; FP64 only).
  * S_k = sqrt(n'/m) R_k (H / sqrt(n')) E_0: the signs of index 0 for every sketch index k and the
  * row sample of index k.  Each S_k alone is an SRHT (Sec. 2.1), so a guarantee stated for one

@@ -133,7 +133,8 @@ void validate(const ProblemDesc& P, double tol, const aes_options& o) {
   if (!(o.rho > 0.0 && o.rho < 1.0)) bad("rho must lie in (0, 1)");
   if (o.m_init < 1) bad("m_init must be >= 1");
   if (o.stop != AES_STOP_FIXED && !(tol > 0)) bad("tol must be > 0");
-  if (o.method != AES_PCG && o.method != AES_IHS && o.method != AES_CG) bad("unknown method");
+  if (o.method != AES_PCG && o.method != AES_IHS && o.method != AES_CG && o.method != AES_POLYAK)
+    bad("unknown method");
   if (o.method == AES_CG && o.precision != AES_FP64) bad("the CG baseline runs in FP64");
   if (o.method == AES_CG && o.stop == AES_STOP_REMARK) bad("the REMARK stop rule needs a sketch");
   if (o.sketch != AES_SRHT && o.sketch != AES_GAUSS && o.sketch != AES_SJLT && o.sketch != AES_SRHT_REUSE)
@@ -536,19 +537,38 @@ class Solver {
   // the initial point is 0).  Returns the status; fills the counters.
   aes_status adaptive(const double* rhs, double* x, bool x_is_zero, bool use32, int stop_rule, double stop_scale,
                       bool reuse_factor) {
-    const bool ihs = o_.method == AES_IHS;
-    double phi, cc, mu = 0.0;
+    // Polyak-IHS (heavy-ball appendix) runs the IHS step with momentum: mu_rho, beta_rho of the
+    // corollary, x_prev = x_0 at the start and x_t after a resize; the test takes the
+    // corollary's finite-time factor alpha(tau, rho) beta_rho^omega(tau) in place of phi^tau
+    const bool polyak = o_.method == AES_POLYAK;
+    const bool ihs = o_.method == AES_IHS || polyak;
+    double phi, cc, mu = 0.0, beta = 0.0;
     const double sr = std::sqrt(o_.rho);
     if (ihs) {
       phi = o_.rho;
       cc = (1.0 + sr) / (1.0 - sr);
       mu = 1.0 - o_.rho;
+      if (polyak) {
+        const double q = std::sqrt(1.0 - o_.rho);
+        mu = 2.0 * (1.0 - o_.rho) / (1.0 + q);
+        beta = (1.0 - q) / (1.0 + q);
+      }
     } else {
       const double q = std::sqrt(1.0 - o_.rho);
       phi = (1.0 - q) / (1.0 + q);
       cc = 4.0 * (1.0 + sr) / (1.0 - sr);
     }
     const double lphi = std::log(phi), lc = std::log(cc);
+    auto thr_at = [&](int64_t tt, int64_t II) {
+      return polyak ? lc + polyak_log_bound((double)(tt + 1 - II), beta) : thr_of(lc, lphi, tt, II);
+    };
+    // previous iterates of the heavy-ball step: step t reads xpv[t & 1] and writes x to xpv[(t+1) & 1]
+    double* xpv[2] = {nullptr, nullptr};
+    if (polyak) {
+      xpv[0] = B<double>("XPV0", d_ * C_);
+      xpv[1] = B<double>("XPV1", d_ * C_);
+      AES_HIP(hipMemcpyAsync(xpv[0], x, d_ * C_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
+    }
     // With one right-hand side every kernel of a step is gated by a device word that the
     // previous step's finish (or the initialisation) sets when it accepted and has active
     // columns, so the next step is enqueued before the host has read the flags of the current
@@ -599,12 +619,13 @@ class Solver {
       double seq;
     };
     auto enqueue_step = [&](int64_t tt, int force, int slot) -> Step {
-      const double thr = thr_of(lc, lphi, tt, I);
+      const double thr = thr_at(tt, I);
       const int at_cap = m_ >= mcap_ ? 1 : 0;
       const int64_t ev = (o_.profile && !use32 && fused_) ? n_events_ : -1;
       const double seq = spec ? (seq_ctr += 1.0) : -1.0;
       if (ihs) {
-        launch_ihs_candidate(d_, C_, x, Pv_, mu, XP_, active_, s_, gate);
+        launch_ihs_candidate(d_, C_, x, Pv_, mu, XP_, active_, s_, gate, polyak ? xpv[tt & 1] : nullptr, beta,
+                             polyak ? xpv[(tt + 1) & 1] : nullptr);
         hv(XP_, RP_, 1.0, rhs, -1.0, use32, gate);
         apply(RP_, RTP_, gate);
         launch_ihs_finish(d_, C_, x, R_, Pv_, XP_, RP_, RTP_, scal_, active_, gate, thr, force, o_.adaptive, at_cap,
@@ -669,7 +690,7 @@ class Solver {
       if (cur.force) forced = true;
       ++attempts_;
       const bool fail = fl_[0] != 0.0, accepted = fl_[3] != 0.0;
-      trace(t, fl_[4], thr_of(lc, lphi, t, I), accepted);
+      trace(t, fl_[4], thr_at(t, I), accepted);
       if (fl_[2] != 0.0) {
         if (have_next) discard(next);
         return AES_ERR_NONFINITE;
@@ -699,6 +720,8 @@ class Solver {
       ++k_;
       ++resketches_;
       sketch_factor();
+      if (polyak)  // the momentum restarts at x_t with the new sketch
+        AES_HIP(hipMemcpyAsync(xpv[t & 1], x, d_ * C_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
       if (ihs) {
         apply(R_, Pv_);
         launch_ihs_init(d_, C_, R_, Pv_, scal_, active_, gate, stop_rule, stop_scale, stop_sr_, tol2_, x, 0, s_,
@@ -724,6 +747,13 @@ class Solver {
   }
 
   static double thr_of(double lc, double lphi, int64_t t, int64_t I) { return lc + (double)(t + 1 - I) * lphi; }
+  // log of alpha(tau, rho) beta^omega(tau): nu = log2(tau) + 1, omega = tau - 2 nu,
+  // alpha = 3^(nu (nu + 1)) (1 + 4 beta + beta^2)^(2 nu) (Polyak-IHS corollary)
+  static double polyak_log_bound(double tau, double beta) {
+    const double nu = std::log(tau) / std::log(2.0) + 1.0;
+    const double la = nu * (nu + 1.0) * std::log(3.0) + 2.0 * nu * std::log(1.0 + 4.0 * beta + beta * beta);
+    return la + (tau - 2.0 * nu) * std::log(beta);
+  }
 
   hipEvent_t flag_event(int slot) {
     if (!fev_[slot]) AES_HIP(hipEventCreateWithFlags(&fev_[slot], hipEventDisableTiming));

@@ -450,20 +450,30 @@ void launch_ihs_init(int64_t d, int C, const double* g, const double* sd, double
   AES_LAUNCH_CHECK();
 }
 
+// xp = x - mu sd (IHS), or with xprev the heavy-ball step xp = (x - mu sd) + beta (x - xprev),
+// which also saves x to xsave (the previous iterate of the next step)
 __global__ void ihs_candidate_kernel(int64_t total, int C, const double* __restrict__ x, const double* __restrict__ sd,
                                      double mu, double* __restrict__ xp, const int* __restrict__ active,
-                                     const int* __restrict__ gate) {
+                                     const int* __restrict__ gate, const double* __restrict__ xprev, double beta,
+                                     double* __restrict__ xsave) {
   if (gate && *gate == 0) return;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
-  xp[e] = active[e % C] ? x[e] - mu * sd[e] : x[e];
+  const double xe = x[e];
+  double v = xe;
+  if (active[e % C]) {
+    v = xe - mu * sd[e];
+    if (xprev) v += beta * (xe - xprev[e]);
+  }
+  xp[e] = v;
+  if (xsave) xsave[e] = xe;
 }
 
 void launch_ihs_candidate(int64_t d, int C, const double* x, const double* sd, double mu, double* xp, const int* active,
-                          hipStream_t s, const int* gate) {
+                          hipStream_t s, const int* gate, const double* xprev, double beta, double* xsave) {
   const int64_t total = d * C;
   hipLaunchKernelGGL(ihs_candidate_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, total, C, x, sd, mu, xp,
-                     active, gate);
+                     active, gate, xprev, beta, xsave);
   AES_LAUNCH_CHECK();
 }
 

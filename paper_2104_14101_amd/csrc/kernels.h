@@ -61,9 +61,11 @@ void launch_pcg_init(int64_t d, int C, const double* r, const double* rt, double
                      int* active, int* gate, int stop_rule, double stop_scale, double stop_sr,
                      double tol2, const double* x, int set_d0, hipStream_t s, const int* chol_flag = nullptr,
                      double* work = nullptr);
-// IHS: xp = x - mu s
+// IHS: xp = x - mu s; Polyak-IHS (xprev given): xp = (x - mu s) + beta (x - xprev), and x is
+// copied to xsave (the previous iterate for the next step)
 void launch_ihs_candidate(int64_t d, int C, const double* x, const double* sd, double mu, double* xp,
-                          const int* active, hipStream_t s, const int* gate = nullptr);
+                          const int* active, hipStream_t s, const int* gate = nullptr,
+                          const double* xprev = nullptr, double beta = 0.0, double* xsave = nullptr);
 void launch_ihs_finish(int64_t d, int C, double* x, double* g, double* sd, const double* xp,
                        const double* gp, const double* sp, double* scal, int* active, int* gate,
                        double thr, int force_reject, int adaptive, int at_cap, int stop_rule,

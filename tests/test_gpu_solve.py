@@ -79,6 +79,39 @@ def test_srht_reuse_trajectory_and_accuracy(small, method):
         aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], sketch="srht_reuse", precision="mixed")
 
 
+@pytest.mark.parametrize("kw", [dict(m_init=8), dict(m_init=512, adaptive=False)])
+def test_polyak_trajectory_and_accuracy(small, kw):
+    kw = dict(method="polyak", seed=1, tol=1e-10, max_iter=500, **kw)
+    x, info = aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], trace_cap=512, **kw)
+    xo, io = solvers.solve(small["A"], small["b"], small["nu"], small["lam"], solvers.Options(**kw))
+    assert info["status"] == "ok"
+    assert _traj_gpu(info) == _traj_cpu(io)
+    assert info["iterations"] == io.iterations and info["final_m"] == io.final_m
+    assert info["a_passes"] == io.a_passes
+    assert reference.rel_error(x.cpu().numpy(), small["xref"]) <= 1e-10
+    assert reference.rel_error(x.cpu().numpy(), xo) <= 1e-9
+
+
+@pytest.mark.parametrize("force", [(), (3,)])
+def test_polyak_iterates_match_the_oracle(small, force):
+    # five accepted heavy-ball steps (with a forced rejection at t = 3: the momentum restart)
+    kw = dict(method="polyak", m_init=64, seed=3, stop="fixed", max_iter=5, force_reject_at=force, tol=1e-10)
+    x, info = aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], trace_cap=64,
+                        **{**kw, "force_reject_at": force[0] if force else -1})
+    xo, io = solvers.solve(small["A"], small["b"], small["nu"], small["lam"], solvers.Options(**kw))
+    assert _traj_gpu(info) == _traj_cpu(io) and info["iterations"] == 5
+    assert reference.rel_error(x.cpu().numpy(), xo) <= 1e-10
+
+
+def test_polyak_several_rhs(small):
+    rng = np.random.default_rng(8)
+    Bm = small["A"].T @ rng.standard_normal((4096, 3))
+    X, info = aes.solve(small["dA"], to_dev(Bm), small["nu"], small["dlam"], method="polyak", m_init=512,
+                        adaptive=False, seed=2, tol=1e-10)
+    Xr = reference.reference_solution(small["A"], Bm, small["nu"], small["lam"])
+    assert info["status"] == "ok" and np.all(reference.rel_error(X.cpu().numpy(), Xr) <= 1e-10)
+
+
 @pytest.mark.parametrize("precision", ["mixed", "mixed_fp32"])
 def test_sjlt_mixed_precision(small, precision):
     x, info = aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], precision=precision, sketch="sjlt",
