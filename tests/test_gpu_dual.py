@@ -74,6 +74,17 @@ def test_dual_several_rhs(sketch, with_lam):
     assert torch.equal(out[:, :3], X) and bool((out[:, 3:] == 7.0).all())
 
 
+@pytest.mark.parametrize("precision", ["mixed", "mixed_fp32"])
+def test_dual_mixed_precision(precision):
+    # the dual solve in mixed precision (FP32 inner solves over B, FP64 refinement of w)
+    A, b, lam = _problem(48, 2000, 3, 3)
+    nu = 0.1
+    X, info = _dual(A, b, lam, nu, precision=precision, m_init=8, seed=1, tol=1e-11)
+    assert info["status"] == "ok", info
+    Xr = reference.reference_solution(A, b, nu, lam)
+    assert np.all(reference.rel_error(X.cpu().numpy(), Xr) <= 1e-10)
+
+
 def test_dual_wider_than_the_primal_limit():
     # d = 40000 > 32768 (the primal entry point's limit); the dual has n = 256 unknowns
     A, b, lam = _problem(256, 40000, 1, 7, decay=0.95)

@@ -113,6 +113,16 @@ def test_polyak_several_rhs(small):
 
 
 @pytest.mark.parametrize("precision", ["mixed", "mixed_fp32"])
+def test_polyak_mixed_precision(small, precision):
+    # FP32 inner heavy-ball solves inside the FP64 refinement, fixed m and adaptive
+    for kw in (dict(m_init=512, adaptive=False), dict(m_init=8)):
+        x, info = aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], method="polyak",
+                            precision=precision, seed=1, max_iter=500, **kw)
+        assert info["status"] == "ok", (kw, info)
+        assert reference.rel_error(x.cpu().numpy(), small["xref"]) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["mixed", "mixed_fp32"])
 def test_sjlt_mixed_precision(small, precision):
     x, info = aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], precision=precision, sketch="sjlt",
                         m_init=8, seed=1)
@@ -153,10 +163,10 @@ def test_wide_problem_two_product_path():
     P = synth.make_problem(12000, 8300, "geo:0.995", 1e-2, seed=17, backend="torch", device="cuda")
     Pn = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in P.items()}
     xr = reference.reference_solution(Pn["A"], Pn["b"], Pn["nu"], None, spectral=(Pn["V"], Pn["sigma"]))
-    for method in ("pcg", "cg"):
-        x, info = aes.solve(P["A"], P["b"], P["nu"], None, method=method, m_init=64, seed=3, tol=1e-10,
-                            max_iter=3000)
-        assert info["status"] == "ok", (method, info)
+    for method, sketch in (("pcg", "srht"), ("cg", "srht"), ("pcg", "srht_reuse"), ("polyak", "srht")):
+        x, info = aes.solve(P["A"], P["b"], P["nu"], None, method=method, sketch=sketch, m_init=64, seed=3,
+                            tol=1e-10, max_iter=3000)
+        assert info["status"] == "ok", (method, sketch, info)
         assert reference.rel_error(x.cpu().numpy(), xr) <= 1e-10
         assert info["a_passes"] >= info["iterations"]
 
