@@ -214,8 +214,9 @@ aes_status aes_solve_keep(aes_handle h, void* stream, int64_t n, int64_t d, int6
                           int64_t ldx, aes_info* info, aes_ctx* ctx);
 
 /*
- * aes_adjoint_solve -- solves H lam = g (H symmetric) by adaptive PCG starting from the
- * context's sketch size and factorisation (resketching only if the improvement test fails).
+ * aes_adjoint_solve -- solves H lam = g (H symmetric) by the forward solve's method (adaptive
+ * PCG, IHS or Polyak-IHS) starting from the context's sketch size and factorisation (resketching
+ * only if the improvement test fails).
  *   g    device, d x c (ld = c);   lam  device, d x c output (ld = c)
  */
 aes_status aes_adjoint_solve(aes_ctx ctx, void* stream, const double* g, double tol,

@@ -1262,7 +1262,7 @@ aes_status aes_solve_keep(aes_handle h, void* stream, int64_t n, int64_t d, int6
     return AES_ERR_INVALID_ARG;
   }
   if (o.method == AES_CG) {
-    h->err = "aes_solve_keep needs a sketched preconditioner (PCG or IHS)";
+    h->err = "aes_solve_keep needs a sketched preconditioner (PCG, IHS or Polyak-IHS)";
     return AES_ERR_INVALID_ARG;
   }
   auto c2 = std::make_unique<aes_ctx_s>();
