@@ -336,7 +336,8 @@ def variants_leg(aes, torch, A, b, nu, lam, w, P_np, args):
 def paper_leg(aes, torch, synth, n, d, nus, cross=False, cg_iters=20000):
     """The synthetic experiments of Sec. 5 (sigma_j = 0.995^j, Lambda = I, b = A^T y) at n x d over
     a sweep of nu, with the paper's comparison set: adaptive PCG and IHS from m = 1 (SRHT and
-    SJLT), PCG with the fixed size m = 2d, and unpreconditioned CG.  One timed solve each (the
+    SJLT), PCG with the fixed size m = 2d, and unpreconditioned CG; plus adaptive PCG with the
+    transform-reuse SRHT (a variant).  One timed solve each (the
     first solve of each problem is repeated untimed).  Error against the oracle's refined
     reference; with cross=True (sizes the host oracle cannot take) against a PCG solve at
     m = 2d to 1e-12 instead."""
@@ -353,6 +354,7 @@ def paper_leg(aes, torch, synth, n, d, nus, cross=False, cg_iters=20000):
     P_np = None if cross else to_numpy(P)
     runs = [("adaptive_pcg_srht", dict(method="pcg", sketch="srht", m_init=1)),
             ("adaptive_pcg_sjlt", dict(method="pcg", sketch="sjlt", m_init=1)),
+            ("adaptive_pcg_srht_reuse", dict(method="pcg", sketch="srht_reuse", m_init=1)),
             ("adaptive_ihs_srht", dict(method="ihs", sketch="srht", m_init=1)),
             ("adaptive_ihs_sjlt", dict(method="ihs", sketch="sjlt", m_init=1)),
             ("pcg_m2d_srht", dict(method="pcg", sketch="srht", m_init=2 * d, adaptive=False)),
