@@ -306,13 +306,16 @@ def test_batched_equals_singles():
         assert torch.equal(xs, x)
 
 
-def test_autograd_adjoint():
+# the adjoint solve runs the forward solve's method and sketch
+@pytest.mark.parametrize("opts", [dict(m_init=16), dict(m_init=16, sketch="srht_reuse"),
+                                  dict(method="polyak", m_init=512, adaptive=False)])
+def test_autograd_adjoint(opts):
     P = synth.make_problem(2048, 64, "pow:0.5", 1e-2, seed=31, with_xt=True)
     A, b, nu, xt = P["A"], P["b"], P["nu"], P["xt"]
     At = to_dev(A).requires_grad_(True)
     bt = to_dev(b).requires_grad_(True)
     ln = torch.tensor(np.log(nu), dtype=torch.float64, device="cuda", requires_grad=True)
-    x = aes.SketchSolve.apply(At, bt, ln, None, dict(m_init=16, seed=2, tol=1e-12))
+    x = aes.SketchSolve.apply(At, bt, ln, None, dict(seed=2, tol=1e-12, **opts))
     loss = 0.5 * torch.sum((x - to_dev(xt)) ** 2)
     loss.backward()
     xs = reference.reference_solution(A, b, nu)
