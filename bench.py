@@ -21,9 +21,13 @@ Extra legs (outside the timed region of the headline value):
   * --adjoint (or --all): forward + backward of the autograd Function on n = 131072, d = 1024
     (sigma_j = j^-1/2, nu = 1e-2), gradients validated against the dense oracle;
   * variants (skip with --no-variants): the headline workload solved with the Gaussian and
-    SJLT sketches, by adaptive IHS, and by the unpreconditioned CG baseline;
-  * --skip-main --paper / --paper-large: the synthetic nu-sweeps of the paper's numerical
-    section (n = 16384 or 131072, d = 7000, sigma_j = 0.995^j) with its comparison set.
+    SJLT sketches, with the transform-reuse SRHT (a variant), by adaptive IHS, by adaptive
+    Polyak-IHS, and by the unpreconditioned CG baseline;
+  * --skip-main --paper / --paper-large / --paper-e3: the synthetic nu-sweeps of the paper's
+    numerical section (n = 16384 or 131072, d = 7000; n = 524288, d = 14000; sigma_j = 0.995^j)
+    with its comparison set;
+  * --skip-main --dual: n < d through the dual problem (the OVA-Lung shape n = 1545, d = 10936,
+    c = 2, and n = 8192, d = 32768) next to the primal solve; --dual-wide: the dual solve alone.
 
 --hv-only runs just fused H.v launches and a calibration copy (for rocprofv3 counter runs);
 --sketch-only M runs just sketches (--sketch kind) of size M of the workload's A.
