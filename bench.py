@@ -27,7 +27,8 @@ Extra legs (outside the timed region of the headline value):
     numerical section (n = 16384 or 131072, d = 7000; n = 524288, d = 14000; sigma_j = 0.995^j)
     with its comparison set;
   * --skip-main --dual: n < d through the dual problem (the OVA-Lung shape n = 1545, d = 10936,
-    c = 2, and n = 8192, d = 32768) next to the primal solve; --dual-wide: the dual solve alone.
+    c = 2, and n = 8192, d = 32768) next to the primal solve; --dual-wide: the dual solve alone;
+    --dual-large: the dual solve at n = 16384, d = 131072 with a primal-residual check.
 
 --hv-only runs just fused H.v launches and a calibration copy (for rocprofv3 counter runs);
 --sketch-only M runs just sketches (--sketch kind) of size M of the workload's A.
@@ -217,6 +218,8 @@ def main():
                          "next to the primal solve")
     ap.add_argument("--dual-wide", action="store_true",
                     help="with --skip-main: only the dual solve at n=8192, d=32768, nu=1e-2 (kernel profiles)")
+    ap.add_argument("--dual-large", action="store_true",
+                    help="with --skip-main: the dual solve at n=16384, d=131072 (beyond the primal's d limit)")
     ap.add_argument("--paper-e3", action="store_true",
                     help="with --skip-main: the same at n=524288, d=14000 (A is 58.7 GB; nu = 1e-2 .. 1e-4; "
                          "CG capped at 2000 steps; errors against PCG at m = 2d to 1e-12)")
@@ -253,6 +256,8 @@ def main():
             out["dual_n8192_d32768"] = dual_leg(aes, torch, synth, 8192, 32768, (1e-1, 1e-2), ref="primal")
         if args.dual_wide:
             out["dual_n8192_d32768"] = dual_leg(aes, torch, synth, 8192, 32768, (1e-2,), ref="none", forms=("dual",))
+        if args.dual_large:
+            out["dual_n16384_d131072"] = dual_large_leg(aes, torch, synth)
         if args.batched or args.all:
             out["batched"] = batched_leg(aes, torch, synth)
         if args.adjoint or args.all:
@@ -426,6 +431,26 @@ def dual_leg(aes, torch, synth, n, d, nus, nrhs=1, ref="oracle", forms=("dual", 
             res["primal_over_dual"] = res["primal"]["s_per_solve"] / res["dual"]["s_per_solve"]
         out["nu"][f"{nu:g}"] = res
     return out
+
+
+def dual_large_leg(aes, torch, synth):
+    """The dual solve at n = 16384, d = 131072 (A and B = Lambda^{-1/2} A^T are 17 GB each), where
+    the primal path does not apply (d > 32768) and the host oracle is too slow: the check is the
+    relative primal residual ||b - A^T (A x) - nu^2 x|| / ||b||, formed with torch in FP64 after the
+    timed solves (a check only, outside the timed region)."""
+    n, d, nu = 16384, 131072, 1e-2
+    P = synth.make_wide_problem(n, d, "geo:0.995", nu, seed=0, backend="torch", device="cuda")
+    A, b = P["A"], P["b"]
+    torch.cuda.empty_cache()
+    print(json.dumps({"dual_large": [n, d, "generated"]}), file=sys.stderr, flush=True)
+    opts = dict(method="pcg", sketch="srht", m_init=1, seed=1, tol=1e-10)
+    x, infos, sec = timed_solves(aes, torch, A, b, nu, None, opts, 2, 1, fn=aes.solve_dual)
+    r = b - A.T @ (A @ x) - nu * nu * x
+    res = float(torch.linalg.norm(r) / torch.linalg.norm(b))
+    i = infos[-1]
+    return {"n": n, "d": d, "nu": nu, "sigma": "0.995^j", "s_per_solve": sec, "rel_residual": res,
+            "status": i["status"], "iterations": i["iterations"], "final_m": i["final_m"],
+            "a_passes": i["a_passes"], "time_sketch_ms": i["time_sketch_ms"]}
 
 
 def mixed_leg(aes, torch, synth):
