@@ -73,3 +73,29 @@ def test_product_path_does_not_import_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
+
+
+def test_binding_enums_match_the_header():
+    # the Python names map to the values include/aes.h gives the enumerators
+    import re
+
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "aes.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    vals = {k: int(v) for k, v in re.findall(r"\b(AES_[A-Z0-9_]+)\s*=\s*(\d+)", hdr)}
+    expect = {
+        "METHODS": {"pcg": "AES_PCG", "ihs": "AES_IHS", "cg": "AES_CG", "polyak": "AES_POLYAK"},
+        "SKETCHES": {"srht": "AES_SRHT", "gauss": "AES_GAUSS", "sjlt": "AES_SJLT", "srht_reuse": "AES_SRHT_REUSE"},
+        "PRECISIONS": {"fp64": "AES_FP64", "mixed": "AES_MIXED", "mixed_fp32": "AES_MIXED_FP32"},
+        "STOPS": {"xrel": "AES_STOP_XREL", "dtilde_rel": "AES_STOP_DTILDE_REL", "fixed": "AES_STOP_FIXED",
+                  "remark": "AES_STOP_REMARK"},
+    }
+    for table, names in expect.items():
+        got = getattr(B, table)
+        assert set(got) == set(names), table
+        for py, c in names.items():
+            assert got[py] == vals[c], (table, py)
+    # every enumerator of those four enums is reachable from Python
+    prefixes = ("AES_PCG", "AES_IHS", "AES_CG", "AES_POLYAK", "AES_SRHT", "AES_GAUSS", "AES_SJLT", "AES_FP64",
+                "AES_MIXED", "AES_STOP_")
+    declared = {k for k in vals if k.startswith(prefixes)}
+    assert declared == {c for names in expect.values() for c in names.values()}
