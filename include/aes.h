@@ -143,7 +143,8 @@ void aes_default_options(aes_options* o);
 
 /*
  * aes_solve -- adaptive PCG (Algorithm 2) or adaptive IHS (Algorithm 1 with the IHS update,
- * step mu = 1 - rho of Theorem "rate IHS") for H x = b with the sketched preconditioner
+ * step mu = 1 - rho of Theorem "rate IHS"; AES_POLYAK and AES_CG select the heavy-ball variant
+ * and the unpreconditioned baseline, see aes_method) for H x = b with the sketched preconditioner
  * H_S = (SA)^T SA + nu^2 Lambda, factorised as in Sec. 4.1 (Cholesky of H_S for m >= d,
  * Woodbury form with the Cholesky of W_S for m < d).  When the improvement test of the
  * algorithm fails, m doubles, a fresh S is drawn and the method restarts at x_t.
