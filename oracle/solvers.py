@@ -80,7 +80,7 @@ class Options:
     adaptive: bool = True
     force_reject_at: tuple = ()  # values of t at which the first candidate step is rejected
     x0: object = None
-    keep_iterates: bool = False  # store the committed x in the trace (tests)
+    keep_iterates: bool = False  # store each candidate (xp) and committed x in the trace (tests)
 
 
 @dataclass
@@ -274,6 +274,8 @@ def adaptive_pcg(A, b, nu, lam=None, opts=None):
             forced.add(t)
             fail = True
         info.trace.append(dict(t=t, m=m, k=k, log_ratio=lr.copy(), threshold=thr, accept=not fail or not o.adaptive or m >= m_cap))
+        if o.keep_iterates:
+            info.trace[-1]["xp"] = Xp.copy()
         if fail and o.adaptive and m < m_cap:
             I = t
             m = min(2 * m, m_cap)
@@ -380,6 +382,8 @@ def adaptive_ihs(A, b, nu, lam=None, opts=None):
             forced.add(t)
             fail = True
         info.trace.append(dict(t=t, m=m, k=k, log_ratio=lr.copy(), threshold=thr, accept=not fail or not o.adaptive or m >= m_cap))
+        if o.keep_iterates:
+            info.trace[-1]["xp"] = Xp.copy()
         if fail and o.adaptive and m < m_cap:
             I = t
             m = min(2 * m, m_cap)

@@ -117,8 +117,6 @@ def small():
 @pytest.mark.parametrize("method", ["pcg", "ihs", "polyak"])
 @pytest.mark.parametrize("kind", ["srht", "gauss", "sjlt", "srht_reuse"])
 def test_solution_accuracy(small, method, kind):
-    if kind not in ("srht", "srht_reuse") and method != "pcg":
-        pytest.skip("covered by the PCG case of the same sketch; keeps the CPU suite short")
     o = solvers.Options(method=method, sketch=kind, m_init=8, tol=1e-10, seed=1)
     x, info = solvers.solve(small["A"], small["b"], small["nu"], small["lam"], o)
     assert info.status == "ok"
