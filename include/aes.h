@@ -244,6 +244,17 @@ void aes_ctx_free(aes_ctx ctx);
 aes_status aes_hv(aes_handle h, void* stream, int64_t n, int64_t d, const double* A, int64_t lda,
                   double nu, const double* lambda, const double* p, double* q, double* pHp);
 
+/* aes_hv without any device allocation, for callers that cannot allocate (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same kernels and results as
+ * aes_hv (bit-identical), with the per-workgroup partials and the pHp state in a static
+ * device array of 33.7 MB that the library holds on every device it runs on until the process
+ * ends (its address is resolved in aes_create).  Takes 1 <= d <= 8192 (AES_ERR_INVALID_ARG
+ * otherwise).  Every call on a device shares that array and leaves its contents behind: calls
+ * that overlap on one device (streams without mutual ordering) race and give wrong results.
+ * Arguments as aes_hv; asynchronous on `stream`. */
+aes_status aes_hv_noalloc(aes_handle h, void* stream, int64_t n, int64_t d, const double* A, int64_t lda,
+                          double nu, const double* lambda, const double* p, double* q, double* pHp);
+
 /* Q = A^T (A P) + nu^2 Lambda P for c right-hand sides (P, Q device d x c, ld = c, c a power of
  * two <= 32) -- the per-step product of the matrix-variable solves (Sec. 5).  precision
  * AES_FP64: FP64 MFMA; AES_MIXED / AES_MIXED_FP32: A rounded to FP32 and FP32 MFMA products

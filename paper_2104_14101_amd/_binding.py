@@ -69,6 +69,8 @@ _PROTOS = {
     "aes_ctx_free": (None, [c_void_p]),
     "aes_hv": (c_int, [c_void_p, c_void_p, c_int64, c_int64, c_void_p, c_int64, c_double, c_void_p, c_void_p, c_void_p,
                        c_void_p]),
+    "aes_hv_noalloc": (c_int, [c_void_p, c_void_p, c_int64, c_int64, c_void_p, c_int64, c_double, c_void_p, c_void_p,
+                               c_void_p, c_void_p]),
     "aes_hv_multi": (c_int, [c_void_p, c_void_p, c_int64, c_int64, c_int64, c_void_p, c_int64, c_double, c_void_p,
                              c_void_p, c_void_p, c_int]),
     "aes_sketch": (c_int, [c_void_p, c_void_p, c_int, c_int64, c_int64, c_void_p, c_int64, c_int64, c_uint64, c_int32,

@@ -1045,6 +1045,8 @@ aes_status aes_create(aes_handle* out, int device) {
     AES_HIP(hipGetDeviceProperties(&prop, device));
     h->num_cu = prop.multiProcessorCount;
     AES_HIP(hipHostMalloc((void**)&h->pinned, 64 * sizeof(double), hipHostMallocDefault));
+    // device address of the allocation-free entry point's static workspace on this device
+    AES_HIP(noalloc_init(device));
   });
   if (st != AES_OK) return st;
   *out = h.release();
@@ -1391,6 +1393,17 @@ aes_status aes_hv(aes_handle h, void* stream, int64_t n, int64_t d, const double
       launch_pcg_candidate(d, 1, spart, nwg, lambda, nu * nu, p, p, p, q, dummy, dummy + d, scal, act, s);
       AES_HIP(hipMemcpyAsync(pHp, scal + 5, sizeof(double), hipMemcpyDeviceToDevice, s));
     }
+  });
+}
+
+aes_status aes_hv_noalloc(aes_handle h, void* stream, int64_t n, int64_t d, const double* A, int64_t lda, double nu,
+                          const double* lambda, const double* p, double* q, double* pHp) {
+  if (!h) return AES_ERR_INVALID_ARG;
+  return guard(h, [&] {
+    if (n < 1 || d < 1 || lda < d || !A || !p || !q || !(nu >= 0)) throw StatusError(AES_ERR_INVALID_ARG, "bad arguments");
+    if (d > kMaxFusedD) throw StatusError(AES_ERR_INVALID_ARG, "aes_hv_noalloc takes d <= 8192");
+    set_device(h);
+    hv_noalloc(h->device, h->num_cu, (hipStream_t)stream, n, d, A, lda, nu, lambda, p, q, pHp);
   });
 }
 

@@ -202,4 +202,10 @@ void cholinv(double* G, int64_t np, double* Linv, double* tmp, int* flag, bool k
 void launch_grad_rank2(const double* A, int64_t n, int64_t d, int64_t lda, const double* y1,
                        const double* y2, double* dA, int64_t ldda, hipStream_t s);
 
+// Allocation-free fused H.v (noalloc.hip): its scratch is a static device array whose address
+// on each device is resolved once by noalloc_init (with that device current).
+hipError_t noalloc_init(int device);
+void hv_noalloc(int device, int num_cu, hipStream_t s, int64_t n, int64_t d, const double* A, int64_t lda, double nu,
+                const double* lambda, const double* p, double* q, double* pHp);
+
 }  // namespace aes
