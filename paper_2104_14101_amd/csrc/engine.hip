@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <initializer_list>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -66,6 +67,21 @@ struct aes_handle_s {
     }
     bufs[name] = {p, alloc};
     return static_cast<T*>(p);
+  }
+  // Frees every pool buffer whose name is not listed (the stream work that used them must be
+  // complete).
+  void release_except(std::initializer_list<const char*> keep) {
+    std::lock_guard<std::mutex> lock(mu);
+    for (auto it = bufs.begin(); it != bufs.end();) {
+      bool kept = false;
+      for (const char* k : keep) kept = kept || it->first == k;
+      if (kept) {
+        ++it;
+      } else {
+        AES_HIP(hipFree(it->second.first));
+        it = bufs.erase(it);
+      }
+    }
   }
   void set_err(const std::string& e) {
     std::lock_guard<std::mutex> lock(mu);
@@ -1301,6 +1317,18 @@ aes_status aes_solve_keep(aes_handle h, void* stream, int64_t n, int64_t d, int6
     AES_HIP(hipStreamSynchronize((hipStream_t)stream));
   });
   delete keep;
+  if (st != AES_OK) {
+    aes_destroy(c2->h);
+    return st;
+  }
+  // Between the forward and the adjoint solve the context holds only what the adjoint reuses:
+  // the sketch (Woodbury branch), the inverse factor and its transpose, x* and Lambda.  The
+  // rest of the pool (the transform scratch, Gram partials, vectors) is released now and
+  // re-allocated by the adjoint solve as it needs it.
+  st = guard(h, [&] {
+    set_device(c2->h);
+    c2->h->release_except({"s.SA", "s.SAT", "s.Linv", "s.LinvT", "ctx_xstar", "ctx_lambda"});
+  });
   if (st != AES_OK) {
     aes_destroy(c2->h);
     return st;
