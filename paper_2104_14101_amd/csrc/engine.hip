@@ -5,11 +5,14 @@
 // Control: every device step is enqueued on the caller's stream; the host reads back one
 // small block of flags per attempted step (accepted / rejected / stopped), because the
 // accept-or-resketch decision of the algorithms is data dependent.
+#include <dlfcn.h>
+
 #include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <functional>
 #include <initializer_list>
@@ -23,6 +26,7 @@
 #include "aes.h"
 #include "common.h"
 #include "kernels.h"
+#include "batch.h"
 
 using namespace aes;
 
@@ -173,8 +177,12 @@ double remark_m_delta(int64_t n, int64_t d) {
 // ---------------------------------------------------------------------------------------
 class Solver {
  public:
-  Solver(aes_handle h, hipStream_t s, const ProblemDesc& P, const aes_options& o, double tol, const std::string& ns)
-      : h_(h), s_(s), P_(P), o_(o), tol_(tol), ns_(ns) {
+  // ns: namespace of the problem's own buffers in the handle pool; sns: namespace of the
+  // scratch that only lives within one eager phase (sketch, factorisation, an eager product),
+  // shared by the problems of a batch (their eager work is ordered on one stream)
+  Solver(aes_handle h, hipStream_t s, const ProblemDesc& P, const aes_options& o, double tol, const std::string& ns,
+         const std::string& sns = std::string())
+      : h_(h), s_(s), P_(P), o_(o), tol_(tol), ns_(ns), sns_(sns.empty() ? ns : sns) {
     n_ = P.n;
     d_ = P.d;
     c_ = P.c;
@@ -205,6 +213,10 @@ class Solver {
   T* B(const char* name, size_t count) {
     return h_->buf<T>(ns_ + name, count);
   }
+  template <typename T>
+  T* S(const char* name, size_t count) {
+    return h_->buf<T>(sns_ + name, count);
+  }
 
   void setup_common() {
     const int64_t dc = d_ * C_;
@@ -229,23 +241,16 @@ class Solver {
     vw_ = B<double>("vec_work", vec_work_elems());
     active_ = B<int>("active", C_);
     nwg_ = hv_num_blocks(h_->num_cu, n_);
-    if (fused_) {
-      part_ = B<double>("part", (size_t)nwg_ * d_);
-      spart_ = B<double>("spart", nwg_);
-    } else {
+    if (!fused_) {
       // row splits of A^T Z: about four workgroups (of 128 columns) per CU in flight
       const int64_t col_tiles = ceil_div(d_, 128);
       const int64_t want = std::max<int64_t>(1, 4 * (int64_t)h_->num_cu / col_tiles);
       const int64_t split_rows = round_up(std::max<int64_t>(512, ceil_div(n_, want)), 32);
       msplit_ = (int)ceil_div(n_, split_rows);
       msplit_rows_ = split_rows;
-      part_ = B<double>("part", (size_t)msplit_ * d_ * C_);
-      Z_ = B<double>("Z", (size_t)n_ * C_);
-      if (C_ == 1) {
-        atz_nrb_ = atz_blocks(h_->num_cu, n_, d_, &atz_rows_);
-        atz_part_ = B<double>("atz_part", (size_t)atz_nrb_ * d_);
-      }
+      if (C_ == 1) atz_nrb_ = atz_blocks(h_->num_cu, n_, d_, &atz_rows_);
     }
+    hv_scratch();
     AES_HIP(hipMemsetAsync(scal_, 0, (8 * C_ + 8) * sizeof(double), s_));
     launch_copy_cols(d_, C_, P_.b, P_.ldb, (int)c_, Bv_, C_, s_);
     std::vector<int> act(C_, 0);
@@ -255,11 +260,7 @@ class Solver {
       // the FP32 copy feeds the inner products and every sketch of the mixed modes
       A32_ = B<float>("A32", (size_t)n_ * d_);
       launch_cast<float>(n_, d_, P_.A, P_.lda, A32_, s_);
-      if (!fused_) {
-        V32_ = B<float>("V32", (size_t)d_ * C_);
-        Z32_ = B<float>("Z32", (size_t)n_ * C_);
-        part32_ = B<float>("part32", (size_t)msplit_ * d_ * C_);
-      }
+      hv_scratch();
     }
     stop_scale_ = nu2_ * min_lambda() * tol_ * tol_;
     if (o_.stop == AES_STOP_REMARK) stop_scale_ = tol_ / (remark_m_delta(n_, d_) + 1.0);
@@ -286,9 +287,28 @@ class Solver {
     return mn;
   }
 
+  // Scratch of the eager H.v, fetched from the pool at every use: within a batch it is shared by
+  // all problems and may have grown (and moved) since this problem last used it.
+  void hv_scratch() {
+    if (fused_) {
+      part_ = S<double>("part", (size_t)nwg_ * d_);
+      spart_ = S<double>("spart", nwg_);
+      return;
+    }
+    part_ = S<double>("part", (size_t)msplit_ * d_ * C_);
+    Z_ = S<double>("Z", (size_t)n_ * C_);
+    if (C_ == 1) atz_part_ = S<double>("atz_part", (size_t)atz_nrb_ * d_);
+    if (mixed_) {
+      V32_ = S<float>("V32", (size_t)d_ * C_);
+      Z32_ = S<float>("Z32", (size_t)n_ * C_);
+      part32_ = S<float>("part32", (size_t)msplit_ * d_ * C_);
+    }
+  }
+
   // out = sgn * (H v) + bsgn * b    (H = A^T A + nu^2 Lambda); A in FP64 or (inner) FP32.
   void hv(const double* v, double* out, double sgn, const double* bb, double bsgn, bool use32,
           const int* gate = nullptr) {
+    hv_scratch();
     if (fused_) {
       const bool prof = o_.profile && !use32;
       if (prof) AES_HIP(hipEventRecord(h_->event(2 * n_events_), s_));
@@ -357,80 +377,81 @@ class Solver {
     const bool f32 = mixed_ && sketch32_ && low;
     woodbury_ = m_ < d_;
     if (bf) {
-      SA16_ = B<__hip_bfloat16>("SA16", (size_t)m_ * d_);
+      SA16_ = S<__hip_bfloat16>("SA16", (size_t)m_ * d_);
     } else if (f32) {
-      SA32_ = B<float>("SA32", (size_t)m_ * d_);
+      SA32_ = S<float>("SA32", (size_t)m_ * d_);
     } else {
-      SA_ = B<double>("SA", (size_t)m_ * d_);
+      // the sketch itself is kept for the Woodbury form's products; for m >= d only its Gram is
+      SA_ = woodbury_ ? B<double>("SA", (size_t)m_ * d_) : S<double>("SAg", (size_t)m_ * d_);
     }
     if (o_.sketch == AES_SRHT_REUSE) {
       // transform-reuse variant: Y = (H / sqrt(n')) E_0 A_pad once per solve (the SRHT of
       // index 0 at m = n', every row kept in order), then rows R_k of Y scaled by sqrt(n'/m)
       SelectScratch sc;
-      sc.keys = B<uint64_t>("sel_keys", npad_);
-      sc.pos = B<int32_t>("sel_pos", npad_);
-      sc.hist = B<uint32_t>("sel_hist", 256 * 8);
-      sc.state = B<uint64_t>("sel_state", 4);
-      sc.blk = B<uint32_t>("sel_blk", 2 * select_blocks(npad_));
+      sc.keys = S<uint64_t>("sel_keys", npad_);
+      sc.pos = S<int32_t>("sel_pos", npad_);
+      sc.hist = S<uint32_t>("sel_hist", 256 * 8);
+      sc.state = S<uint64_t>("sel_state", 4);
+      sc.blk = S<uint32_t>("sel_blk", 2 * select_blocks(npad_));
       if (!yr_ready_) {
-        double* eps = B<double>("eps", n_);
+        double* eps = S<double>("eps", n_);
         launch_signs(o_.seed, o_.problem, 0, n_, eps, s_);
         launch_srht_select(o_.seed, o_.problem, 0, npad_, npad_, sc, s_);
         yr_ = B<double>("Yreuse", (size_t)npad_ * d_);
         launch_srht_apply<double, double, double>(P_.A, n_, d_, P_.lda, eps, npad_, sc.pos, npad_,
-                                                  B<double>("Y", srht_scratch_elems(npad_, d_)), yr_, d_,
-                                                  B<int32_t>("need", 512), s_);
+                                                  S<double>("Y", srht_scratch_elems(npad_, d_)), yr_, d_,
+                                                  S<int32_t>("need", 512), s_);
         yr_ready_ = true;
       }
       launch_srht_select(o_.seed, o_.problem, k_, npad_, m_, sc, s_);
       launch_gather_rows(npad_, d_, yr_, sc.pos, std::sqrt((double)npad_ / (double)m_), SA_, d_, s_);
     } else if (o_.sketch == AES_SRHT) {
-      double* eps = B<double>("eps", n_);
+      double* eps = S<double>("eps", n_);
       launch_signs(o_.seed, o_.problem, k_, n_, eps, s_);
       SelectScratch sc;
-      sc.keys = B<uint64_t>("sel_keys", npad_);
-      sc.pos = B<int32_t>("sel_pos", npad_);
-      sc.hist = B<uint32_t>("sel_hist", 256 * 8);
-      sc.state = B<uint64_t>("sel_state", 4);
-      sc.blk = B<uint32_t>("sel_blk", 2 * select_blocks(npad_));
+      sc.keys = S<uint64_t>("sel_keys", npad_);
+      sc.pos = S<int32_t>("sel_pos", npad_);
+      sc.hist = S<uint32_t>("sel_hist", 256 * 8);
+      sc.state = S<uint64_t>("sel_state", 4);
+      sc.blk = S<uint32_t>("sel_blk", 2 * select_blocks(npad_));
       launch_srht_select(o_.seed, o_.problem, k_, npad_, m_, sc, s_);
       if (bf) {
-        float* Y = B<float>("Y32", srht_scratch_elems(npad_, d_));
+        float* Y = S<float>("Y32", srht_scratch_elems(npad_, d_));
         launch_srht_apply<float, float, __hip_bfloat16>(A32_, n_, d_, d_, eps, npad_, sc.pos, m_, Y, SA16_, d_,
-                                                        B<int32_t>("need", 512), s_);
+                                                        S<int32_t>("need", 512), s_);
       } else if (f32) {
-        float* Y = B<float>("Y32", srht_scratch_elems(npad_, d_));
+        float* Y = S<float>("Y32", srht_scratch_elems(npad_, d_));
         launch_srht_apply<float, float, float>(A32_, n_, d_, d_, eps, npad_, sc.pos, m_, Y, SA32_, d_,
-                                               B<int32_t>("need", 512), s_);
+                                               S<int32_t>("need", 512), s_);
       } else {
-        double* Y = B<double>("Y", srht_scratch_elems(npad_, d_));
+        double* Y = S<double>("Y", srht_scratch_elems(npad_, d_));
         launch_srht_apply<double, double, double>(P_.A, n_, d_, P_.lda, eps, npad_, sc.pos, m_, Y, SA_, d_,
-                                                  B<int32_t>("need", 512), s_);
+                                                  S<int32_t>("need", 512), s_);
       }
     } else if (o_.sketch == AES_SJLT) {
       const SjltPlan sp = sjlt_plan(n_, d_, m_, (bf || f32) ? sizeof(float) : sizeof(double));
       SjltScratch sc;
-      sc.code = B<int32_t>("sj_code", n_);
-      sc.cnt = B<int32_t>("sj_cnt", sp.count_elems);
-      sc.csum = B<int32_t>("sj_csum", sp.csum_elems);
-      sc.perm = B<int32_t>("sj_perm", n_);
+      sc.code = S<int32_t>("sj_code", n_);
+      sc.cnt = S<int32_t>("sj_cnt", sp.count_elems);
+      sc.csum = S<int32_t>("sj_csum", sp.csum_elems);
+      sc.perm = S<int32_t>("sj_perm", n_);
       const size_t part = sp.Q > 1 ? (size_t)m_ * sp.Q * d_ : 0;
       if (bf) {
-        sc.part = part ? B<float>("sj_part32", part) : nullptr;
+        sc.part = part ? S<float>("sj_part32", part) : nullptr;
         launch_sjlt<float, __hip_bfloat16>(sp, A32_, n_, d_, d_, m_, o_.seed, o_.problem, k_, SA16_, sc, s_);
       } else if (f32) {
-        sc.part = part ? B<float>("sj_part32", part) : nullptr;
+        sc.part = part ? S<float>("sj_part32", part) : nullptr;
         launch_sjlt<float, float>(sp, A32_, n_, d_, d_, m_, o_.seed, o_.problem, k_, SA32_, sc, s_);
       } else {
-        sc.part = part ? B<double>("sj_part", part) : nullptr;
+        sc.part = part ? S<double>("sj_part", part) : nullptr;
         launch_sjlt<double, double>(sp, P_.A, n_, d_, P_.lda, m_, o_.seed, o_.problem, k_, SA_, sc, s_);
       }
     } else {
       const GaussPlan gp = gauss_plan(h_->num_cu, n_, d_, m_);
-      launch_gauss_sketch(gp, P_.A, n_, d_, P_.lda, m_, o_.seed, o_.problem, k_, SA_, B<double>("gauss_gt", gp.gt_elems),
-                          gp.part_elems ? B<double>("gauss_part", gp.part_elems) : nullptr, s_);
+      launch_gauss_sketch(gp, P_.A, n_, d_, P_.lda, m_, o_.seed, o_.problem, k_, SA_, S<double>("gauss_gt", gp.gt_elems),
+                          gp.part_elems ? S<double>("gauss_part", gp.part_elems) : nullptr, s_);
     }
-    int* flag = B<int>("chol_flag", 1);
+    int* flag = B<int>("chol_flag", 1);  // read by the problem's next initialisation
     AES_HIP(hipMemsetAsync(flag, 0, sizeof(int), s_));
     factor_from_sa(bf ? 1 : (f32 ? 2 : 0), flag);
     // no wait here: the initialisation that follows copies the failure flag into the flag
@@ -445,29 +466,29 @@ class Solver {
     const bool bf = sk == 1;
     if (!woodbury_) {
       fp_ = round_up(d_, 64);
-      double* G = B<double>("G", (size_t)fp_ * fp_);
+      double* G = S<double>("G", (size_t)fp_ * fp_);
       if (sk == 2) {
         // FP32 sketch, FP64 Gram: an FP32-accumulated Gram carries errors ~ u32 ||SA||^2,
         // above nu^2 Lambda once nu is small, and would not stay positive definite.
-        SA_ = B<double>("SA", (size_t)m_ * d_);
+        SA_ = S<double>("SAg", (size_t)m_ * d_);
         widen_f32(m_ * d_, SA32_, SA_, s_);
         const int splits = gram_splits(h_->num_cu, m_, d_, true);
-        double* part = B<double>("gram_part", (size_t)splits * fp_ * fp_);
+        double* part = S<double>("gram_part", (size_t)splits * fp_ * fp_);
         gram_tn(m_, d_, SA_, d_, nu2_, lam_, part, splits, G, fp_, s_);
       } else if (bf) {
         const int splits = gram_splits(h_->num_cu, m_, d_, false);
-        float* part = B<float>("gram_part32", (size_t)splits * fp_ * fp_);
+        float* part = S<float>("gram_part32", (size_t)splits * fp_ * fp_);
         gram_tn_bf16(m_, d_, SA16_, d_, nu2_, lam_, part, splits, G, fp_, s_);
       } else {
         const int splits = gram_splits(h_->num_cu, m_, d_, true);
-        double* part = B<double>("gram_part", (size_t)splits * fp_ * fp_);
+        double* part = S<double>("gram_part", (size_t)splits * fp_ * fp_);
         gram_tn(m_, d_, SA_, d_, nu2_, lam_, part, splits, G, fp_, s_);
       }
       factor_and_invert(G, fp_, flag);
     } else {
       fp_ = round_up(m_, 64);
-      double* W = B<double>("G", (size_t)fp_ * fp_);
-      double* scaled = B<double>("sa_scaled", (size_t)m_ * d_);
+      double* W = S<double>("G", (size_t)fp_ * fp_);
+      double* scaled = S<double>("sa_scaled", (size_t)m_ * d_);
       if (bf) {
         SA_ = B<double>("SA", (size_t)m_ * d_);
         gram_nt_bf16(m_, d_, SA16_, d_, nu2_, invlam_, SA_, scaled, W, fp_, s_);
@@ -487,7 +508,7 @@ class Solver {
   void factor_and_invert(double* G, int64_t np, int* flag) {
     Linv_ = B<double>("Linv", (size_t)np * np);
     LinvT_ = B<double>("LinvT", (size_t)np * np);
-    double* tmp = B<double>("cholinv_tmp", cholinv_tmp_size(np));
+    double* tmp = S<double>("cholinv_tmp", cholinv_tmp_size(np));
     cholinv(G, np, Linv_, tmp, flag, false, s_);
     launch_transpose(np, np, Linv_, np, LinvT_, np, s_);
   }
@@ -498,30 +519,30 @@ class Solver {
       launch_copy_cols(d_, C_, z, C_, C_, v, C_, s_, gate);
       return;
     }
-    double* t1 = B<double>("ap_t1", (size_t)std::max(m_, d_) * C_);
+    double* t1 = S<double>("ap_t1", (size_t)std::max(m_, d_) * C_);
     if (!woodbury_) {
       if (C_ >= 8) {
         // split-K skinny GEMMs over the padded factor (zero rows/columns beyond d)
         const int64_t np = fp_;
-        int S = 1;
-        while (S < 16 && np / (2 * S) >= 128 && (np / (2 * S)) % 64 == 0) S *= 2;
-        const int64_t Ks = np / S;
-        double* zp = B<double>("ap_zp", (size_t)np * C_);
-        double* tp = B<double>("ap_tp", (size_t)np * C_);
-        double* part = B<double>("ap_part", (size_t)S * np * C_);
+        int ns = 1;
+        while (ns < 16 && np / (2 * ns) >= 128 && (np / (2 * ns)) % 64 == 0) ns *= 2;
+        const int64_t Ks = np / ns;
+        double* zp = S<double>("ap_zp", (size_t)np * C_);
+        double* tp = S<double>("ap_tp", (size_t)np * C_);
+        double* part = S<double>("ap_part", (size_t)ns * np * C_);
         if (np > d_) launch_fill(zp + d_ * C_, (np - d_) * C_, 0.0, s_);
         AES_HIP(hipMemcpyAsync(zp, z, d_ * C_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
-        gemm_f64(false, false, np, C_, Ks, 1.0, Linv_, np, Ks, zp, C_, Ks * C_, 0.0, part, C_, np * C_, S, 0, s_, 1, Ks);
-        launch_sum_parts(np * C_, S, np * C_, part, tp, s_);
-        gemm_f64(false, false, np, C_, Ks, 1.0, LinvT_, np, Ks, tp, C_, Ks * C_, 0.0, part, C_, np * C_, S, 0, s_, 2, Ks);
-        launch_sum_parts(d_ * C_, S, np * C_, part, v, s_);
+        gemm_f64(false, false, np, C_, Ks, 1.0, Linv_, np, Ks, zp, C_, Ks * C_, 0.0, part, C_, np * C_, ns, 0, s_, 1, Ks);
+        launch_sum_parts(np * C_, ns, np * C_, part, tp, s_);
+        gemm_f64(false, false, np, C_, Ks, 1.0, LinvT_, np, Ks, tp, C_, Ks * C_, 0.0, part, C_, np * C_, ns, 0, s_, 2, Ks);
+        launch_sum_parts(d_ * C_, ns, np * C_, part, v, s_);
       } else {
         launch_rowdot(d_, d_, Linv_, fp_, 1, z, C_, nullptr, 1.0, nullptr, nullptr, 1.0, t1, s_, gate);
         launch_rowdot(d_, d_, LinvT_, fp_, 2, t1, C_, nullptr, 1.0, nullptr, nullptr, 1.0, v, s_, gate);
       }
     } else {
-      double* u = B<double>("ap_u", (size_t)m_ * C_);
-      double* w = B<double>("ap_w", (size_t)m_ * C_);
+      double* u = S<double>("ap_u", (size_t)m_ * C_);
+      double* w = S<double>("ap_w", (size_t)m_ * C_);
       launch_rowdot(m_, d_, SA_, d_, 0, z, C_, invlam_, 1.0, nullptr, nullptr, 1.0, u, s_, gate);
       launch_rowdot(m_, m_, Linv_, fp_, 1, u, C_, nullptr, 1.0, nullptr, nullptr, 1.0, t1, s_, gate);
       launch_rowdot(m_, m_, LinvT_, fp_, 2, t1, C_, nullptr, 1.0, nullptr, nullptr, 1.0, w, s_, gate);
@@ -595,7 +616,7 @@ class Solver {
     // initial residual / gradient
     if (ihs) {
       if (x_is_zero)
-        launch_hv_colsum(part_, 0, d_, C_, x, lam_, 0.0, 0.0, rhs, -1.0, R_, s_);  // g = -b
+        launch_hv_colsum(nullptr, 0, d_, C_, x, lam_, 0.0, 0.0, rhs, -1.0, R_, s_);  // g = -b (no partials)
       else
         hv(x, R_, 1.0, rhs, -1.0, use32);  // g = H x - b
       apply(R_, Pv_);
@@ -926,6 +947,371 @@ class Solver {
   }
   void set_pinned(double* p) { pinned_ = p; }
 
+  // ---- batch mode ----------------------------------------------------------------------
+  // The steps of the adaptive loop run in the grouped kernels of a BatchEngine (one launch
+  // sequence for all problems of a batch); this solver keeps the problem's control: the
+  // (re)initialisations, resizes and restarts (Algorithm 2 / Algorithm 1), the refinement
+  // sweeps of the mixed modes, the counters and the trace.
+  enum BState { kBStep = 0, kBRefine = 1, kBDone = 2 };
+
+  void batch_begin() {
+    setup_common();
+    // fixed addresses for the grouped step: the inverse factors at their largest padded size
+    // (both branches: round_up(min(m, d), 64) <= round_up(d, 64)), the Woodbury operands at
+    // d x d (m < d there), the products' intermediates
+    const int64_t npm = round_up(d_, 64);
+    (void)B<double>("Linv", (size_t)npm * npm);
+    (void)B<double>("LinvT", (size_t)npm * npm);
+    (void)B<double>("SA", (size_t)d_ * d_);
+    (void)B<double>("SAT", (size_t)d_ * d_);
+    bu_ = B<double>("bap_u", (size_t)d_ * C_);
+    bt1_ = B<double>("bap_t1", (size_t)d_ * C_);
+    bw_ = B<double>("bap_w", (size_t)d_ * C_);
+    gate_ = B<int>("gate", 1);
+    bihs_ = o_.method == AES_IHS || o_.method == AES_POLYAK;
+    bpolyak_ = o_.method == AES_POLYAK;
+    const double sr = std::sqrt(o_.rho);
+    if (bihs_) {
+      blphi_ = std::log(o_.rho);
+      blc_ = std::log((1.0 + sr) / (1.0 - sr));
+      bmu_ = 1.0 - o_.rho;
+      if (bpolyak_) {
+        const double q = std::sqrt(1.0 - o_.rho);
+        bmu_ = 2.0 * (1.0 - o_.rho) / (1.0 + q);
+        bbeta_ = (1.0 - q) / (1.0 + q);
+      }
+    } else {
+      const double q = std::sqrt(1.0 - o_.rho);
+      blphi_ = std::log((1.0 - q) / (1.0 + q));
+      blc_ = std::log(4.0 * (1.0 + sr) / (1.0 - sr));
+    }
+    if (bpolyak_) {
+      bxpv_[0] = B<double>("XPV0", d_ * C_);
+      bxpv_[1] = B<double>("XPV1", d_ * C_);
+    }
+    m_ = cg_ ? 0 : std::min<int64_t>(o_.m_init, mcap_);
+    k_ = 0;
+    const bool x0 = o_.x0 != nullptr;
+    if (x0)
+      launch_copy_cols(d_, C_, o_.x0, P_.ldx, (int)c_, X_, C_, s_);
+    else
+      launch_fill(X_, d_ * C_, 0.0, s_);
+    if (!mixed_) {
+      inner_begin(Bv_, X_, !x0, false, o_.stop, stop_scale_, false);
+    } else {
+      bE_ = B<double>("E", d_ * C_);
+      bRr_ = B<double>("Rres", d_ * C_);
+      bnrm_ = B<double>("nrm", 2 * C_);
+      bact_.assign(C_, 0);
+      for (int j = 0; j < c_; ++j) bact_[j] = 1;
+      const double inner = o_.inner_tol > 0 ? o_.inner_tol : 1e-6;
+      binner_scale_ = nu2_ * min_lambda() * inner * inner;
+      bxzero_ = !x0;
+      sweep_begin(true);
+    }
+  }
+
+  // Start an inner adaptive solve of H x = rhs (Algorithm 2 / Algorithm 1): sketch and factor
+  // unless the current factorisation is kept, then the initial residual and decrement.
+  void inner_begin(const double* rhs, double* x, bool x_zero, bool use32, int stop_rule, double stop_scale,
+                   bool reuse) {
+    brhs_ = rhs;
+    bx_ = x;
+    bx_zero_ = x_zero;
+    buse32_ = use32;
+    bstop_ = stop_rule;
+    bscale_ = stop_scale;
+    bt_ = 0;
+    bI_ = 0;
+    bforced_ = false;
+    if (bpolyak_) AES_HIP(hipMemcpyAsync(bxpv_[0], x, d_ * C_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
+    if (!reuse && !cg_) sketch_factor();
+    binit(true);
+    bstate_ = kBStep;
+  }
+
+  // (Re)initialisation at x after a factorisation: g or r, the preconditioned direction, D.
+  void binit(bool first) {
+    if (bihs_) {
+      if (bx_zero_ && first)
+        launch_hv_colsum(nullptr, 0, d_, C_, bx_, lam_, 0.0, 0.0, brhs_, -1.0, R_, s_);  // g = -b (no partials)
+      else if (first)
+        hv(bx_, R_, 1.0, brhs_, -1.0, buse32_);  // g = H x - b
+      apply(R_, Pv_);
+      launch_ihs_init(d_, C_, R_, Pv_, scal_, active_, gate_, bstop_, bscale_, stop_sr_, tol2_, bx_, first ? 1 : 0,
+                      s_, chol_flag_, vw_);
+    } else {
+      if (bx_zero_ && bt_ == 0)
+        AES_HIP(hipMemcpyAsync(R_, brhs_, d_ * C_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
+      else
+        hv(bx_, R_, -1.0, brhs_, 1.0, buse32_);  // explicit r_t = b - H x_t
+      apply(R_, RTP_);
+      launch_pcg_init(d_, C_, R_, RTP_, Pv_, scal_, active_, gate_, bstop_, bscale_, stop_sr_, tol2_, bx_,
+                      first ? 1 : 0, s_, chol_flag_, vw_);
+    }
+  }
+
+  // One refinement sweep of the mixed modes: r = b - H x in FP64, then the inner solve of H e = r.
+  void sweep_begin(bool first) {
+    ++sweeps_;
+    const int64_t dc = d_ * C_;
+    if (bxzero_)
+      AES_HIP(hipMemcpyAsync(bRr_, Bv_, dc * sizeof(double), hipMemcpyDeviceToDevice, s_));
+    else
+      residual_fp64(X_, Bv_, bRr_);
+    launch_fill(bE_, dc, 0.0, s_);
+    AES_HIP(hipMemcpyAsync(active_, bact_.data(), C_ * sizeof(int), hipMemcpyHostToDevice, s_));
+    inner_begin(bRr_, bE_, true, true, AES_STOP_XREL, binner_scale_, !first);
+  }
+
+  // r = b - H x with the FP64 matrix (the refinement residual)
+  void residual_fp64(const double* x, const double* b, double* r) { hv(x, r, -1.0, b, 1.0, false); }
+
+  bool batch_fp32() const { return mixed_; }
+  bool batch_ihs() const { return bihs_; }
+  int64_t batch_n() const { return n_; }
+  int64_t batch_d() const { return d_; }
+  int batch_C() const { return C_; }
+  int bstate() const { return bstate_; }
+  aes_status bstatus() const { return bstatus_; }
+
+  // Operands of the grouped step.  Ahp: the matrix the step multiplies by (FP32 copy or FP64).
+  // kpad: length of the rows of the transposed operand (the fused form's column-block width)
+  void batch_fill(BProb& bp, double* flags_out, int nrb, int64_t rows, bool twopass, int64_t kpad) {
+    const bool f32 = mixed_;
+    const size_t es = f32 ? sizeof(float) : sizeof(double);
+    const int NC = C_ < 16 ? 16 : C_;
+    bp = BProb{};
+    bp.A = f32 ? (const void*)A32_ : (const void*)P_.A;
+    bp.lda = f32 ? d_ : P_.lda;
+    bp.n = n_;
+    bp.d = d_;
+    bp.C = C_;
+    bp.nrb = nrb;
+    bp.rows = rows;
+    bp.kpad = kpad;
+    bp.VT = h_->buf<unsigned char>(ns_ + "bVT", (size_t)NC * bp.kpad * es);
+    bp.Z = twopass ? h_->buf<unsigned char>(ns_ + "bZ", (size_t)n_ * NC * es) : nullptr;
+    bp.part = h_->buf<unsigned char>(ns_ + "bpart", (size_t)nrb * d_ * C_ * es);
+    bp.lam = lam_;
+    bp.nu2 = nu2_;
+    bp.X = bx_;  // the iterate of the inner solve (the correction E in the mixed modes)
+    bp.R = R_;
+    bp.P = Pv_;
+    bp.Q = Q_;
+    bp.XP = XP_;
+    bp.RP = RP_;
+    bp.RTP = RTP_;
+    bp.rhs = brhs_;
+    bp.xpv0 = bxpv_[0];
+    bp.xpv1 = bxpv_[1];
+    bp.scal = scal_;
+    bp.active = active_;
+    bp.gate = gate_;
+    bp.flags_out = flags_out;
+    bp.mu = bmu_;
+    bp.beta = bbeta_;
+    bp.stop_scale = bscale_;
+    bp.stop_sr = stop_sr_;
+    bp.tol2 = tol2_;
+    bp.stop_rule = bstop_;
+    bp.adaptive = o_.adaptive;
+  }
+  // The iterate and right-hand side of the current inner solve change between sweeps.
+  void batch_refill(BProb& bp) {
+    bp.X = bx_;
+    bp.rhs = brhs_;
+    bp.stop_scale = bscale_;
+    bp.stop_rule = bstop_;
+  }
+
+  // Step parameters (before every step of the batch).
+  void batch_dyn(BDyn& dy) {
+    dy = BDyn{};
+    dy.run = bstate_ == kBStep ? 1 : 0;
+    if (!dy.run) return;
+    dy.thr = bpolyak_ ? blc_ + polyak_log_bound((double)(bt_ + 1 - bI_), bbeta_) : thr_of(blc_, blphi_, bt_, bI_);
+    bseq_ += 1.0;
+    dy.seq = bseq_;
+    dy.force = (o_.adaptive && o_.force_reject_at >= 0 && bt_ == o_.force_reject_at && !bforced_) ? 1 : 0;
+    dy.at_cap = m_ >= mcap_ ? 1 : 0;
+    dy.parity = (int)(bt_ & 1);
+    // H_S^{-1} rp -> rtp: the products of the current branch (Sec. 4.1)
+    auto prod = [](const double* mat, int64_t rows, int64_t K, int64_t ld, int tri, const double* in,
+                   const double* xs, double ysgn, const double* zadd, const double* rs, double gs, double* out) {
+      BProd p{};
+      p.mat = mat;
+      p.rows = rows;
+      p.K = K;
+      p.ld = ld;
+      p.tri = tri;
+      p.in = in;
+      p.xs = xs;
+      p.ysgn = ysgn;
+      p.zadd = zadd;
+      p.rs = rs;
+      p.gs = gs;
+      p.out = out;
+      return p;
+    };
+    if (cg_) {
+      dy.prod[0] = prod(nullptr, d_, 0, 0, 0, RP_, nullptr, 1.0, RP_, nullptr, 1.0, RTP_);  // identity
+    } else if (!woodbury_) {
+      dy.prod[0] = prod(Linv_, d_, d_, fp_, 1, RP_, nullptr, 1.0, nullptr, nullptr, 1.0, bt1_);
+      dy.prod[1] = prod(LinvT_, d_, d_, fp_, 2, bt1_, nullptr, 1.0, nullptr, nullptr, 1.0, RTP_);
+    } else {
+      dy.prod[0] = prod(SA_, m_, d_, d_, 0, RP_, invlam_, 1.0, nullptr, nullptr, 1.0, bu_);
+      dy.prod[1] = prod(Linv_, m_, m_, fp_, 1, bu_, nullptr, 1.0, nullptr, nullptr, 1.0, bt1_);
+      dy.prod[2] = prod(LinvT_, m_, m_, fp_, 2, bt1_, nullptr, 1.0, nullptr, nullptr, 1.0, bw_);
+      dy.prod[3] = prod(SAT_, d_, m_, m_, 0, bw_, nullptr, -1.0, RP_, invlam_, 1.0 / nu2_, RTP_);
+    }
+  }
+
+  // Host side of a step (flags: the problem's flag block after the step).  Returns true when
+  // the inner solve has ended and the mixed modes need their refinement check.
+  bool batch_after(const double* fl) {
+    if (bstate_ != kBStep) return false;
+    try {
+      for (int i = 0; i < 8; ++i) fl_[i] = fl[i];
+      if (fl_[7] != bseq_) {
+        // the step did not run: the initialisation before it closed the gate
+        if (fl_[6] != 0.0) throw StatusError(AES_ERR_NOT_SPD, "Cholesky pivot of the sketched Hessian is not positive");
+        if (fl_[2] != 0.0) return bdone(AES_ERR_NONFINITE);
+        return inner_end();
+      }
+      ++attempts_;
+      ++a_passes_;
+      const bool fail = fl_[0] != 0.0, accepted = fl_[3] != 0.0;
+      const bool forced_now = o_.adaptive && o_.force_reject_at >= 0 && bt_ == o_.force_reject_at && !bforced_;
+      if (forced_now) bforced_ = true;
+      trace(bt_, fl_[4], bpolyak_ ? blc_ + polyak_log_bound((double)(bt_ + 1 - bI_), bbeta_) : thr_of(blc_, blphi_, bt_, bI_),
+            accepted);
+      if (fl_[2] != 0.0) return bdone(AES_ERR_NONFINITE);
+      if (accepted) {
+        ++bt_;
+        ++iters_;
+        if (fail && o_.adaptive) m_cap_reached_ = 1;
+        if (fl_[1] <= 0.5) return inner_end();
+        if (bt_ >= o_.max_iter) return at_max_iter();
+        return false;
+      }
+      // rejected: double m, fresh sketch, restart at x_t
+      bI_ = bt_;
+      m_ = std::min<int64_t>(2 * m_, mcap_);
+      ++k_;
+      ++resketches_;
+      sketch_factor();
+      if (bpolyak_) AES_HIP(hipMemcpyAsync(bxpv_[bt_ & 1], bx_, d_ * C_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
+      binit(false);
+      return false;
+    } catch (const StatusError& e) {
+      h_->set_err(e.what());
+      bdone(e.st);
+    } catch (const HipError& e) {
+      h_->set_err(e.what());
+      bdone(AES_ERR_HIP);
+    } catch (const std::bad_alloc&) {
+      h_->set_err("device workspace allocation failed");
+      bdone(AES_ERR_OOM);
+    }
+    return false;
+  }
+
+  // max_iter accepted steps: the FIXED rule's end, MAX_ITER otherwise; an inner solve of the
+  // mixed modes ends its sweep instead (the refinement decides)
+  bool at_max_iter() {
+    if (mixed_) return inner_end();
+    return bdone(bstop_ == AES_STOP_FIXED ? AES_OK : AES_ERR_MAX_ITER);
+  }
+  // Before a step: a problem already at max_iter (max_iter = 0) takes no step.
+  bool batch_precheck() {
+    if (bstate_ == kBStep && bt_ >= o_.max_iter) return at_max_iter();
+    return false;
+  }
+
+  bool bdone(aes_status st) {
+    bstatus_ = st;
+    bstate_ = kBDone;
+    return false;
+  }
+
+  // End of an inner solve: done (FP64), or the refinement update and its check (mixed).
+  bool inner_end() {
+    if (!mixed_) return bdone(AES_OK);
+    launch_axpy_cols(d_, C_, X_, bE_, nullptr, s_);
+    bxzero_ = false;
+    launch_colnorm2(d_, C_, bE_, X_, bnrm_, s_);
+    bstate_ = kBRefine;
+    return true;
+  }
+  const double* batch_norms() const { return bnrm_; }
+
+  // Refinement check (host copy of ||e||^2, ||x||^2 per column): stop when ||e|| <= tol ||x|| / 4.
+  void batch_refine(const double* hn) {
+    try {
+      bool done = true;
+      for (int j = 0; j < c_; ++j) {
+        const double en = std::sqrt(hn[j]), xn = std::sqrt(hn[C_ + j]);
+        const bool ok = en <= 0.25 * tol_ * xn || xn == 0.0;
+        bact_[j] = ok ? 0 : 1;
+        done = done && ok;
+      }
+      if (done) {
+        bdone(AES_OK);
+        return;
+      }
+      if (sweeps_ >= std::max(1, o_.max_refine)) {
+        bdone(AES_ERR_MAX_ITER);
+        return;
+      }
+      sweep_begin(false);
+    } catch (const StatusError& e) {
+      h_->set_err(e.what());
+      bdone(e.st);
+    } catch (const HipError& e) {
+      h_->set_err(e.what());
+      bdone(AES_ERR_HIP);
+    } catch (const std::bad_alloc&) {
+      h_->set_err("device workspace allocation failed");
+      bdone(AES_ERR_OOM);
+    }
+  }
+
+  // Result and counters (after the batch has finished and the stream is idle).
+  aes_status batch_result(aes_info* info, double t0) {
+    aes_status st = bstatus_;
+    try {
+      if (st == AES_OK || st == AES_ERR_MAX_ITER || st == AES_ERR_NONFINITE)
+        launch_copy_cols(d_, (int)c_, X_, C_, (int)c_, P_.x, P_.ldx, s_);
+    } catch (const HipError& e) {
+      h_->set_err(e.what());
+      st = AES_ERR_HIP;
+    }
+    if (info) {
+      info->time_hv_ms = 0.0;
+      info->hv_launches = 0;
+      info->iterations = iters_;
+      info->attempts = attempts_;
+      info->final_m = m_;
+      info->resketches = resketches_;
+      info->a_passes = a_passes_;
+      info->refine_sweeps = sweeps_;
+      info->trace_len = trace_len_;
+      info->dtilde_final = fl_[5];
+      double sk_ms = 0.0;
+      if (st != AES_ERR_HIP)
+        for (auto& e : sk_ev_) {
+          float ms = 0.f;
+          if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) sk_ms += ms;
+        }
+      info->time_sketch_ms = sk_ms;
+      info->time_total_ms = now_ms() - t0;
+      info->m_cap_reached = m_cap_reached_;
+      info->status = st;
+    }
+    return st;
+  }
+
   // accessors for the kept context
   int64_t m() const { return m_; }
   int64_t k() const { return k_; }
@@ -957,7 +1343,7 @@ class Solver {
   ProblemDesc P_;
   aes_options o_;
   double tol_;
-  std::string ns_;
+  std::string ns_, sns_;
   int64_t n_, d_, c_;
   int C_;
   int64_t npad_, mcap_, m_ = 1, k_ = 0, fp_ = 64;
@@ -992,6 +1378,337 @@ class Solver {
   bool fused_ = true;  // single-RHS fused H.v (and the speculative step pipeline)
   bool cg_ = false;
   const int* chol_flag_ = nullptr;
+  // batch mode
+  BState bstate_ = kBStep;
+  aes_status bstatus_ = AES_OK;
+  const double* brhs_ = nullptr;
+  double* bx_ = nullptr;
+  bool bx_zero_ = true, buse32_ = false, bxzero_ = true;
+  int bstop_ = 0;
+  double bscale_ = 0.0, binner_scale_ = 0.0;
+  int64_t bt_ = 0, bI_ = 0;
+  bool bforced_ = false;
+  double bseq_ = 0.0;
+  double blc_ = 0.0, blphi_ = 0.0, bmu_ = 0.0, bbeta_ = 0.0;
+  bool bihs_ = false, bpolyak_ = false;
+  double* bxpv_[2] = {nullptr, nullptr};
+  double *bu_ = nullptr, *bt1_ = nullptr, *bw_ = nullptr, *bE_ = nullptr, *bRr_ = nullptr, *bnrm_ = nullptr;
+  int* gate_ = nullptr;
+  std::vector<int> bact_;
+};
+
+// ---------------------------------------------------------------------------------------
+// Batched solves (Sec. 5 "matrix variables", many problems): each problem keeps its own
+// Solver for the control of Algorithm 2 / Algorithm 1 (resizes, restarts, refinement sweeps),
+// while the step of every problem that is stepping runs as one fixed sequence of grouped
+// launches (k_batch.hip), captured once in a HIP graph and replayed once per step.  Between
+// replays the host reads every problem's flag block (one copy) and enqueues the eager work of
+// the problems that were rejected (sketch, factorisation, explicit residual, initialisation) or
+// finished an inner solve (refinement).
+// ---------------------------------------------------------------------------------------
+struct HpPlan {
+  bool twopass = false;
+  int64_t rows = 0;  // rows per range of the partial products
+};
+
+// Tuned plans of the grouped H.P, one per (precision, ceil(log2 n), ceil(d / 256)) bucket, read
+// once from a text file (lines "fp32|fp64 <log2 n> <d blocks> fused|twopass <rows> ..."): the
+// file named by AES_TUNE_FILE, else tune/hp_plans.txt beside the library's directory.
+struct HpTuned {
+  std::mutex mu;
+  bool loaded = false;
+  std::unordered_map<std::string, HpPlan> plans;
+};
+HpTuned& hp_tuned_table() {
+  static HpTuned t;
+  return t;
+}
+std::string hp_bucket(int64_t n, int64_t d, bool fp32) {
+  int lg = 0;
+  while ((int64_t(1) << lg) < n) ++lg;
+  return std::string(fp32 ? "fp32 " : "fp64 ") + std::to_string(lg) + " " + std::to_string(ceil_div(d, 256));
+}
+void hp_tuned_load(HpTuned& t) {
+  t.loaded = true;
+  std::string path;
+  if (const char* e = std::getenv("AES_TUNE_FILE")) {
+    path = e;
+  } else {
+    Dl_info info;
+    if (dladdr(reinterpret_cast<void*>(&hp_tuned_table), &info) && info.dli_fname) {
+      std::string lib = info.dli_fname;
+      const size_t sl = lib.rfind('/');
+      const std::string dir = sl == std::string::npos ? std::string(".") : lib.substr(0, sl);
+      path = dir + "/../tune/hp_plans.txt";
+    }
+  }
+  if (path.empty()) return;
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return;
+  char line[256];
+  while (std::fgets(line, sizeof(line), f)) {
+    char prec[8], kind[16];
+    int lg = 0, db = 0;
+    long long rows = 0;
+    if (line[0] == '#') continue;
+    if (std::sscanf(line, "%7s %d %d %15s %lld", prec, &lg, &db, kind, &rows) != 5) continue;
+    HpPlan p;
+    p.twopass = std::strcmp(kind, "twopass") == 0;
+    p.rows = rows;
+    if (rows <= 0 || (!p.twopass && std::strcmp(kind, "fused") != 0)) continue;
+    t.plans[std::string(prec) + " " + std::to_string(lg) + " " + std::to_string(db)] = p;
+  }
+  std::fclose(f);
+}
+bool hp_tuned(int64_t n, int64_t d, bool fp32, HpPlan* out) {
+  HpTuned& t = hp_tuned_table();
+  std::lock_guard<std::mutex> lock(t.mu);
+  if (!t.loaded) hp_tuned_load(t);
+  auto it = t.plans.find(hp_bucket(n, d, fp32));
+  if (it == t.plans.end()) return false;
+  *out = it->second;
+  return true;
+}
+
+// Plan of the grouped H.P for one problem.  It depends only on the problem's shape (so a
+// problem gives the same sums alone and in a batch): the tuned plan of its bucket when there is
+// one and it applies, else the default (fused when the shape allows it).
+HpPlan hp_plan(int64_t n, int64_t d, bool fp32, bool vec_ok) {
+  const bool fused_ok = vec_ok && bhp_fused_mb(!fp32, d) <= bhp_fused_max_mb(!fp32);
+  HpPlan p;
+  if (hp_tuned(n, d, fp32, &p) && (p.twopass || fused_ok)) return p;
+  p.twopass = !fused_ok;
+  if (!p.twopass)
+    p.rows = std::max<int64_t>(64, std::min<int64_t>(512, round_up(ceil_div(n, 256), 16)));
+  else
+    p.rows = std::max<int64_t>(512, round_up(ceil_div(n, 64), 64));
+  return p;
+}
+
+class BatchEngine {
+ public:
+  BatchEngine(aes_handle h, hipStream_t caller, const std::vector<ProblemDesc>& probs, const aes_options& o,
+              double tol, const std::vector<int32_t>& ids)
+      : h_(h), caller_(caller), P_(probs), o_(o), tol_(tol), ids_(ids) {}
+  ~BatchEngine() { cleanup(); }
+
+  aes_status run(aes_info* infos) {
+    const double t0 = now_ms();
+    const int np = (int)P_.size();
+    AES_HIP(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
+    AES_HIP(hipEventCreateWithFlags(&ready_, hipEventDisableTiming));
+    AES_HIP(hipEventRecord(ready_, caller_));
+    AES_HIP(hipStreamWaitEvent(s_, ready_, 0));
+    so_.resize(np);
+    for (int p = 0; p < np; ++p) {
+      aes_options op = o_;
+      op.problem = ids_[p];
+      so_[p] = std::make_unique<Solver>(h_, s_, P_[p], op, tol_, "b" + std::to_string(p) + ".", "bs.");
+    }
+    // per-problem set-up (eager): casts, the first sketch and factorisation, the initialisation
+    for (int p = 0; p < np; ++p) {
+      try {
+        so_[p]->batch_begin();
+      } catch (const StatusError& e) {
+        h_->set_err(e.what());
+        so_[p]->bdone(e.st);
+      } catch (const std::bad_alloc&) {
+        h_->set_err("device workspace allocation failed");
+        so_[p]->bdone(AES_ERR_OOM);
+      }
+    }
+    build(np);
+    const bool graph = graph_enabled();
+    if (graph) capture();
+    std::vector<int> refine;
+    for (;;) {
+      refine.clear();
+      bool any = false;
+      for (int p = 0; p < np; ++p) {
+        if (so_[p]->batch_precheck()) refine.push_back(p);
+        so_[p]->batch_dyn(hdyn_[p]);
+        any = any || hdyn_[p].run != 0;
+      }
+      if (any) {
+        AES_HIP(hipMemcpyAsync(ddyn_, hdyn_, np * sizeof(BDyn), hipMemcpyHostToDevice, s_));
+        if (graph)
+          AES_HIP(hipGraphLaunch(exec_, s_));
+        else
+          enqueue_step();
+        AES_HIP(hipMemcpyAsync(hflags_, dflags_, (size_t)np * 8 * sizeof(double), hipMemcpyDeviceToHost, s_));
+        AES_HIP(hipStreamSynchronize(s_));
+        ++steps_;
+        for (int p = 0; p < np; ++p)
+          if (hdyn_[p].run && so_[p]->batch_after(hflags_ + 8 * p)) refine.push_back(p);
+      }
+      if (!refine.empty()) {
+        for (int p : refine)
+          AES_HIP(hipMemcpyAsync(hnrm_ + 64 * p, so_[p]->batch_norms(), 2 * so_[p]->batch_C() * sizeof(double),
+                                 hipMemcpyDeviceToHost, s_));
+        AES_HIP(hipStreamSynchronize(s_));
+        for (int p : refine) so_[p]->batch_refine(hnrm_ + 64 * p);
+      }
+      bool all_done = true;
+      for (int p = 0; p < np; ++p) all_done = all_done && so_[p]->bstate() == Solver::kBDone;
+      if (all_done) break;
+      if (!any && refine.empty()) throw HipError("batched solve made no progress");
+    }
+    aes_status worst = AES_OK;
+    for (int p = 0; p < np; ++p) {
+      const aes_status st = so_[p]->batch_result(infos ? &infos[p] : nullptr, t0);
+      if (st != AES_OK && worst == AES_OK) worst = st;
+    }
+    AES_HIP(hipStreamSynchronize(s_));
+    return worst;
+  }
+
+  int64_t steps() const { return steps_; }
+
+ private:
+  static bool graph_enabled() {
+    const char* e = std::getenv("AES_BATCH_GRAPH");
+    return !(e && e[0] == '0');
+  }
+
+  void build(int np) {
+    fp32_ = so_[0]->batch_fp32();
+    ihs_ = so_[0]->batch_ihs();
+    method_ = o_.method;
+    np_ = np;
+    dflags_ = h_->buf<double>("bt.flags", (size_t)np * 8);
+    dprob_ = h_->buf<BProb>("bt.prob", np);
+    ddyn_ = h_->buf<BDyn>("bt.dyn", np);
+    AES_HIP(hipHostMalloc((void**)&hdyn_, np * sizeof(BDyn), hipHostMallocDefault));
+    AES_HIP(hipHostMalloc((void**)&hflags_, (size_t)np * 8 * sizeof(double), hipHostMallocDefault));
+    AES_HIP(hipHostMalloc((void**)&hnrm_, (size_t)np * 64 * sizeof(double), hipHostMallocDefault));
+    std::vector<BProb> hp(np);
+    std::vector<BWork> z, a, tiles;
+    std::vector<std::vector<BWork>> fw(9);
+    const size_t es = fp32_ ? sizeof(float) : sizeof(double);
+    for (int p = 0; p < np; ++p) {
+      Solver& so = *so_[p];
+      const int64_t n = so.batch_n(), d = so.batch_d();
+      const int vw = (int)(16 / es);
+      const ProblemDesc& P = P_[p];
+      // the FP32 copy is dense (ld d) in a 256-byte aligned pool buffer
+      const bool vec_ok = fp32_ ? d % vw == 0
+                                : (d % vw == 0 && P.lda % vw == 0 && (reinterpret_cast<uintptr_t>(P.A) & 15) == 0);
+      const HpPlan hpp = hp_plan(n, d, fp32_, vec_ok);
+      const int nrb = (int)ceil_div(n, hpp.rows);
+      // the fused form reads whole column blocks of 256 * mb of the transposed operand
+      const int64_t kpad = hpp.twopass ? round_up(d, 256) : 256 * (int64_t)bhp_fused_mb(!fp32_, d);
+      so.batch_fill(hp[p], dflags_ + 8 * p, nrb, hpp.rows, hpp.twopass, kpad);
+      max_vt_ = std::max<int64_t>(max_vt_, (int64_t)std::max(16, so.batch_C()) * kpad);
+      max_dc_ = std::max<int64_t>(max_dc_, d * so.batch_C());
+      if (!hpp.twopass) {
+        const int mb = bhp_fused_mb(!fp32_, d);
+        for (int r = 0; r < nrb; ++r) fw[mb].push_back(BWork{p, r});
+      } else {
+        for (int64_t t = 0; t < ceil_div(n, 64); ++t) z.push_back(BWork{p, (int32_t)t});
+        const int64_t ct = ceil_div(d, 64);
+        for (int64_t r = 0; r < nrb; ++r)
+          for (int64_t t = 0; t < ct; ++t) a.push_back(BWork{p, (int32_t)(r * ct + t)});
+      }
+      for (int64_t t = 0; t < ceil_div(d, 64); ++t) tiles.push_back(BWork{p, (int32_t)t});
+    }
+    AES_HIP(hipMemcpyAsync(dprob_, hp.data(), np * sizeof(BProb), hipMemcpyHostToDevice, s_));
+    auto upload = [&](const std::vector<BWork>& v, const char* name) -> BWork* {
+      if (v.empty()) return nullptr;
+      BWork* dv = h_->buf<BWork>(name, v.size());
+      AES_HIP(hipMemcpyAsync(dv, v.data(), v.size() * sizeof(BWork), hipMemcpyHostToDevice, s_));
+      return dv;
+    };
+    for (int mb = 1; mb <= 8; ++mb) {
+      fwork_[mb] = upload(fw[mb], ("bt.fw" + std::to_string(mb)).c_str());
+      nfwork_[mb] = (int)fw[mb].size();
+    }
+    zwork_ = upload(z, "bt.zw");
+    nz_ = (int)z.size();
+    awork_ = upload(a, "bt.aw");
+    na_ = (int)a.size();
+    tiles_ = upload(tiles, "bt.tiles");
+    ntiles_ = (int)tiles.size();
+    // the host vectors must outlive the asynchronous copies
+    AES_HIP(hipStreamSynchronize(s_));
+  }
+
+  // The step of every problem (run flag and device gate decide who takes part).
+  void enqueue_step() {
+    if (fp32_)
+      enqueue_typed<float>();
+    else
+      enqueue_typed<double>();
+  }
+  template <typename T>
+  void enqueue_typed() {
+    if (ihs_) launch_bcandidate(dprob_, ddyn_, np_, method_, s_);  // xp = x - mu s (+ momentum)
+    launch_bprep<T>(dprob_, ddyn_, np_, max_vt_, ihs_, s_);
+    for (int mb = 1; mb <= 8; ++mb)
+      if (nfwork_[mb]) launch_bhp_fused<T>(dprob_, ddyn_, fwork_[mb], nfwork_[mb], mb, s_);
+    if (nz_ || na_) launch_bhp_twopass<T>(dprob_, ddyn_, zwork_, nz_, awork_, na_, s_);
+    launch_bcolsum<T>(dprob_, ddyn_, np_, max_dc_, ihs_, s_);
+    if (!ihs_) launch_bcandidate(dprob_, ddyn_, np_, method_, s_);  // alpha, xp, rp
+    const int slots = method_ == AES_CG ? 1 : kBProds;
+    for (int sl = 0; sl < slots; ++sl) launch_bapply(dprob_, ddyn_, tiles_, ntiles_, sl, s_);
+    launch_bfinish(dprob_, ddyn_, np_, ihs_, s_);
+  }
+
+  void capture() {
+    hipGraph_t g = nullptr;
+    AES_HIP(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
+    try {
+      enqueue_step();
+    } catch (...) {
+      hipGraph_t junk = nullptr;
+      (void)hipStreamEndCapture(s_, &junk);
+      if (junk) (void)hipGraphDestroy(junk);
+      throw;
+    }
+    AES_HIP(hipStreamEndCapture(s_, &g));
+    const hipError_t e = hipGraphInstantiate(&exec_, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    AES_HIP(e);
+  }
+
+  void cleanup() {
+    if (s_) (void)hipStreamSynchronize(s_);
+    if (exec_) (void)hipGraphExecDestroy(exec_);
+    exec_ = nullptr;
+    so_.clear();
+    if (hdyn_) (void)hipHostFree(hdyn_);
+    if (hflags_) (void)hipHostFree(hflags_);
+    if (hnrm_) (void)hipHostFree(hnrm_);
+    hdyn_ = nullptr;
+    hflags_ = nullptr;
+    hnrm_ = nullptr;
+    if (ready_) (void)hipEventDestroy(ready_);
+    ready_ = nullptr;
+    if (s_) (void)hipStreamDestroy(s_);
+    s_ = nullptr;
+  }
+
+  aes_handle h_;
+  hipStream_t caller_;
+  std::vector<ProblemDesc> P_;
+  aes_options o_;
+  double tol_;
+  std::vector<int32_t> ids_;
+  hipStream_t s_ = nullptr;
+  hipEvent_t ready_ = nullptr;
+  hipGraphExec_t exec_ = nullptr;
+  std::vector<std::unique_ptr<Solver>> so_;
+  bool fp32_ = false, ihs_ = false;
+  int method_ = 0, np_ = 0;
+  BProb* dprob_ = nullptr;
+  BDyn* ddyn_ = nullptr;
+  BDyn* hdyn_ = nullptr;
+  double *dflags_ = nullptr, *hflags_ = nullptr, *hnrm_ = nullptr;
+  BWork* fwork_[9] = {};
+  int nfwork_[9] = {};
+  BWork *zwork_ = nullptr, *awork_ = nullptr, *tiles_ = nullptr;
+  int nz_ = 0, na_ = 0, ntiles_ = 0;
+  int64_t max_vt_ = 0, max_dc_ = 0;
+  int64_t steps_ = 0;
 };
 
 aes_status guard(aes_handle h, const std::function<void()>& f) {
@@ -1097,6 +1814,20 @@ static aes_status solve_impl(aes_handle h, void* stream, const ProblemDesc& P, d
       info->status = st;
     }
     return st;
+  }
+  if (P.c > 1 && !keep) {
+    // several right-hand sides: the grouped step of the batched engine (one problem), so that a
+    // problem solved alone and within a batch takes the same arithmetic
+    aes_status bst = AES_OK;
+    st = guard(h, [&] {
+      BatchEngine eng(h, (hipStream_t)stream, std::vector<ProblemDesc>{P}, o, tol, std::vector<int32_t>{o.problem});
+      bst = eng.run(info);
+    });
+    if (st != AES_OK && info) {
+      std::memset(info, 0, sizeof(*info));
+      info->status = st;
+    }
+    return st != AES_OK ? st : bst;
   }
   auto* solver = new Solver(h, (hipStream_t)stream, P, o, tol, ns);
   st = solver->run(info);
@@ -1204,61 +1935,27 @@ aes_status aes_solve_batched(aes_handle h, void* stream, int64_t nprob, const ae
     aes_status st = guard(h, [&] { validate(P, tol, o); });
     if (st != AES_OK) return st;
   }
-  hipEvent_t ready = nullptr;
-  aes_status st0 = guard(h, [&] {
-    set_device(h);
-    AES_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
-    AES_HIP(hipEventRecord(ready, (hipStream_t)stream));
-  });
-  if (st0 != AES_OK) return st0;
-  // Problems run concurrently on W workers, each with its own stream (default priority),
-  // pinned flag block and workspace namespace; every problem keeps its own adaptive control.
-  int max_workers = 8;
-  if (const char* env = std::getenv("AES_BATCH_WORKERS")) {
-    const int v = std::atoi(env);
-    if (v >= 1 && v <= 64) max_workers = v;
+  // all problems step together in the grouped kernels (one graph launch per step); problem p
+  // draws its sketches from Philox stream p
+  std::vector<ProblemDesc> P;
+  std::vector<int32_t> ids;
+  for (int64_t p = 0; p < nprob; ++p) {
+    const aes_problem& q = probs[p];
+    P.push_back(ProblemDesc{q.n, q.d, q.c, q.A, q.lda, q.b, q.ldb, q.nu, q.lambda, q.x, q.ldx});
+    ids.push_back((int32_t)p);
   }
-  const int W = (int)std::min<int64_t>(nprob, max_workers);
-  std::vector<aes_status> sts((size_t)nprob, AES_OK);
-  std::atomic<int64_t> next{0};
-  auto worker = [&](int w) {
-    hipStream_t sw = nullptr;
-    double* pin = nullptr;
-    aes_status wst = guard(h, [&] {
-      set_device(h);
-      AES_HIP(hipStreamCreateWithFlags(&sw, hipStreamNonBlocking));
-      AES_HIP(hipStreamWaitEvent(sw, ready, 0));
-      AES_HIP(hipHostMalloc((void**)&pin, 64 * sizeof(double), hipHostMallocDefault));
-    });
-    for (;;) {
-      const int64_t p = next.fetch_add(1);
-      if (p >= nprob) break;
-      if (wst != AES_OK) {
-        sts[p] = wst;
-        continue;
-      }
-      const aes_problem& q = probs[p];
-      ProblemDesc P{q.n, q.d, q.c, q.A, q.lda, q.b, q.ldb, q.nu, q.lambda, q.x, q.ldx};
-      aes_options op = o;
-      op.problem = (int32_t)p;
-      Solver so(h, sw, P, op, tol, "w" + std::to_string(w) + ".");
-      so.set_pinned(pin);
-      sts[p] = so.run(infos ? &infos[p] : nullptr);
+  aes_status bst = AES_OK;
+  const aes_status st = guard(h, [&] {
+    set_device(h);
+    BatchEngine eng(h, (hipStream_t)stream, P, o, tol, ids);
+    bst = eng.run(infos);
+  });
+  if (st != AES_OK && infos)
+    for (int64_t p = 0; p < nprob; ++p) {
+      std::memset(&infos[p], 0, sizeof(aes_info));
+      infos[p].status = st;
     }
-    if (sw) {
-      (void)hipStreamSynchronize(sw);
-      (void)hipStreamDestroy(sw);
-    }
-    if (pin) (void)hipHostFree(pin);
-  };
-  std::vector<std::thread> th;
-  for (int w = 0; w < W; ++w) th.emplace_back(worker, w);
-  for (auto& t : th) t.join();
-  (void)hipEventDestroy(ready);
-  aes_status worst = AES_OK;
-  for (aes_status st : sts)
-    if (st != AES_OK && worst == AES_OK) worst = st;
-  return worst;
+  return st != AES_OK ? st : bst;
 }
 
 aes_status aes_solve_keep(aes_handle h, void* stream, int64_t n, int64_t d, int64_t c, const double* A, int64_t lda,

@@ -16,24 +16,10 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "vec_device.h"
 
 namespace aes {
 
-constexpr int kVT = 1024;  // threads of the single-workgroup vector kernels
-
-enum StopRule { kStopXrel = 0, kStopDtildeRel = 1, kStopFixed = 2, kStopRemark = 3 };
-
-// Column-wise block sum: thread t contributes v to column t % C (C a power of two dividing
-// 1024); on return buf[c] holds the sum for column c (fixed-order tree).
-__device__ __forceinline__ void col_reduce(double* buf, double v, int C) {
-  const int tid = threadIdx.x;
-  buf[tid] = v;
-  __syncthreads();
-  for (int s = kVT / 2; s >= C; s >>= 1) {
-    if (tid < s) buf[tid] += buf[tid + s];
-    __syncthreads();
-  }
-}
 
 // ---------------------------------------------------------------------------------------
 // Wide form of the vector kernels (d * C >= kSplitElems, no device gate): the column sums
@@ -178,21 +164,6 @@ void launch_pcg_candidate(int64_t d, int C, const double* spart, int nwg, const 
   }
 }
 
-// Stop rule of one column after a commit (see oracle docs / design notes for the readings).
-__device__ __forceinline__ bool stop_test(int rule, double Dfull, double D0full, double xn2, bool resid_zero,
-                                          double stop_scale, double stop_sr, double tol2) {
-  if (Dfull <= 0.0 || resid_zero) return true;
-  switch (rule) {
-    case kStopXrel:
-      return stop_sr * Dfull <= stop_scale * xn2;
-    case kStopDtildeRel:
-      return Dfull <= tol2 * D0full;
-    case kStopRemark:
-      return 0.5 * Dfull <= stop_scale;
-    default:
-      return false;  // kStopFixed is decided by the host from the step count
-  }
-}
 
 // Shared tail of the PCG / IHS finish kernels.  `half` = 1 for the IHS decrement.
 template <bool IHS>
