@@ -14,12 +14,14 @@ Extra legs (outside the timed region of the headline value):
   * mixed precision vs FP64 on the n = 262144, d = 4096 workload (sigma_j = 0.995^j,
     nu = 1e-2), both validated against the oracle reference (skip with --no-mixed);
   * cpu_baseline: the oracle on the host cores (see cpu_baseline());
-  * --batched (or --all): 64 uneven problems x 32 right-hand sides (n = 256 U{32..512},
-    d = 256 U{1..8}, sigma_j = 0.98^j, nu log-uniform in [1e-4, 1e-1]) solved by the concurrent
-    batched driver in FP32 storage + FP64 refinement and in FP64, a stratified sample of four
-    problems validated against the oracle;
-  * --adjoint (or --all): forward + backward of the autograd Function on n = 131072, d = 1024
-    (sigma_j = j^-1/2, nu = 1e-2), gradients validated against the dense oracle;
+  * small_n4096_d256 (skip with --no-small): the n = 4096, d = 256 workload, time per solve and
+    per step;
+  * batched (skip with --no-batched): 64 uneven problems x 32 right-hand sides (n = 256 U{32..512},
+    d = 256 U{1..8}, sigma_j = 0.98^j, nu log-uniform in [1e-4, 1e-1]), every step of all problems
+    one replay of the captured grouped step, in FP32 storage + FP64 refinement and in FP64; eight
+    problems (the four smallest nu, four spread over n d) validated against the oracle;
+  * adjoint (skip with --no-adjoint): forward + backward of the autograd Function on n = 131072,
+    d = 1024 (sigma_j = j^-1/2, nu = 1e-2), gradients validated against the dense oracle;
   * variants (skip with --no-variants): the headline workload solved with the Gaussian and
     SJLT sketches, with the transform-reuse SRHT (a variant), by adaptive IHS, by adaptive
     Polyak-IHS, and by the unpreconditioned CG baseline;
@@ -46,6 +48,11 @@ sys.path.insert(0, ROOT)
 METRIC = "time-to-1e-10 rel err per solve (s); Aᵀ(Ax) HBM GB/s; mixed vs FP64 speedup"
 HBM_PEAK_GBPS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "hv_fused_counters.json")
+
+
+def log(msg):
+    """Progress line on stderr (the JSON result line is the only stdout output)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def sha256_file(path):
@@ -204,8 +211,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--hv-only", action="store_true")
     ap.add_argument("--sketch-only", type=int, default=0, metavar="M")
-    ap.add_argument("--batched", action="store_true")
-    ap.add_argument("--adjoint", action="store_true")
+    ap.add_argument("--batched", action="store_true", help="with --skip-main: the batched leg")
+    ap.add_argument("--adjoint", action="store_true", help="with --skip-main: the autograd leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched leg of the default line")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the autograd leg of the default line")
+    ap.add_argument("--no-small", action="store_true", help="skip the n = 4096, d = 256 leg")
     ap.add_argument("--all", action="store_true")
     ap.add_argument("--skip-main", action="store_true", help="run only the selected extra legs (profiling)")
     ap.add_argument("--mixed", action="store_true", help="with --skip-main: the mixed-precision leg")
@@ -271,6 +281,7 @@ def main():
     if w.lam == "identity":
         lam = None
     opts = dict(method=args.method, sketch=args.sketch, m_init=w.m_init, seed=1, tol=1e-10)
+    log(f"main leg: {args.workload} {args.method} {args.sketch}, {args.warmup} warmup + {args.steps} timed solves")
     x, infos, sec = timed_solves(aes, torch, A, b, nu, lam, opts, args.steps, args.warmup, profile=True)
     info = infos[-1]
     n, d = w.n, w.d
@@ -302,16 +313,24 @@ def main():
     }
 
     if not args.no_variants:
+        log("variants leg")
         out["variants"] = variants_leg(aes, torch, A, b, nu, lam, w, P_np, args)
     if not args.no_mixed:
+        log("mixed vs fp64 leg")
         out["mixed_vs_fp64"] = mixed_leg(aes, torch, synth)
 
-    if args.batched or args.all:
+    if not args.no_small:
+        log("small n=4096 d=256 leg")
+        out["small_n4096_d256"] = small_leg(aes, torch, synth)
+    if not args.no_batched:
+        log("batched 64 x 32 rhs leg")
         out["batched"] = batched_leg(aes, torch, synth)
-    if args.adjoint or args.all:
+    if not args.no_adjoint:
+        log("adjoint leg")
         out["adjoint"] = adjoint_leg(aes, torch, synth)
 
     if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on the host) leg")
         cb = cpu_baseline(P_np, info, w.m_init)
         cb["gpu_speedup"] = cb["value"] / sec
         out["cpu_baseline"] = cb
@@ -483,10 +502,27 @@ def mixed_leg(aes, torch, synth):
     return res
 
 
-def batched_leg(aes, torch, synth):
+def spectral_error(P_np, x):
+    """Per-column ||x - x*|| / ||x|| of a synthetic problem A = U diag(sigma) V^T (Lambda = I):
+    the oracle's extended-precision residual r = b - H x mapped by the spectral inverse
+    V diag(1 / (sigma^2 + nu^2)) V^T (x* - x = H^{-1} r)."""
     import numpy as np
 
     from oracle import reference
+
+    r = reference.residual_extended(P_np["A"], P_np["b"], P_np["nu"], None, x, threads=16).astype(np.float64)
+    w = 1.0 / (np.asarray(P_np["sigma"], dtype=np.float64) ** 2 + P_np["nu"] ** 2)
+    V = P_np["V"]
+    e = V @ (w[:, None] * (V.T @ r))
+    return np.linalg.norm(e, axis=0) / np.linalg.norm(x, axis=0)
+
+
+def batched_leg(aes, torch, synth, nvalidate=8):
+    """64 uneven problems x 32 right-hand sides, every step of all problems one replay of the
+    captured grouped step; FP32 storage + FP64 refinement, then FP64.  The 4 worst-conditioned
+    problems (smallest nu) and 4 spread over n d are validated with the oracle's
+    extended-precision residual (all 64 are validated by the GPU test suite)."""
+    import numpy as np
 
     specs = synth.batched_specs(64, seed=0)
     probs, keep = [], []
@@ -496,7 +532,8 @@ def batched_leg(aes, torch, synth):
         probs.append(dict(A=P["A"], b=P["b"], nu=P["nu"]))
         keep.append(P)
     torch.cuda.synchronize()
-    res = {"problems": 64, "rhs": 32, "sum_nd": int(sum(sp["n"] * sp["d"] for sp in specs))}
+    nd = [sp["n"] * sp["d"] for sp in specs]
+    res = {"problems": 64, "rhs": 32, "sum_nd": int(sum(nd))}
     outs = {}
     for prec, steps in (("mixed_fp32", 2), ("fp64", 1)):
         aes.solve_batched(probs, tol=1e-10, precision=prec, m_init=16, seed=7)  # warmup
@@ -507,26 +544,52 @@ def batched_leg(aes, torch, synth):
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t0) / steps
         outs[prec] = r
-        res[prec] = {"s_per_batch": sec, "statuses_ok": sum(1 for _, i in r if i["status"] == "ok"),
-                     "max_final_m": max(i["final_m"] for _, i in r),
-                     "sum_problem_ms": sum(i["time_total_ms"] for _, i in r),
-                     "sum_sketch_ms": sum(i["time_sketch_ms"] for _, i in r),
-                     "sum_a_passes": sum(i["a_passes"] for _, i in r),
-                     "sum_resketches": sum(i["resketches"] for _, i in r)}
-    order = sorted(range(64), key=lambda i: specs[i]["n"] * specs[i]["d"])
-    pick = sorted({order[0], order[-1], min(range(64), key=lambda i: specs[i]["nu"]), order[32]})
-    errs = {"mixed_fp32": [], "fp64": []}
+        infos = [i for _, i in r]
+        # useful work of the grouped products: 4 n d flops per column per step attempt
+        flops = sum(4.0 * nd[p] * 32 * infos[p]["attempts"] for p in range(64))
+        res[prec] = {"s_per_batch": sec, "statuses_ok": sum(1 for i in infos if i["status"] == "ok"),
+                     "max_final_m": max(i["final_m"] for i in infos),
+                     "max_attempts": max(i["attempts"] for i in infos),
+                     "sum_attempts": sum(i["attempts"] for i in infos),
+                     "sum_sketch_ms": sum(i["time_sketch_ms"] for i in infos),
+                     "sum_resketches": sum(i["resketches"] for i in infos),
+                     "sum_refine_sweeps": sum(i["refine_sweeps"] for i in infos),
+                     "step_products_tflop": flops / 1e12}
+    by_nu = sorted(range(64), key=lambda i: specs[i]["nu"])[:nvalidate // 2]
+    order = sorted(range(64), key=lambda i: nd[i])
+    spread = [order[0], order[21], order[42], order[63]]
+    pick = sorted(set(by_nu) | set(spread))
+    log(f"batched: validating problems {pick} against the oracle residual")
+    for prec in ("mixed_fp32", "fp64"):
+        res[prec]["per_problem_max_err"] = {}
     for i in pick:
         Pn = to_numpy(keep[i])
-        xr = reference.reference_solution(Pn["A"], Pn["b"], Pn["nu"], None, spectral=(Pn["V"], Pn["sigma"]))
-        for prec in errs:
-            errs[prec].append(float(np.max(reference.rel_error(outs[prec][i][0].cpu().numpy(), xr))))
-    for prec in errs:
+        for prec in ("mixed_fp32", "fp64"):
+            e = float(np.max(spectral_error(Pn, outs[prec][i][0].cpu().numpy())))
+            res[prec]["per_problem_max_err"][str(i)] = e
+        log(f"batched: problem {i} checked")
+    for prec in ("mixed_fp32", "fp64"):
+        errs = list(res[prec]["per_problem_max_err"].values())
         res[prec]["validated_problems"] = pick
-        res[prec]["max_rel_err"] = max(errs[prec])
-        res[prec]["valid"] = bool(max(errs[prec]) <= 1e-10)
+        res[prec]["max_rel_err"] = max(errs)
+        res[prec]["valid"] = bool(max(errs) <= 1e-10 and res[prec]["statuses_ok"] == 64)
     res["speedup_mixed_vs_fp64"] = res["fp64"]["s_per_batch"] / res["mixed_fp32"]["s_per_batch"]
     return res
+
+
+def small_leg(aes, torch, synth, steps=20):
+    """The n = 4096, d = 256 workload (A of 8.4 MB, resident in cache): time per solve and per
+    attempted step, validated against the oracle's refined reference."""
+    P = synth.make_workload("pcg_n4096_d256", seed=0, backend="torch", device="cuda")
+    opts = dict(m_init=8, seed=1, tol=1e-10)
+    x, infos, sec = timed_solves(aes, torch, P["A"], P["b"], P["nu"], None, opts, steps, 3)
+    info = infos[-1]
+    P_np = to_numpy(P)
+    P_np["lam"] = None
+    err = reference_error(P_np, x.cpu().numpy())
+    return {"workload": "pcg_n4096_d256", "s_per_solve": sec, "us_per_attempted_step": sec * 1e6 / info["attempts"],
+            "us_per_iteration": sec * 1e6 / max(info["iterations"], 1), "iterations": info["iterations"],
+            "attempts": info["attempts"], "final_m": info["final_m"], "rel_err": err, "valid": bool(err <= 1e-10)}
 
 
 def adjoint_leg(aes, torch, synth):

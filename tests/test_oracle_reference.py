@@ -54,3 +54,20 @@ def test_wide_problem_recipe():
     assert np.max(np.abs(s - P["sigma"]) / P["sigma"]) <= 1e-12
     assert np.allclose(P["b"], A.T @ P["y"], rtol=0, atol=1e-12)
     assert np.all((P["lam"] >= 1.0) & (P["lam"] <= 10.0))
+
+
+def test_spectral_error_bound_matches_the_refined_reference():
+    # the residual-based error of the GPU tests (extended residual, spectral inverse) equals the
+    # error against the refined reference, for x far from and close to x*
+    import sys, os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from _helpers import spectral_error
+
+    P = synth.make_problem(3000, 96, "geo:0.98", 1e-4, nrhs=3, seed=8)
+    xr = reference.reference_solution(P["A"], P["b"], P["nu"], spectral=(P["V"], P["sigma"]))
+    rng = np.random.default_rng(1)
+    for scale in (1e-3, 1e-9, 1e-12):
+        x = xr * (1.0 + scale * rng.standard_normal(xr.shape))
+        e_true = reference.rel_error(x, xr)
+        e_est = spectral_error(P["A"], P["b"], P["nu"], P["V"], P["sigma"], x)
+        np.testing.assert_allclose(e_est, e_true, rtol=1e-3)
