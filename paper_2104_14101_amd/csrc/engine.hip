@@ -1126,9 +1126,11 @@ class Solver {
   }
 
   // Step parameters (before every step of the batch).
-  void batch_dyn(BDyn& dy) {
+  // ready: the problem's eager work (initialisation, resize) has completed; otherwise it sits
+  // this step out and takes the next one
+  void batch_dyn(BDyn& dy, bool ready) {
     dy = BDyn{};
-    dy.run = bstate_ == kBStep ? 1 : 0;
+    dy.run = (bstate_ == kBStep && ready) ? 1 : 0;
     if (!dy.run) return;
     dy.thr = bpolyak_ ? blc_ + polyak_log_bound((double)(bt_ + 1 - bI_), bbeta_) : thr_of(blc_, blphi_, bt_, bI_);
     bseq_ += 1.0;
@@ -1170,6 +1172,7 @@ class Solver {
   // Host side of a step (flags: the problem's flag block after the step).  Returns true when
   // the inner solve has ended and the mixed modes need their refinement check.
   bool batch_after(const double* fl) {
+    beager_ = false;
     if (bstate_ != kBStep) return false;
     try {
       for (int i = 0; i < 8; ++i) fl_[i] = fl[i];
@@ -1196,6 +1199,7 @@ class Solver {
         return false;
       }
       // rejected: double m, fresh sketch, restart at x_t
+      beager_ = true;
       bI_ = bt_;
       m_ = std::min<int64_t>(2 * m_, mcap_);
       ++k_;
@@ -1245,6 +1249,8 @@ class Solver {
     return true;
   }
   const double* batch_norms() const { return bnrm_; }
+  // the last batch_after enqueued eager work (a resize and restart)
+  bool batch_eager() const { return beager_; }
 
   // Refinement check (host copy of ||e||^2, ||x||^2 per column): stop when ||e|| <= tol ||x|| / 4.
   void batch_refine(const double* hn) {
@@ -1395,6 +1401,7 @@ class Solver {
   double *bu_ = nullptr, *bt1_ = nullptr, *bw_ = nullptr, *bE_ = nullptr, *bRr_ = nullptr, *bnrm_ = nullptr;
   int* gate_ = nullptr;
   std::vector<int> bact_;
+  bool beager_ = false;
 };
 
 // ---------------------------------------------------------------------------------------
@@ -1499,11 +1506,22 @@ class BatchEngine {
     AES_HIP(hipEventCreateWithFlags(&ready_, hipEventDisableTiming));
     AES_HIP(hipEventRecord(ready_, caller_));
     AES_HIP(hipStreamWaitEvent(s_, ready_, 0));
+    // the eager phases of problem p run on worker stream p % W (default priority) with that
+    // stream's own scratch namespace; the step waits for all of them through events
+    const int W = std::min(np, kWorkers);
+    ws_.assign(W, nullptr);
+    wev_.assign(W, nullptr);
+    for (int w = 0; w < W; ++w) {
+      AES_HIP(hipStreamCreateWithFlags(&ws_[w], hipStreamNonBlocking));
+      AES_HIP(hipEventCreateWithFlags(&wev_[w], hipEventDisableTiming));
+      AES_HIP(hipStreamWaitEvent(ws_[w], ready_, 0));
+    }
     so_.resize(np);
     for (int p = 0; p < np; ++p) {
       aes_options op = o_;
       op.problem = ids_[p];
-      so_[p] = std::make_unique<Solver>(h_, s_, P_[p], op, tol_, "b" + std::to_string(p) + ".", "bs.");
+      so_[p] = std::make_unique<Solver>(h_, ws_[p % W], P_[p], op, tol_, "b" + std::to_string(p) + ".",
+                                        "bs" + std::to_string(p % W) + ".");
     }
     // per-problem set-up (eager): casts, the first sketch and factorisation, the initialisation
     for (int p = 0; p < np; ++p) {
@@ -1520,14 +1538,62 @@ class BatchEngine {
     build(np);
     const bool graph = graph_enabled();
     if (graph) capture();
-    std::vector<int> refine;
+    // A problem whose eager work (set-up, resize and restart, refinement sweep) is still running
+    // on its worker stream sits steps out until an event says it is done, so a long resize does
+    // not hold the other problems back; its own sequence of operations is the same either way.
+    AES_HIP(hipEventCreateWithFlags(&sev_, hipEventDisableTiming));
+    pev_.assign(np, nullptr);
+    nev_.assign(np, nullptr);
+    for (int p = 0; p < np; ++p) {
+      AES_HIP(hipEventCreateWithFlags(&pev_[p], hipEventDisableTiming));
+      AES_HIP(hipEventCreateWithFlags(&nev_[p], hipEventDisableTiming));
+    }
+    std::vector<char> pending(np, 0), refine_wait(np, 0);
+    auto mark_eager = [&](int p) {
+      AES_HIP(hipEventRecord(pev_[p], ws_[p % ws_.size()]));
+      pending[p] = 1;
+    };
+    auto start_refine = [&](int p) {
+      // ||e||^2, ||x||^2 of the finished inner solve, copied to the host behind its eager work
+      hipStream_t w = ws_[p % ws_.size()];
+      AES_HIP(hipMemcpyAsync(hnrm_ + 64 * p, so_[p]->batch_norms(), 2 * so_[p]->batch_C() * sizeof(double),
+                             hipMemcpyDeviceToHost, w));
+      AES_HIP(hipEventRecord(nev_[p], w));
+      refine_wait[p] = 1;
+    };
+    for (int p = 0; p < np; ++p) mark_eager(p);
     for (;;) {
-      refine.clear();
-      bool any = false;
+      bool any = false, waiting = false;
       for (int p = 0; p < np; ++p) {
-        if (so_[p]->batch_precheck()) refine.push_back(p);
-        so_[p]->batch_dyn(hdyn_[p]);
+        if (refine_wait[p]) {
+          const hipError_t q = hipEventQuery(nev_[p]);
+          if (q == hipSuccess) {
+            refine_wait[p] = 0;
+            so_[p]->batch_refine(hnrm_ + 64 * p);
+            if (so_[p]->bstate() == Solver::kBStep) mark_eager(p);
+          } else if (q != hipErrorNotReady) {
+            AES_HIP(q);
+          }
+        }
+        if (so_[p]->batch_precheck()) {
+          mark_eager(p);
+          start_refine(p);
+        }
+        bool ready = true;
+        if (so_[p]->bstate() == Solver::kBStep && pending[p]) {
+          const hipError_t q = hipEventQuery(pev_[p]);
+          if (q == hipSuccess) {
+            pending[p] = 0;
+            AES_HIP(hipStreamWaitEvent(s_, pev_[p], 0));  // orders the step after it (complete already)
+          } else if (q == hipErrorNotReady) {
+            ready = false;
+          } else {
+            AES_HIP(q);
+          }
+        }
+        so_[p]->batch_dyn(hdyn_[p], ready);
         any = any || hdyn_[p].run != 0;
+        waiting = waiting || refine_wait[p] || (so_[p]->bstate() == Solver::kBStep && !ready);
       }
       if (any) {
         AES_HIP(hipMemcpyAsync(ddyn_, hdyn_, np * sizeof(BDyn), hipMemcpyHostToDevice, s_));
@@ -1536,28 +1602,41 @@ class BatchEngine {
         else
           enqueue_step();
         AES_HIP(hipMemcpyAsync(hflags_, dflags_, (size_t)np * 8 * sizeof(double), hipMemcpyDeviceToHost, s_));
+        AES_HIP(hipEventRecord(sev_, s_));
         AES_HIP(hipStreamSynchronize(s_));
         ++steps_;
-        for (int p = 0; p < np; ++p)
-          if (hdyn_[p].run && so_[p]->batch_after(hflags_ + 8 * p)) refine.push_back(p);
-      }
-      if (!refine.empty()) {
-        for (int p : refine)
-          AES_HIP(hipMemcpyAsync(hnrm_ + 64 * p, so_[p]->batch_norms(), 2 * so_[p]->batch_C() * sizeof(double),
-                                 hipMemcpyDeviceToHost, s_));
-        AES_HIP(hipStreamSynchronize(s_));
-        for (int p : refine) so_[p]->batch_refine(hnrm_ + 64 * p);
+        // eager work enqueued from here on is ordered after the step on every worker stream
+        for (hipStream_t w : ws_) AES_HIP(hipStreamWaitEvent(w, sev_, 0));
+        for (int p = 0; p < np; ++p) {
+          if (!hdyn_[p].run) continue;
+          const bool refine_now = so_[p]->batch_after(hflags_ + 8 * p);
+          if (so_[p]->batch_eager()) mark_eager(p);
+          if (refine_now) start_refine(p);
+        }
+        continue;
       }
       bool all_done = true;
       for (int p = 0; p < np; ++p) all_done = all_done && so_[p]->bstate() == Solver::kBDone;
       if (all_done) break;
-      if (!any && refine.empty()) throw HipError("batched solve made no progress");
+      if (!waiting) throw HipError("batched solve made no progress");
+      // nothing can step: wait for the earliest outstanding eager work
+      for (int p = 0; p < np; ++p) {
+        if (refine_wait[p]) {
+          AES_HIP(hipEventSynchronize(nev_[p]));
+          break;
+        }
+        if (so_[p]->bstate() == Solver::kBStep && pending[p]) {
+          AES_HIP(hipEventSynchronize(pev_[p]));
+          break;
+        }
+      }
     }
     aes_status worst = AES_OK;
     for (int p = 0; p < np; ++p) {
       const aes_status st = so_[p]->batch_result(infos ? &infos[p] : nullptr, t0);
       if (st != AES_OK && worst == AES_OK) worst = st;
     }
+    for (hipStream_t w : ws_) AES_HIP(hipStreamSynchronize(w));
     AES_HIP(hipStreamSynchronize(s_));
     return worst;
   }
@@ -1565,6 +1644,16 @@ class BatchEngine {
   int64_t steps() const { return steps_; }
 
  private:
+  static constexpr int kWorkers = 8;
+
+  // the step stream waits for the eager work enqueued on every worker stream
+  void join_workers() {
+    for (size_t w = 0; w < ws_.size(); ++w) {
+      AES_HIP(hipEventRecord(wev_[w], ws_[w]));
+      AES_HIP(hipStreamWaitEvent(s_, wev_[w], 0));
+    }
+  }
+
   static bool graph_enabled() {
     const char* e = std::getenv("AES_BATCH_GRAPH");
     return !(e && e[0] == '0');
@@ -1611,6 +1700,7 @@ class BatchEngine {
       }
       for (int64_t t = 0; t < ceil_div(d, 64); ++t) tiles.push_back(BWork{p, (int32_t)t});
     }
+    join_workers();  // the descriptors point at buffers the set-up initialised
     AES_HIP(hipMemcpyAsync(dprob_, hp.data(), np * sizeof(BProb), hipMemcpyHostToDevice, s_));
     auto upload = [&](const std::vector<BWork>& v, const char* name) -> BWork* {
       if (v.empty()) return nullptr;
@@ -1671,6 +1761,8 @@ class BatchEngine {
   }
 
   void cleanup() {
+    for (hipStream_t w : ws_)
+      if (w) (void)hipStreamSynchronize(w);
     if (s_) (void)hipStreamSynchronize(s_);
     if (exec_) (void)hipGraphExecDestroy(exec_);
     exec_ = nullptr;
@@ -1683,6 +1775,20 @@ class BatchEngine {
     hnrm_ = nullptr;
     if (ready_) (void)hipEventDestroy(ready_);
     ready_ = nullptr;
+    for (hipEvent_t e : wev_)
+      if (e) (void)hipEventDestroy(e);
+    wev_.clear();
+    if (sev_) (void)hipEventDestroy(sev_);
+    sev_ = nullptr;
+    for (hipEvent_t e : pev_)
+      if (e) (void)hipEventDestroy(e);
+    pev_.clear();
+    for (hipEvent_t e : nev_)
+      if (e) (void)hipEventDestroy(e);
+    nev_.clear();
+    for (hipStream_t w : ws_)
+      if (w) (void)hipStreamDestroy(w);
+    ws_.clear();
     if (s_) (void)hipStreamDestroy(s_);
     s_ = nullptr;
   }
@@ -1695,6 +1801,10 @@ class BatchEngine {
   std::vector<int32_t> ids_;
   hipStream_t s_ = nullptr;
   hipEvent_t ready_ = nullptr;
+  std::vector<hipStream_t> ws_;
+  std::vector<hipEvent_t> wev_;
+  std::vector<hipEvent_t> pev_, nev_;  // per problem: end of its eager work; its norms on the host
+  hipEvent_t sev_ = nullptr;           // end of the last step
   hipGraphExec_t exec_ = nullptr;
   std::vector<std::unique_ptr<Solver>> so_;
   bool fp32_ = false, ihs_ = false;

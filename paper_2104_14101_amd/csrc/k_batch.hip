@@ -671,10 +671,11 @@ __global__ __launch_bounds__(kVT) void bfinish_kernel(const BProb* __restrict__ 
   }
 }
 
-// Flag blocks of every problem (whether or not it stepped) into the packed host-read array.
-__global__ void bflags_kernel(const BProb* __restrict__ probs, int nprob) {
+// Flag blocks of the problems that took part in the step (whether the step ran or their
+// initialisation had closed the gate) into the packed host-read array.
+__global__ void bflags_kernel(const BProb* __restrict__ probs, const BDyn* __restrict__ dyn, int nprob) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nprob) return;
+  if (p >= nprob || !dyn[p].run) return;
   const BProb& P = probs[p];
   if (!P.scal || !P.flags_out) return;  // a problem whose set-up failed
   for (int i = 0; i < 8; ++i) P.flags_out[i] = P.scal[7 * P.C + i];
@@ -686,7 +687,7 @@ void launch_bfinish(const BProb* probs, const BDyn* dyn, int nprob, bool ihs, hi
   else
     hipLaunchKernelGGL(bfinish_kernel<false>, dim3((unsigned)nprob), dim3(kVT), 0, s, probs, dyn);
   AES_LAUNCH_CHECK();
-  hipLaunchKernelGGL(bflags_kernel, dim3((unsigned)ceil_div(nprob, 64)), dim3(64), 0, s, probs, nprob);
+  hipLaunchKernelGGL(bflags_kernel, dim3((unsigned)ceil_div(nprob, 64)), dim3(64), 0, s, probs, dyn, nprob);
   AES_LAUNCH_CHECK();
 }
 
