@@ -255,6 +255,18 @@ aes_status aes_hv(aes_handle h, void* stream, int64_t n, int64_t d, const double
 aes_status aes_hv_noalloc(aes_handle h, void* stream, int64_t n, int64_t d, const double* A, int64_t lda,
                           double nu, const double* lambda, const double* p, double* q, double* pHp);
 
+/* Tuner of the batched step's product A^T (A P) (the matrix-variable solves of Sec. 5): the average
+ * time in milliseconds (*ms, host) of the grouped product for one n x d problem with
+ * c <= 32 columns under a given plan, over `reps` launches after a warm-up launch.
+ *   precision  AES_FP64 (the FP64 matrix) or AES_MIXED_FP32 (its FP32 copy, as the mixed modes)
+ *   twopass    0: the fused single-read form (needs d <= 2048 in FP32, d <= 1024 in FP64, rows
+ *              of A 16-byte aligned); 1: the two-pass form
+ *   rows       rows of A per partial product (a multiple of 16)
+ * The plans the library uses come from the file the tuning script writes (one per precision,
+ * ceil(log2 n) and ceil(d / 256)); asynchronous work is complete when the call returns. */
+aes_status aes_tune_hp(aes_handle h, void* stream, int64_t n, int64_t d, int64_t c, const double* A, int64_t lda,
+                       int precision, int twopass, int64_t rows, int reps, double* ms);
+
 /* Q = A^T (A P) + nu^2 Lambda P for c right-hand sides (P, Q device d x c, ld = c, c a power of
  * two <= 32) -- the per-step product of the matrix-variable solves (Sec. 5).  precision
  * AES_FP64: FP64 MFMA; AES_MIXED / AES_MIXED_FP32: A rounded to FP32 and FP32 MFMA products

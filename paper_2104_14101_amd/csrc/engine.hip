@@ -1067,6 +1067,17 @@ class Solver {
   // r = b - H x with the FP64 matrix (the refinement residual)
   void residual_fp64(const double* x, const double* b, double* r) { hv(x, r, -1.0, b, 1.0, false); }
 
+  // Set-up for timing the grouped H.P alone (no sketch, no solve): buffers and an open gate.
+  void batch_tune_setup() {
+    setup_common();
+    gate_ = B<int>("gate", 1);
+    bx_ = X_;
+    brhs_ = Bv_;
+    launch_fill(X_, d_ * C_, 0.0, s_);
+    launch_fill(Pv_, d_ * C_, 1.0, s_);
+    AES_HIP(hipMemsetAsync(gate_, 0xff, sizeof(int), s_));  // nonzero: the gate is open
+  }
+
   bool batch_fp32() const { return mixed_; }
   bool batch_ihs() const { return bihs_; }
   int64_t batch_n() const { return n_; }
@@ -1642,6 +1653,77 @@ class BatchEngine {
   }
 
   int64_t steps() const { return steps_; }
+
+  // Average time (ms) of the grouped H.P (prep, products, column sums) of one problem under a
+  // given plan, over `reps` launches after one warm-up launch.  For the tuner of the plans.
+  double time_hp(const HpPlan& plan, int reps) {
+    AES_HIP(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
+    AES_HIP(hipEventCreateWithFlags(&ready_, hipEventDisableTiming));
+    AES_HIP(hipEventRecord(ready_, caller_));
+    AES_HIP(hipStreamWaitEvent(s_, ready_, 0));
+    so_.resize(1);
+    so_[0] = std::make_unique<Solver>(h_, s_, P_[0], o_, tol_, "tune.", "tune_s.");
+    so_[0]->batch_tune_setup();
+    fp32_ = so_[0]->batch_fp32();
+    np_ = 1;
+    const int64_t n = P_[0].n, d = P_[0].d;
+    const int mb = bhp_fused_mb(!fp32_, d);
+    if (!plan.twopass && mb > bhp_fused_max_mb(!fp32_)) throw StatusError(AES_ERR_INVALID_ARG, "the fused form takes no such d");
+    const int64_t kpad = plan.twopass ? round_up(d, 256) : 256 * (int64_t)mb;
+    const int nrb = (int)ceil_div(n, plan.rows);
+    dflags_ = h_->buf<double>("tune.flags", 8);
+    dprob_ = h_->buf<BProb>("tune.prob", 1);
+    ddyn_ = h_->buf<BDyn>("tune.dyn", 1);
+    BProb hp;
+    so_[0]->batch_fill(hp, dflags_, nrb, plan.rows, plan.twopass, kpad);
+    BDyn dy{};
+    dy.run = 1;
+    std::vector<BWork> work, z, a;
+    if (!plan.twopass) {
+      for (int r = 0; r < nrb; ++r) work.push_back(BWork{0, r});
+    } else {
+      for (int64_t t = 0; t < ceil_div(n, 64); ++t) z.push_back(BWork{0, (int32_t)t});
+      const int64_t ct = ceil_div(d, 64);
+      for (int64_t r = 0; r < nrb; ++r)
+        for (int64_t t = 0; t < ct; ++t) a.push_back(BWork{0, (int32_t)(r * ct + t)});
+    }
+    BWork* dw = work.empty() ? nullptr : h_->buf<BWork>("tune.fw", work.size());
+    BWork* dz = z.empty() ? nullptr : h_->buf<BWork>("tune.zw", z.size());
+    BWork* da = a.empty() ? nullptr : h_->buf<BWork>("tune.aw", a.size());
+    AES_HIP(hipMemcpyAsync(dprob_, &hp, sizeof(BProb), hipMemcpyHostToDevice, s_));
+    AES_HIP(hipMemcpyAsync(ddyn_, &dy, sizeof(BDyn), hipMemcpyHostToDevice, s_));
+    if (dw) AES_HIP(hipMemcpyAsync(dw, work.data(), work.size() * sizeof(BWork), hipMemcpyHostToDevice, s_));
+    if (dz) AES_HIP(hipMemcpyAsync(dz, z.data(), z.size() * sizeof(BWork), hipMemcpyHostToDevice, s_));
+    if (da) AES_HIP(hipMemcpyAsync(da, a.data(), a.size() * sizeof(BWork), hipMemcpyHostToDevice, s_));
+    const int64_t vt = (int64_t)std::max(16, so_[0]->batch_C()) * kpad, dc = d * so_[0]->batch_C();
+    auto once = [&]() {
+      if (fp32_) {
+        launch_bprep<float>(dprob_, ddyn_, 1, vt, false, s_);
+        if (dw) launch_bhp_fused<float>(dprob_, ddyn_, dw, (int)work.size(), mb, s_);
+        if (dz) launch_bhp_twopass<float>(dprob_, ddyn_, dz, (int)z.size(), da, (int)a.size(), s_);
+        launch_bcolsum<float>(dprob_, ddyn_, 1, dc, false, s_);
+      } else {
+        launch_bprep<double>(dprob_, ddyn_, 1, vt, false, s_);
+        if (dw) launch_bhp_fused<double>(dprob_, ddyn_, dw, (int)work.size(), mb, s_);
+        if (dz) launch_bhp_twopass<double>(dprob_, ddyn_, dz, (int)z.size(), da, (int)a.size(), s_);
+        launch_bcolsum<double>(dprob_, ddyn_, 1, dc, false, s_);
+      }
+    };
+    once();
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    AES_HIP(hipEventCreate(&e0));
+    AES_HIP(hipEventCreate(&e1));
+    AES_HIP(hipEventRecord(e0, s_));
+    for (int i = 0; i < reps; ++i) once();
+    AES_HIP(hipEventRecord(e1, s_));
+    AES_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    const hipError_t te = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    AES_HIP(te);
+    return (double)ms / std::max(reps, 1);
+  }
 
  private:
   static constexpr int kWorkers = 8;
@@ -2228,6 +2310,31 @@ aes_status aes_hv(aes_handle h, void* stream, int64_t n, int64_t d, const double
       launch_pcg_candidate(d, 1, spart, nwg, lambda, nu * nu, p, p, p, q, dummy, dummy + d, scal, act, s);
       AES_HIP(hipMemcpyAsync(pHp, scal + 5, sizeof(double), hipMemcpyDeviceToDevice, s));
     }
+  });
+}
+
+aes_status aes_tune_hp(aes_handle h, void* stream, int64_t n, int64_t d, int64_t c, const double* A, int64_t lda,
+                       int precision, int twopass, int64_t rows, int reps, double* ms) {
+  if (!h || !ms) return AES_ERR_INVALID_ARG;
+  return guard(h, [&] {
+    if (n < 1 || d < 1 || c < 1 || c > 32 || lda < d || !A || rows < 16 || rows % 16 || reps < 1)
+      throw StatusError(AES_ERR_INVALID_ARG, "bad arguments (rows a multiple of 16)");
+    if (d > kMaxD) throw StatusError(AES_ERR_INVALID_ARG, "d > 32768 is not supported");
+    if (precision != AES_FP64 && precision != AES_MIXED_FP32) throw StatusError(AES_ERR_INVALID_ARG, "precision");
+    set_device(h);
+    aes_options o;
+    aes_default_options(&o);
+    o.precision = precision;
+    const int C = (int)next_pow2(c);
+    double* b = h->buf<double>("tune.b", (size_t)d * C);
+    double* x = h->buf<double>("tune.x", (size_t)d * C);
+    launch_fill(b, d * C, 0.0, (hipStream_t)stream);
+    HpPlan plan;
+    plan.twopass = twopass != 0;
+    plan.rows = rows;
+    BatchEngine eng(h, (hipStream_t)stream, std::vector<ProblemDesc>{ProblemDesc{n, d, C, A, lda, b, C, 1.0, nullptr, x, C}},
+                    o, 1e-10, std::vector<int32_t>{0});
+    *ms = eng.time_hp(plan, reps);
   });
 }
 

@@ -46,3 +46,30 @@ def test_graph_replays_equal_eager_steps(precision, method):
         xr = reference.reference_solution(probs[p]["A_np"], probs[p]["b_np"], probs[p]["nu"],
                                           spectral=(probs[p]["V"], probs[p]["sigma"]))
         assert np.all(reference.rel_error(xg.cpu().numpy(), xr) <= 1e-10), p
+
+
+def test_tuner_times_plans_and_rejects_inapplicable_ones():
+    import ctypes
+
+    from paper_2104_14101_amd import _binding as B
+
+    lib = B.load()
+    dev = torch.device("cuda:0")
+    h = aes._handle(dev)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    A = torch.randn((4096, 512), dtype=torch.float64, device=dev)
+
+    def t(prec, twopass, rows, d=512, a=A):
+        ms = ctypes.c_double(-1.0)
+        st = lib.aes_tune_hp(h, stream, a.shape[0], d, 32, ctypes.c_void_p(a.data_ptr()), a.shape[1],
+                             B.PRECISIONS[prec], twopass, rows, 3, ctypes.byref(ms))
+        return st, ms.value
+
+    for prec in ("fp64", "mixed_fp32"):
+        for twopass in (0, 1):
+            st, ms = t(prec, twopass, 256)
+            assert st == B.AES_OK and ms > 0.0
+    wide = torch.randn((512, 1536), dtype=torch.float64, device=dev)
+    assert t("fp64", 0, 256, 1536, wide)[0] == B.AES_ERR_INVALID_ARG   # fused FP64 takes d <= 1024
+    assert t("fp64", 1, 256, 1536, wide)[0] == B.AES_OK
+    assert t("fp64", 0, 24)[0] == B.AES_ERR_INVALID_ARG                # rows not a multiple of 16
