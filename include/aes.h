@@ -255,6 +255,17 @@ aes_status aes_hv(aes_handle h, void* stream, int64_t n, int64_t d, const double
 aes_status aes_hv_noalloc(aes_handle h, void* stream, int64_t n, int64_t d, const double* A, int64_t lda,
                           double nu, const double* lambda, const double* p, double* q, double* pHp);
 
+/* r = b - A^T (A x) - nu^2 Lambda x -- the explicit residual of Algorithm 2 ("compute
+ * r_t = b - H x_t"), as the refinement sweeps of the mixed-precision and batched solves form it:
+ * in compensated FP64 (every product split exactly by fma, every sum carried as an unevaluated
+ * pair), rounded to FP64 once, so its error is about one rounding of r plus (n + d) u^2 times
+ * |A|^T |A| |x| instead of (n + d) u |A|^T |A| |x|.  Two reads of A.
+ *   A device n x d (lda); b, x device d x c (ldb, ldx); r device d x c output (ldr); c <= 32;
+ *   lambda device length d or NULL; nu >= 0.  Asynchronous on `stream`. */
+aes_status aes_residual(aes_handle h, void* stream, int64_t n, int64_t d, int64_t c, const double* A, int64_t lda,
+                        const double* b, int64_t ldb, double nu, const double* lambda, const double* x, int64_t ldx,
+                        double* r, int64_t ldr);
+
 /* Tuner of the batched step's product A^T (A P) (the matrix-variable solves of Sec. 5): the average
  * time in milliseconds (*ms, host) of the grouped product for one n x d problem with
  * c <= 32 columns under a given plan, over `reps` launches after a warm-up launch.

@@ -71,6 +71,8 @@ _PROTOS = {
                        c_void_p]),
     "aes_hv_noalloc": (c_int, [c_void_p, c_void_p, c_int64, c_int64, c_void_p, c_int64, c_double, c_void_p, c_void_p,
                                c_void_p, c_void_p]),
+    "aes_residual": (c_int, [c_void_p, c_void_p, c_int64, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_int64,
+                             c_double, c_void_p, c_void_p, c_int64, c_void_p, c_int64]),
     "aes_tune_hp": (c_int, [c_void_p, c_void_p, c_int64, c_int64, c_int64, c_void_p, c_int64, c_int, c_int, c_int64,
                             c_int, POINTER(c_double)]),
     "aes_hv_multi": (c_int, [c_void_p, c_void_p, c_int64, c_int64, c_int64, c_void_p, c_int64, c_double, c_void_p,

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT, "libaes.so")
-SOURCES = ["k_hv.hip", "k_vec.hip", "k_sketch.hip", "k_sjlt.hip", "k_dense.hip", "k_batch.hip", "noalloc.hip", "engine.hip"]
+SOURCES = ["k_hv.hip", "k_vec.hip", "k_sketch.hip", "k_sjlt.hip", "k_dense.hip", "k_batch.hip", "k_resid.hip", "noalloc.hip", "engine.hip"]
 ARCH = os.environ.get("AES_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -887,11 +887,11 @@ class Solver {
     std::vector<double> hn(2 * C_);
     for (int sweep = 0; sweep < std::max(1, o_.max_refine); ++sweep) {
       ++sweeps_;
-      // r = b - H x in FP64 (one pass over the FP64 A)
+      // r = b - H x with the FP64 matrix, compensated
       if (x_zero)
         AES_HIP(hipMemcpyAsync(Rr, Bv_, dc * sizeof(double), hipMemcpyDeviceToDevice, s_));
       else
-        hv(X_, Rr, -1.0, Bv_, 1.0, false);
+        residual_fp64(X_, Bv_, Rr);
       AES_HIP(hipMemsetAsync(E, 0, dc * sizeof(double), s_));
       AES_HIP(hipMemcpyAsync(active_, act.data(), C_ * sizeof(int), hipMemcpyHostToDevice, s_));
       aes_status st = adaptive(Rr, E, true, true, AES_STOP_XREL, inner_scale, !first);
@@ -1064,8 +1064,18 @@ class Solver {
     inner_begin(bRr_, bE_, true, true, AES_STOP_XREL, binner_scale_, !first);
   }
 
-  // r = b - H x with the FP64 matrix (the refinement residual)
-  void residual_fp64(const double* x, const double* b, double* r) { hv(x, r, -1.0, b, 1.0, false); }
+  // r = b - H x with the FP64 matrix in compensated arithmetic (the refinement residual: the
+  // explicit residual of Algorithm 2 formed as in twice the working precision); two reads of A
+  void residual_fp64(const double* x, const double* b, double* r) {
+    double* zh = S<double>("rz_h", (size_t)n_ * C_);
+    double* zl = S<double>("rz_l", (size_t)n_ * C_);
+    const size_t pe = residual_dd_part_elems(h_->num_cu, n_, d_, C_);
+    double* ph = S<double>("rp_h", pe);
+    double* pl = S<double>("rp_l", pe);
+    launch_residual_dd(h_->num_cu, n_, d_, C_, P_.A, P_.lda, b, C_, P_.nu, P_.lambda ? lam_ : nullptr, x, zh, zl, ph,
+                       pl, r, C_, s_);
+    a_passes_ += 2;
+  }
 
   // Set-up for timing the grouped H.P alone (no sketch, no solve): buffers and an open gate.
   void batch_tune_setup() {
@@ -2310,6 +2320,31 @@ aes_status aes_hv(aes_handle h, void* stream, int64_t n, int64_t d, const double
       launch_pcg_candidate(d, 1, spart, nwg, lambda, nu * nu, p, p, p, q, dummy, dummy + d, scal, act, s);
       AES_HIP(hipMemcpyAsync(pHp, scal + 5, sizeof(double), hipMemcpyDeviceToDevice, s));
     }
+  });
+}
+
+aes_status aes_residual(aes_handle h, void* stream, int64_t n, int64_t d, int64_t c, const double* A, int64_t lda,
+                        const double* b, int64_t ldb, double nu, const double* lambda, const double* x, int64_t ldx,
+                        double* r, int64_t ldr) {
+  if (!h) return AES_ERR_INVALID_ARG;
+  return guard(h, [&] {
+    if (n < 1 || d < 1 || c < 1 || c > 32 || lda < d || ldb < c || ldx < c || ldr < c || !A || !b || !x || !r ||
+        !(std::isfinite(nu) && nu >= 0))
+      throw StatusError(AES_ERR_INVALID_ARG, "bad arguments");
+    set_device(h);
+    hipStream_t s = (hipStream_t)stream;
+    const int C = (int)next_pow2(c);
+    // x and b into C-column blocks (zero padding columns), the residual back to the caller's layout
+    double* xc = h->buf<double>("res.x", (size_t)d * C);
+    double* bc = h->buf<double>("res.b", (size_t)d * C);
+    double* rc = h->buf<double>("res.r", (size_t)d * C);
+    launch_copy_cols(d, C, x, ldx, (int)c, xc, C, s);
+    launch_copy_cols(d, C, b, ldb, (int)c, bc, C, s);
+    const size_t pe = residual_dd_part_elems(h->num_cu, n, d, C);
+    launch_residual_dd(h->num_cu, n, d, C, A, lda, bc, C, nu, lambda, xc, h->buf<double>("res.zh", (size_t)n * C),
+                       h->buf<double>("res.zl", (size_t)n * C), h->buf<double>("res.ph", pe),
+                       h->buf<double>("res.pl", pe), rc, C, s);
+    launch_copy_cols(d, (int)c, rc, C, (int)c, r, ldr, s);
   });
 }
 

@@ -208,4 +208,13 @@ hipError_t noalloc_init(int device);
 void hv_noalloc(int device, int num_cu, hipStream_t s, int64_t n, int64_t d, const double* A, int64_t lda, double nu,
                 const double* lambda, const double* p, double* q, double* pHp);
 
+// ---- compensated explicit residual (k_resid.hip) -----------------------------------------
+// r = b - A^T (A x) - nu^2 Lambda x for C columns (x, b, r: d x C with leading dimensions C, ldb,
+// ldr), formed in double-double arithmetic and rounded once.  Scratch: zh, zl (n x C) and ph, pl
+// (residual_dd_part_elems doubles each).  lam: device or NULL (identity).
+size_t residual_dd_part_elems(int num_cu, int64_t n, int64_t d, int C);
+void launch_residual_dd(int num_cu, int64_t n, int64_t d, int C, const double* A, int64_t lda, const double* b,
+                        int64_t ldb, double nu, const double* lam, const double* x, double* zh, double* zl, double* ph,
+                        double* pl, double* r, int64_t ldr, hipStream_t s);
+
 }  // namespace aes

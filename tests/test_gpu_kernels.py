@@ -9,7 +9,7 @@ from oracle import factor as ofac
 from oracle import philox
 from oracle import sketch as osk
 
-from _helpers import hv_bound, to_dev
+from _helpers import U, hv_bound, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -222,3 +222,90 @@ def test_philox_streams_on_device_match_oracle():
     np.testing.assert_array_equal(SA, ref)
     eps = philox.signs(2**63 + 5, 7, n, problem=3)
     assert np.all(np.sign(SA[0]) == np.sign(ref[0])) and set(np.unique(eps)) <= {-1.0, 1.0}
+
+
+@pytest.mark.parametrize("n,d,c,nu,with_lam", [(16384, 2048, 4, 1e-4, False), (3000, 257, 1, 1e-3, True),
+                                               (777, 96, 32, 1e-2, True)])
+def test_compensated_residual_matches_the_extended_oracle(n, d, c, nu, with_lam):
+    # near the solution b - H x is a tiny difference of terms of the size of H x (kappa(H) ~ 1e8
+    # for the first, batched-workload-like shape): the compensated FP64 residual agrees with the
+    # oracle's 64-bit-significand one to within their rounding bounds, which plain FP64 misses
+    from oracle import reference
+
+    P = synth.make_problem(n, d, "geo:0.98", nu, nrhs=c, seed=31, lam="uniform1_10" if with_lam else "identity")
+    A, b = P["A"], P["b"].reshape(d, c)
+    lam = P["lam"] if with_lam else None
+    xr = reference.reference_solution(A, b, nu, lam)
+    x = xr * (1.0 + 1e-12 * np.random.default_rng(2).standard_normal(xr.shape))
+    r_ref = reference.residual_extended(A, b, nu, lam, x)
+    rd = torch.empty((d, c), dtype=torch.float64, device="cuda")
+    from paper_2104_14101_amd import _binding as B
+    import ctypes
+
+    h = aes._handle(torch.device("cuda:0"))
+    At, bt, xt = to_dev(A), to_dev(b), to_dev(x)
+    lt = to_dev(lam) if with_lam else None
+    st = B.load().aes_residual(h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), n, d, c,
+                               ctypes.c_void_p(At.data_ptr()), d, ctypes.c_void_p(bt.data_ptr()), c, nu,
+                               ctypes.c_void_p(lt.data_ptr() if lt is not None else 0),
+                               ctypes.c_void_p(xt.data_ptr()), c, ctypes.c_void_p(rd.data_ptr()), c)
+    assert st == B.AES_OK
+    torch.cuda.synchronize()
+    r_gpu = rd.cpu().numpy()
+    lamv = np.ones(d) if lam is None else lam
+    mag = np.abs(A).T @ (np.abs(A) @ np.abs(x)) + nu ** 2 * lamv[:, None] * np.abs(x) + np.abs(b)
+    k = n + d + 8
+    uld = 2.0 ** -64
+    bound = 2 * U * np.abs(r_ref.astype(np.float64)) + 2 * k * uld * mag + 4 * k * U * U * mag
+    err = np.abs(r_gpu - r_ref.astype(np.float64))
+    assert np.all(err <= bound), float(np.max(err / bound))
+
+
+
+def _residual_gpu(A, b, nu, lam, x):
+    import ctypes
+
+    from paper_2104_14101_amd import _binding as B
+
+    n, d = A.shape
+    c = b.shape[1]
+    rd = torch.empty((d, c), dtype=torch.float64, device="cuda")
+    At, bt, xt = to_dev(A), to_dev(b), to_dev(x)
+    lt = to_dev(lam) if lam is not None else None
+    h = aes._handle(torch.device("cuda:0"))
+    st = B.load().aes_residual(h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), n, d, c,
+                               ctypes.c_void_p(At.data_ptr()), d, ctypes.c_void_p(bt.data_ptr()), c, nu,
+                               ctypes.c_void_p(lt.data_ptr() if lt is not None else 0),
+                               ctypes.c_void_p(xt.data_ptr()), c, ctypes.c_void_p(rd.data_ptr()), c)
+    assert st == B.AES_OK
+    torch.cuda.synchronize()
+    return rd.cpu().numpy()
+
+
+def test_compensated_residual_within_one_rounding_of_the_exact_value():
+    # exact rational arithmetic on a small problem near its solution (the residual is ~1e-12 of
+    # the terms it is the difference of): the compensated result is the exact residual rounded,
+    # up to (n + d) u^2 of the terms' magnitude; the plain FP64 evaluation is not
+    from fractions import Fraction
+
+    rng = np.random.default_rng(5)
+    n, d, c, nu = 200, 48, 2, 1e-3
+    A = rng.standard_normal((n, d)) * np.exp(-0.15 * np.arange(d))
+    lam = 1.0 + rng.random(d)
+    b = A.T @ rng.standard_normal((n, c))
+    x = np.linalg.solve(A.T @ A + nu ** 2 * np.diag(lam), b)
+    Af = [[Fraction(v) for v in row] for row in A]
+    xf = [[Fraction(v) for v in row] for row in x]
+    nu2 = Fraction(nu) ** 2
+    r_exact = np.empty((d, c))
+    for cc in range(c):
+        z = [sum(Af[i][k] * xf[k][cc] for k in range(d)) for i in range(n)]
+        for j in range(d):
+            q = sum(Af[i][j] * z[i] for i in range(n)) + nu2 * Fraction(lam[j]) * xf[j][cc]
+            r_exact[j, cc] = float(Fraction(b[j, cc]) - q)
+    mag = np.abs(A).T @ (np.abs(A) @ np.abs(x)) + nu ** 2 * lam[:, None] * np.abs(x) + np.abs(b)
+    bound = U * np.abs(r_exact) + 8 * (n + d) * U * U * mag
+    r_gpu = _residual_gpu(A, b, nu, lam, x)
+    assert np.all(np.abs(r_gpu - r_exact) <= bound), float(np.max(np.abs(r_gpu - r_exact) / bound))
+    r_plain = b - A.T @ (A @ x) - nu ** 2 * lam[:, None] * x
+    assert np.any(np.abs(r_plain - r_exact) > 100 * bound)
