@@ -41,6 +41,14 @@ __device__ __forceinline__ void dd_add(double& hi, double& lo, double bh, double
   e = e + (lo + bl);
   fast_two_sum(s, e, hi, lo);
 }
+// (hi, lo) = (ah, al) + (hi, lo): the same operation with the operands in the other order, so
+// that two lanes exchanging their pairs compute bit-identical sums
+__device__ __forceinline__ void dd_add2(double ah, double al, double& hi, double& lo) {
+  double s, e;
+  two_sum(ah, hi, s, e);
+  e = e + (al + lo);
+  fast_two_sum(s, e, hi, lo);
+}
 // (hi, lo) += a * (zh + zl): the product a zh exactly, a zl to working precision
 __device__ __forceinline__ void dd_fma(double& hi, double& lo, double a, double zh, double zl) {
   double p, pe;
@@ -136,7 +144,85 @@ __global__ __launch_bounds__(kRT) void resid_combine_kernel(int64_t d, int C, in
   r[j * ldr + c] = rh + rl;
 }
 
+// Single-pass form for one column (d <= 4096, rows 16-byte aligned): a workgroup of 4 waves owns
+// rows r0, r0 + G, ... (G workgroups); thread t owns the columns (j 256 + t) 2 + {0, 1}, j < NCH,
+// keeps x for them and its partial A^T z as pairs in registers; each row's z = A_i x is reduced
+// as pairs over the wave (butterfly) and the four waves (LDS, fixed order), then
+// (part_hi, part_lo)[w][j] += A_ij z_i.  A is read once.
+template <int NCH>
+__global__ __launch_bounds__(kRT) void resid_fused_kernel(int64_t n, int d, const double* __restrict__ A, int64_t lda,
+                                                          const double* __restrict__ x, double* __restrict__ ph,
+                                                          double* __restrict__ pl) {
+  typedef double dv2 __attribute__((ext_vector_type(2)));
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  __shared__ double redh[2][4], redl[2][4];
+  double xv[NCH][2], qh[NCH][2], ql[NCH][2];
+#pragma unroll
+  for (int j = 0; j < NCH; ++j)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int col = (j * kRT + tid) * 2 + e;
+      xv[j][e] = col < d ? x[col] : 0.0;
+      qh[j][e] = ql[j][e] = 0.0;
+    }
+  int buf = 0;
+  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const double* Ai = A + i * lda;
+    dv2 a[NCH];
+#pragma unroll
+    for (int j = 0; j < NCH; ++j) {
+      const int col = (j * kRT + tid) * 2;
+      a[j] = col < d ? __builtin_nontemporal_load(reinterpret_cast<const dv2*>(Ai + col)) : dv2{0.0, 0.0};
+    }
+    double hi = 0.0, lo = 0.0;
+#pragma unroll
+    for (int j = 0; j < NCH; ++j)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) dd_fma(hi, lo, a[j][e], xv[j][e], 0.0);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double oh = __shfl_xor(hi, off, 64), ol = __shfl_xor(lo, off, 64);
+      // both partners form the same pair sum (operands ordered by lane) so every lane ends equal
+      if (lane & off)
+        dd_add2(oh, ol, hi, lo);
+      else
+        dd_add(hi, lo, oh, ol);
+    }
+    if (lane == 0) {
+      redh[buf][wid] = hi;
+      redl[buf][wid] = lo;
+    }
+    __syncthreads();
+    double zh = redh[buf][0], zl = redl[buf][0];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) dd_add(zh, zl, redh[buf][w], redl[buf][w]);
+    buf ^= 1;
+#pragma unroll
+    for (int j = 0; j < NCH; ++j)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) dd_fma(qh[j][e], ql[j][e], a[j][e], zh, zl);
+  }
+  const int64_t base = (int64_t)blockIdx.x * d;
+#pragma unroll
+  for (int j = 0; j < NCH; ++j)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int col = (j * kRT + tid) * 2 + e;
+      if (col < d) {
+        ph[base + col] = qh[j][e];
+        pl[base + col] = ql[j][e];
+      }
+    }
+}
+
 }  // namespace
+
+// Workgroups of the single-pass form (each writes a d-length partial pair).
+constexpr int kResidFusedWG = 512;
+
+bool residual_dd_fused_ok(int64_t d, int C, const double* A, int64_t lda) {
+  return C == 1 && d <= 4096 && d % 2 == 0 && lda % 2 == 0 && ((uintptr_t)A & 15) == 0;
+}
 
 int resid_blocks(int num_cu, int64_t n, int64_t d, int C, int64_t* rows) {
   const int64_t tiles = ceil_div(d, (int64_t)(kRT / C) * 8);
@@ -150,6 +236,29 @@ int resid_blocks(int num_cu, int64_t n, int64_t d, int C, int64_t* rows) {
 void launch_residual_dd(int num_cu, int64_t n, int64_t d, int C, const double* A, int64_t lda, const double* b,
                         int64_t ldb, double nu, const double* lam, const double* x, double* zh, double* zl, double* ph,
                         double* pl, double* r, int64_t ldr, hipStream_t s) {
+  if (residual_dd_fused_ok(d, C, A, lda)) {
+    const int nwg = (int)std::min<int64_t>(kResidFusedWG, n);
+    const int nch = (int)ceil_div(d, 2 * kRT);
+#define AES_RFUSED(NC)                                                                                        \
+  hipLaunchKernelGGL(resid_fused_kernel<NC>, dim3(nwg), dim3(kRT), 0, s, n, (int)d, A, lda, x, ph, pl); \
+  break;
+    switch (nch <= 1 ? 1 : nch <= 2 ? 2 : nch <= 4 ? 4 : 8) {
+      case 1:
+        AES_RFUSED(1)
+      case 2:
+        AES_RFUSED(2)
+      case 4:
+        AES_RFUSED(4)
+      default:
+        AES_RFUSED(8)
+    }
+#undef AES_RFUSED
+    AES_LAUNCH_CHECK();
+    hipLaunchKernelGGL(resid_combine_kernel, dim3((unsigned)ceil_div(d, kRT)), dim3(kRT), 0, s, d, 1, nwg, ph, pl, b,
+                       ldb, x, lam, nu, r, ldr);
+    AES_LAUNCH_CHECK();
+    return;
+  }
   int64_t rows = 0;
   const int nrb = resid_blocks(num_cu, n, d, C, &rows);
   const unsigned g1 = (unsigned)std::min<int64_t>(ceil_div(n, kRT / 64), 8 * (int64_t)num_cu);
@@ -178,6 +287,7 @@ void launch_residual_dd(int num_cu, int64_t n, int64_t d, int C, const double* A
 }
 
 size_t residual_dd_part_elems(int num_cu, int64_t n, int64_t d, int C) {
+  if (C == 1 && d <= 4096) return std::max<size_t>((size_t)kResidFusedWG * d, 1);
   int64_t rows = 0;
   const int nrb = resid_blocks(num_cu, n, d, C, &rows);
   return (size_t)nrb * d * C;

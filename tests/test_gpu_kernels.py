@@ -224,8 +224,10 @@ def test_philox_streams_on_device_match_oracle():
     assert np.all(np.sign(SA[0]) == np.sign(ref[0])) and set(np.unique(eps)) <= {-1.0, 1.0}
 
 
+# (c = 1 with even d takes the single-pass form, the others the two-pass one)
 @pytest.mark.parametrize("n,d,c,nu,with_lam", [(16384, 2048, 4, 1e-4, False), (3000, 257, 1, 1e-3, True),
-                                               (777, 96, 32, 1e-2, True)])
+                                               (777, 96, 32, 1e-2, True), (20000, 4096, 1, 1e-4, False),
+                                               (5000, 1000, 1, 1e-3, True)])
 def test_compensated_residual_matches_the_extended_oracle(n, d, c, nu, with_lam):
     # near the solution b - H x is a tiny difference of terms of the size of H x (kappa(H) ~ 1e8
     # for the first, batched-workload-like shape): the compensated FP64 residual agrees with the
@@ -282,14 +284,15 @@ def _residual_gpu(A, b, nu, lam, x):
     return rd.cpu().numpy()
 
 
-def test_compensated_residual_within_one_rounding_of_the_exact_value():
+@pytest.mark.parametrize("c", [1, 2])
+def test_compensated_residual_within_one_rounding_of_the_exact_value(c):
     # exact rational arithmetic on a small problem near its solution (the residual is ~1e-12 of
     # the terms it is the difference of): the compensated result is the exact residual rounded,
     # up to (n + d) u^2 of the terms' magnitude; the plain FP64 evaluation is not
     from fractions import Fraction
 
     rng = np.random.default_rng(5)
-    n, d, c, nu = 200, 48, 2, 1e-3
+    n, d, nu = 200, 48, 1e-3
     A = rng.standard_normal((n, d)) * np.exp(-0.15 * np.arange(d))
     lam = 1.0 + rng.random(d)
     b = A.T @ rng.standard_normal((n, c))
