@@ -1,13 +1,18 @@
-// Dense kernels on the FP64 (and BF16) matrix cores of gfx950:
-//   * a tiled GEMM C = alpha op(A) op(B) + beta C (64 x 64 tiles, v_mfma_f64_16x16x4f64),
-//     used for the Gram of the sketch, the Cholesky panels and trailing updates and the
-//     triangular inverse;
-//   * the Gram (SA)^T SA + nu^2 Lambda with split-K, and W = SA Lambda^{-1} SA^T + nu^2 I
-//     (the two factorisation branches of Sec. 4.1);
-//   * a blocked right-looking Cholesky (64 x 64 diagonal blocks factorised in LDS) and the
-//     inverse of its lower-triangular factor;
-//   * the Gaussian sketch S A = G A / sqrt(m) with the N(0,1) tile of G generated on chip
-//     (Philox + Box-Muller) for every K-step, so G is never stored.
+// Dense kernels of the factorisation (Sec. 4.1) and of the Gaussian sketch, on the matrix
+// cores of gfx950:
+//   * gemm_kernel: C = alpha op(A) op(B) + beta C, FP64 (v_mfma_f64_16x16x4f64) or FP32
+//     (v_mfma_f32_16x16x4f32), tiles up to 128 x 128, optional split-K over XCD-local row
+//     ranges and a lower-triangle-only output; the products of the factorisation recursion and
+//     of the Gaussian sketch;
+//   * the Gram of the sketch, G = (SA)^T SA + nu^2 Lambda (m >= d), as split-K partials over
+//     lower-triangle tiles reduced in a fixed order, with an optional BF16 form (FP32
+//     accumulation, v_mfma_f32_32x32x16_bf16), and W = SA Lambda^-1 (SA)^T + nu^2 I (m < d);
+//   * the Cholesky factor L of G and its inverse X = L^-1, by recursion on 2 x 2 block
+//     partitions down to 128 x 128 nodes (one workgroup: two 64 x 64 leaves and three 64-wide
+//     FP64 MFMA products in LDS); in a leaf one wavefront factorises column by column (lane =
+//     row, next pivot updated ahead) while a second one inverts 8 rows behind it;
+//   * the Gaussian sketch S A = G A / sqrt(m), its N(0, 1) entries generated in slabs from a
+//     counter-based generator (Philox-4x64-10, Box-Muller), each exactly once per sketch.
 #include "common.h"
 #include "kernels.h"
 
