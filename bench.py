@@ -34,6 +34,7 @@ Extra legs (outside the timed region of the headline value):
 
 --hv-only runs just fused H.v launches and a calibration copy (for rocprofv3 counter runs);
 --sketch-only M runs just sketches (--sketch kind) of size M of the workload's A.
+--factor-only M runs just factorisations (aes_factor) of an M x d Gaussian sketch.
 """
 import argparse
 import hashlib
@@ -198,6 +199,32 @@ def sketch_only(args):
     print(json.dumps({"sketches": args.steps, "kind": args.sketch, "m": args.sketch_only, "n": w.n, "d": w.d}))
 
 
+def factor_only(args):
+    """aes_factor (Gram of an m x d sketch, Cholesky factor and its inverse) of a Gaussian sketch of
+    the workload's width, with the workload's nu and Lambda = 1 + U[0, 9]; the kernels of the
+    factorisation are the ones a solve runs after each resize (this entry point also copies L back)."""
+    import torch
+
+    import paper_2104_14101_amd as aes
+    import synth
+
+    w = synth.WORKLOADS[args.workload]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(6)
+    m = args.factor_only
+    SA = torch.randn((m, w.d), dtype=torch.float64, device="cuda", generator=g) / m ** 0.5
+    lam = 1.0 + 9.0 * torch.rand(w.d, dtype=torch.float64, device="cuda", generator=g)
+    for _ in range(max(args.warmup, 1)):
+        aes.factor(SA, w.nu, lam)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        aes.factor(SA, w.nu, lam)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    print(json.dumps({"factorisations": args.steps, "m": m, "d": w.d, "ms_per_factor": ms}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -211,6 +238,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--hv-only", action="store_true")
     ap.add_argument("--sketch-only", type=int, default=0, metavar="M")
+    ap.add_argument("--factor-only", type=int, default=0, metavar="M",
+                    help="only aes_factor of an M x d sketch of the workload's width")
     ap.add_argument("--batched", action="store_true", help="with --skip-main: the batched leg")
     ap.add_argument("--adjoint", action="store_true", help="with --skip-main: the autograd leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched leg of the default line")
@@ -242,6 +271,8 @@ def main():
         return hv_only(args)
     if args.sketch_only:
         return sketch_only(args)
+    if args.factor_only:
+        return factor_only(args)
 
     import numpy as np
     import torch

@@ -878,6 +878,7 @@ class Solver {
     double* nrm = B<double>("nrm", 2 * C_);
     bool first = true;
     bool x_zero = !x0;
+    corr_ratio_ = 1.0;
     m_ = std::min<int64_t>(o_.m_init, mcap_);
     k_ = 0;
     const double inner = o_.inner_tol > 0 ? o_.inner_tol : 1e-6;
@@ -887,11 +888,11 @@ class Solver {
     std::vector<double> hn(2 * C_);
     for (int sweep = 0; sweep < std::max(1, o_.max_refine); ++sweep) {
       ++sweeps_;
-      // r = b - H x with the FP64 matrix, compensated
+      // r = b - H x with the FP64 matrix (compensated once x is close)
       if (x_zero)
         AES_HIP(hipMemcpyAsync(Rr, Bv_, dc * sizeof(double), hipMemcpyDeviceToDevice, s_));
       else
-        residual_fp64(X_, Bv_, Rr);
+        refine_residual(X_, Bv_, Rr);
       AES_HIP(hipMemsetAsync(E, 0, dc * sizeof(double), s_));
       AES_HIP(hipMemcpyAsync(active_, act.data(), C_ * sizeof(int), hipMemcpyHostToDevice, s_));
       aes_status st = adaptive(Rr, E, true, true, AES_STOP_XREL, inner_scale, !first);
@@ -904,9 +905,11 @@ class Solver {
       AES_HIP(hipMemcpyAsync(hn.data(), nrm, 2 * C_ * sizeof(double), hipMemcpyDeviceToHost, s_));
       AES_HIP(hipStreamSynchronize(s_));
       bool done = true;
+      corr_ratio_ = 0.0;
       for (int j = 0; j < c_; ++j) {
         const double en = std::sqrt(hn[j]), xn = std::sqrt(hn[C_ + j]);
         const bool ok = en <= 0.25 * tol_ * xn || xn == 0.0;
+        if (act[j] && xn > 0.0) corr_ratio_ = std::max(corr_ratio_, en / xn);
         act[j] = ok ? 0 : 1;
         done = done && ok;
       }
@@ -1054,14 +1057,28 @@ class Solver {
   // One refinement sweep of the mixed modes: r = b - H x in FP64, then the inner solve of H e = r.
   void sweep_begin(bool first) {
     ++sweeps_;
+    if (first) corr_ratio_ = 1.0;
     const int64_t dc = d_ * C_;
     if (bxzero_)
       AES_HIP(hipMemcpyAsync(bRr_, Bv_, dc * sizeof(double), hipMemcpyDeviceToDevice, s_));
     else
-      residual_fp64(X_, Bv_, bRr_);
+      refine_residual(X_, Bv_, bRr_);
     launch_fill(bE_, dc, 0.0, s_);
     AES_HIP(hipMemcpyAsync(active_, bact_.data(), C_ * sizeof(int), hipMemcpyHostToDevice, s_));
     inner_begin(bRr_, bE_, true, true, AES_STOP_XREL, binner_scale_, !first);
+  }
+
+  // The refinement residual r = b - H x with the FP64 matrix.  While the last correction was
+  // larger than kCompensateBelow ||x|| in some column, x is still far from the solution and the
+  // residual far above the rounding error of a plain FP64 product (about d u ||A||^2 ||x||), so the
+  // plain product (one pass) gives all the digits the next inner solve can use; once every column's
+  // correction is below that, the residual is formed in compensated arithmetic.
+  static constexpr double kCompensateBelow = 1e-4;
+  void refine_residual(const double* x, const double* b, double* r) {
+    if (corr_ratio_ > kCompensateBelow)
+      hv(x, r, -1.0, b, 1.0, false);
+    else
+      residual_fp64(x, b, r);
   }
 
   // r = b - H x with the FP64 matrix in compensated arithmetic (the refinement residual: the
@@ -1277,9 +1294,11 @@ class Solver {
   void batch_refine(const double* hn) {
     try {
       bool done = true;
+      corr_ratio_ = 0.0;
       for (int j = 0; j < c_; ++j) {
         const double en = std::sqrt(hn[j]), xn = std::sqrt(hn[C_ + j]);
         const bool ok = en <= 0.25 * tol_ * xn || xn == 0.0;
+        if (bact_[j] && xn > 0.0) corr_ratio_ = std::max(corr_ratio_, en / xn);
         bact_[j] = ok ? 0 : 1;
         done = done && ok;
       }
@@ -1370,6 +1389,8 @@ class Solver {
   ProblemDesc P_;
   aes_options o_;
   double tol_;
+  // largest ||e|| / ||x|| of the last refinement sweep over the columns still refining
+  double corr_ratio_ = 1.0;
   std::string ns_, sns_;
   int64_t n_, d_, c_;
   int C_;

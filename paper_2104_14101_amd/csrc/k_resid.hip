@@ -85,6 +85,55 @@ __global__ __launch_bounds__(kRT) void resid_ax_kernel(int64_t n, int64_t d, con
   }
 }
 
+// pass 1 for C >= 8: a workgroup owns RB = 512 / C consecutive rows; thread t takes column
+// c = t % C of rows t / C and t / C + 256 / C, summing k in increasing order.  K-chunks of 64
+// columns of the row block and the matching 64 rows of x are staged in LDS, so x is read once
+// per RB rows rather than once per row.
+constexpr int kRK = 64;
+template <int C>
+__global__ __launch_bounds__(kRT) void resid_ax_tiled_kernel(int64_t n, int64_t d, const double* __restrict__ A,
+                                                             int64_t lda, const double* __restrict__ x,
+                                                             double* __restrict__ zh, double* __restrict__ zl) {
+  constexpr int TR = kRT / C, RB = 2 * TR;
+  __shared__ double As[RB][kRK + 1];
+  __shared__ double Xs[kRK][C];
+  const int t = threadIdx.x, c = t % C, tr = t / C;
+  const int64_t i0 = (int64_t)blockIdx.x * RB;
+  double h0 = 0.0, l0 = 0.0, h1 = 0.0, l1 = 0.0;
+  for (int64_t k0 = 0; k0 < d; k0 += kRK) {
+    const int kc = (int)(d - k0 < kRK ? d - k0 : kRK);
+    // row block: element e = t + 256 q -> (row e / 64, column e % 64), 512 consecutive bytes per row
+    static_assert(RB * kRK % kRT == 0 && kRK * C % kRT == 0, "tiles: whole rounds of the workgroup");
+#pragma unroll
+    for (int q = 0; q < RB * kRK / kRT; ++q) {
+      const int e = t + kRT * q, r = e / kRK, k = e % kRK;
+      const int64_t i = i0 + r;
+      As[r][k] = (i < n && k < kc) ? A[i * lda + k0 + k] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kRK * C / kRT; ++q) {
+      const int e = t + kRT * q, k = e / C, cc = e % C;
+      Xs[k][cc] = k < kc ? x[(k0 + k) * C + cc] : 0.0;
+    }
+    __syncthreads();
+    for (int k = 0; k < kc; ++k) {
+      const double xv = Xs[k][c];
+      dd_fma(h0, l0, As[tr][k], xv, 0.0);
+      dd_fma(h1, l1, As[tr + TR][k], xv, 0.0);
+    }
+    __syncthreads();
+  }
+  const int64_t ia = i0 + tr, ib = i0 + tr + TR;
+  if (ia < n) {
+    zh[ia * C + c] = h0;
+    zl[ia * C + c] = l0;
+  }
+  if (ib < n) {
+    zh[ib * C + c] = h1;
+    zl[ib * C + c] = l1;
+  }
+}
+
 // pass 2: part[b][j][c] = sum over the rows of block b of A[i][j] (zh + zl)[i][c]; thread t owns
 // column c = t % C and the columns j0 + t / C + J s (J = 256 / C, s < 8) of its tile.
 template <int C>
@@ -104,6 +153,58 @@ __global__ __launch_bounds__(kRT) void resid_atz_kernel(int64_t n, int64_t d, co
 #pragma unroll
     for (int s = 0; s < S; ++s)
       if (j0 + jj + J * s < d) dd_fma(hi[s], lo[s], Ai[J * s], h, l);
+  }
+  const int64_t base = (int64_t)blockIdx.y * d * C;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int64_t j = j0 + jj + J * s;
+    if (j < d) {
+      ph[base + j * C + c] = hi[s];
+      pl[base + j * C + c] = lo[s];
+    }
+  }
+}
+
+// pass 2 for C >= 8, the same sums in the same order with the operands staged in LDS: chunks of
+// RC rows of the workgroup's column tile of A and of (zh, zl) are loaded with coalesced reads (all
+// of a chunk's loads in flight together), then every thread runs its S accumulators over the
+// chunk's rows from LDS.
+template <int C>
+__global__ __launch_bounds__(kRT) void resid_atz_tiled_kernel(int64_t n, int64_t d, const double* __restrict__ A,
+                                                              int64_t lda, const double* __restrict__ zh,
+                                                              const double* __restrict__ zl, int64_t rows,
+                                                              double* __restrict__ ph, double* __restrict__ pl) {
+  constexpr int J = kRT / C, S = 8, W = J * S;  // W columns of A per workgroup
+  constexpr int RC = W <= 128 ? 32 : 16;        // rows per chunk
+  __shared__ double As[RC][W + 1];
+  __shared__ double Zs[2][RC][C];
+  const int t = threadIdx.x, c = t % C, jj = t / C;
+  const int64_t j0 = (int64_t)blockIdx.x * W;
+  const int64_t r0 = (int64_t)blockIdx.y * rows, r1 = r0 + rows < n ? r0 + rows : n;
+  double hi[S], lo[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) hi[s] = lo[s] = 0.0;
+  for (int64_t i0 = r0; i0 < r1; i0 += RC) {
+    const int rc = (int)(r1 - i0 < RC ? r1 - i0 : RC);
+    static_assert(RC * W % kRT == 0, "row chunk of A: whole rounds of the workgroup");
+#pragma unroll
+    for (int q = 0; q < RC * W / kRT; ++q) {
+      const int e = t + kRT * q, r = e / W, j = e % W;
+      As[r][j] = (r < rc && j0 + j < d) ? A[(i0 + r) * lda + j0 + j] : 0.0;
+    }
+    for (int e = t; e < RC * C; e += kRT) {
+      const int r = e / C, cc = e % C;
+      Zs[0][r][cc] = r < rc ? zh[(i0 + r) * C + cc] : 0.0;
+      Zs[1][r][cc] = r < rc ? zl[(i0 + r) * C + cc] : 0.0;
+    }
+    __syncthreads();
+    for (int r = 0; r < rc; ++r) {
+      const double h = Zs[0][r][c], l = Zs[1][r][c];
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+        if (j0 + jj + J * s < d) dd_fma(hi[s], lo[s], As[r][jj + J * s], h, l);
+    }
+    __syncthreads();
   }
   const int64_t base = (int64_t)blockIdx.y * d * C;
 #pragma unroll
@@ -226,7 +327,7 @@ bool residual_dd_fused_ok(int64_t d, int C, const double* A, int64_t lda) {
 
 int resid_blocks(int num_cu, int64_t n, int64_t d, int C, int64_t* rows) {
   const int64_t tiles = ceil_div(d, (int64_t)(kRT / C) * 8);
-  const int64_t want = std::max<int64_t>(1, 4 * (int64_t)num_cu / tiles);
+  const int64_t want = std::max<int64_t>(1, 8 * (int64_t)num_cu / tiles);
   int64_t nrb = std::min<int64_t>(want, ceil_div(n, 64));
   nrb = std::max<int64_t>(1, nrb);
   *rows = ceil_div(n, nrb);
@@ -265,9 +366,17 @@ void launch_residual_dd(int num_cu, int64_t n, int64_t d, int C, const double* A
   const dim3 g2((unsigned)ceil_div(d, (int64_t)(kRT / C) * 8), (unsigned)nrb);
 #define AES_RESID_CASE(CV)                                                                                        \
   case CV:                                                                                                        \
-    hipLaunchKernelGGL(resid_ax_kernel<CV>, dim3(g1), dim3(kRT), 0, s, n, d, A, lda, x, zh, zl);                  \
+    if (CV >= 8)                                                                                                  \
+      hipLaunchKernelGGL(resid_ax_tiled_kernel<(CV >= 8 ? CV : 8)>, dim3((unsigned)ceil_div(n, 512 / (CV >= 8 ? CV : 8))), \
+                         dim3(kRT), 0, s, n, d, A, lda, x, zh, zl);                                               \
+    else                                                                                                          \
+      hipLaunchKernelGGL(resid_ax_kernel<CV>, dim3(g1), dim3(kRT), 0, s, n, d, A, lda, x, zh, zl);                \
     AES_LAUNCH_CHECK();                                                                                           \
-    hipLaunchKernelGGL(resid_atz_kernel<CV>, g2, dim3(kRT), 0, s, n, d, A, lda, zh, zl, rows, ph, pl);            \
+    if (CV >= 8)                                                                                                  \
+      hipLaunchKernelGGL(resid_atz_tiled_kernel<(CV >= 8 ? CV : 8)>, g2, dim3(kRT), 0, s, n, d, A, lda, zh, zl, rows, \
+                         ph, pl);                                                                                 \
+    else                                                                                                          \
+      hipLaunchKernelGGL(resid_atz_kernel<CV>, g2, dim3(kRT), 0, s, n, d, A, lda, zh, zl, rows, ph, pl);          \
     AES_LAUNCH_CHECK();                                                                                           \
     break;
   switch (C) {

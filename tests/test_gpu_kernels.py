@@ -227,7 +227,8 @@ def test_philox_streams_on_device_match_oracle():
 # (c = 1 with even d takes the single-pass form, the others the two-pass one)
 @pytest.mark.parametrize("n,d,c,nu,with_lam", [(16384, 2048, 4, 1e-4, False), (3000, 257, 1, 1e-3, True),
                                                (777, 96, 32, 1e-2, True), (20000, 4096, 1, 1e-4, False),
-                                               (5000, 1000, 1, 1e-3, True)])
+                                               (5000, 1000, 1, 1e-3, True), (4100, 300, 8, 1e-3, False),
+                                               (2050, 520, 16, 1e-2, True)])
 def test_compensated_residual_matches_the_extended_oracle(n, d, c, nu, with_lam):
     # near the solution b - H x is a tiny difference of terms of the size of H x (kappa(H) ~ 1e8
     # for the first, batched-workload-like shape): the compensated FP64 residual agrees with the
@@ -284,7 +285,7 @@ def _residual_gpu(A, b, nu, lam, x):
     return rd.cpu().numpy()
 
 
-@pytest.mark.parametrize("c", [1, 2])
+@pytest.mark.parametrize("c", [1, 2, 8, 16, 32])
 def test_compensated_residual_within_one_rounding_of_the_exact_value(c):
     # exact rational arithmetic on a small problem near its solution (the residual is ~1e-12 of
     # the terms it is the difference of): the compensated result is the exact residual rounded,
