@@ -112,7 +112,11 @@ typedef struct {
   aes_trace_entry* trace;   /* host, optional: filled with the attempted steps */
   const double* x0;         /* device d x c (ld = ldx) initial point, or NULL for 0 */
   int32_t profile;          /* 1: time every fused H.v launch with HIP events on `stream` */
-  int32_t pad_;
+  int32_t keep_fp32_copy;   /* AES_MIXED / AES_MIXED_FP32, default 0.  1: the caller promises that A
+                               is unchanged since the last solve on this handle that cast the same
+                               pointer with the same n, d, lda; the FP32 copy made then (kept in the
+                               handle's pool) is reused instead of cast again.  A changed in place
+                               under this promise gives results for the old A. */
 } aes_options;
 
 typedef struct {

@@ -147,7 +147,7 @@ def _rowmajor(t):
 
 def make_options(method="pcg", sketch="srht", precision="fp64", stop="xrel", rho=0.125, m_init=1, m_max=0,
                  max_iter=200, seed=0, problem=0, adaptive=True, force_reject_at=-1, inner_tol=1e-6, max_refine=20,
-                 trace_cap=0, x0=None, profile=False):
+                 trace_cap=0, x0=None, profile=False, keep_fp32_copy=False):
     o = B.Options()
     _lib().aes_default_options(ctypes.byref(o))
     o.method = B.METHODS[method]
@@ -171,6 +171,7 @@ def make_options(method="pcg", sketch="srht", precision="fp64", stop="xrel", rho
         o.trace_cap = int(trace_cap)
     o.x0 = ctypes.c_void_p(x0.data_ptr()) if x0 is not None else None
     o.profile = 1 if profile else 0
+    o.keep_fp32_copy = 1 if keep_fp32_copy else 0
     return o, buf
 
 
@@ -187,7 +188,8 @@ def solve(A, b, nu, lam=None, tol=1e-10, x=None, check=True, **opts):
 
     b: (d,) or (d, c) with c <= 32.  Options: method, sketch, precision, stop, rho, m_init,
     m_max, max_iter, seed, problem, adaptive, force_reject_at, inner_tol, max_refine,
-    trace_cap (record the attempted steps), x0, profile (event-time the fused H.v kernel).
+    trace_cap (record the attempted steps), x0, profile (event-time the fused H.v kernel),
+    keep_fp32_copy (mixed precision: reuse the handle's FP32 copy of this same, unchanged A).
     """
     _req(A, "A", (2,))
     _req(b, "b", (1, 2))

@@ -30,7 +30,7 @@ class Options(ctypes.Structure):
                 ("rho", c_double), ("m_init", c_int64), ("m_max", c_int64), ("max_iter", c_int64),
                 ("seed", c_uint64), ("problem", c_int32), ("adaptive", c_int32), ("force_reject_at", c_int64),
                 ("inner_tol", c_double), ("max_refine", c_int32), ("trace_cap", c_int32),
-                ("trace", POINTER(TraceEntry)), ("x0", c_void_p), ("profile", c_int32), ("pad_", c_int32)]
+                ("trace", POINTER(TraceEntry)), ("x0", c_void_p), ("profile", c_int32), ("keep_fp32_copy", c_int32)]
 
 
 class Info(ctypes.Structure):

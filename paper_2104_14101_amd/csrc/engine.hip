@@ -52,6 +52,23 @@ struct aes_handle_s {
 
   std::mutex mu;  // guards bufs / events / err when batched workers share the handle
 
+  // Source of the FP32 copy each pool buffer holds (options.keep_fp32_copy): written by every
+  // cast into the buffer, dropped when the pool frees the buffer.
+  struct F32Src {
+    const void* A;
+    int64_t n, d, lda;
+  };
+  std::unordered_map<void*, F32Src> f32src;
+  bool f32_copy_of(void* buf, const void* A, int64_t n, int64_t d, int64_t lda) {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = f32src.find(buf);
+    return it != f32src.end() && it->second.A == A && it->second.n == n && it->second.d == d && it->second.lda == lda;
+  }
+  void f32_copy_set(void* buf, const void* A, int64_t n, int64_t d, int64_t lda) {
+    std::lock_guard<std::mutex> lock(mu);
+    f32src[buf] = F32Src{A, n, d, lda};
+  }
+
   template <typename T>
   T* buf(const std::string& name, size_t count) {
     std::lock_guard<std::mutex> lock(mu);
@@ -59,6 +76,7 @@ struct aes_handle_s {
     auto it = bufs.find(name);
     if (it != bufs.end() && it->second.second >= bytes) return static_cast<T*>(it->second.first);
     if (it != bufs.end()) {
+      f32src.erase(it->second.first);
       AES_HIP(hipFree(it->second.first));
       bufs.erase(it);
     }
@@ -82,6 +100,7 @@ struct aes_handle_s {
       if (kept) {
         ++it;
       } else {
+        f32src.erase(it->second.first);
         AES_HIP(hipFree(it->second.first));
         it = bufs.erase(it);
       }
@@ -94,6 +113,7 @@ struct aes_handle_s {
   void release() {
     for (auto& kv : bufs) (void)hipFree(kv.second.first);
     bufs.clear();
+    f32src.clear();
     for (auto e : events) (void)hipEventDestroy(e);
     events.clear();
     if (pinned) (void)hipHostFree(pinned);
@@ -259,7 +279,11 @@ class Solver {
     if (mixed_) {
       // the FP32 copy feeds the inner products and every sketch of the mixed modes
       A32_ = B<float>("A32", (size_t)n_ * d_);
-      launch_cast<float>(n_, d_, P_.A, P_.lda, A32_, s_);
+      // the caller may promise that A is the one the buffer was cast from and unchanged since
+      if (!(o_.keep_fp32_copy && h_->f32_copy_of(A32_, P_.A, n_, d_, P_.lda))) {
+        launch_cast<float>(n_, d_, P_.A, P_.lda, A32_, s_);
+        h_->f32_copy_set(A32_, P_.A, n_, d_, P_.lda);
+      }
       hv_scratch();
     }
     stop_scale_ = nu2_ * min_lambda() * tol_ * tol_;

@@ -110,3 +110,21 @@ def test_threads_share_the_handle():
         t.join()
     for x in out:
         assert torch.equal(x, ref)
+
+
+def test_keep_fp32_copy_reuses_only_the_same_matrix():
+    A, b, nu = _problem(8192, 256, 11)
+    opts = dict(precision="mixed", m_init=8, seed=2)
+    x_ref, i_ref = aes.solve(A, b, nu, **opts)
+    x1, i1 = aes.solve(A, b, nu, keep_fp32_copy=True, **opts)  # the copy cast by the first solve
+    assert i_ref["status"] == "ok" and i1["status"] == "ok"
+    assert torch.equal(x1, x_ref)
+    # another matrix of the same shape at another address: cast again despite the option
+    A2 = A * 0.5
+    x2, _ = aes.solve(A2, b, nu, keep_fp32_copy=True, **opts)
+    x2_ref, _ = aes.solve(A2.clone(), b, nu, **opts)
+    assert torch.equal(x2, x2_ref)
+    # without the promise an in-place change is always seen
+    A.mul_(0.5)
+    x3, _ = aes.solve(A, b, nu, **opts)
+    assert torch.equal(x3, x2_ref)
