@@ -350,13 +350,18 @@ __global__ __launch_bounds__(256) void wht_pass_kernel(const TIN* __restrict__ A
                                                        int zero_bits, const double* __restrict__ eps,
                                                        const int32_t* __restrict__ pos, double scale,
                                                        int a_aligned, const int32_t* __restrict__ need,
-                                                       int check_tiles, int pw) {
+                                                       int check_tiles, int pw, int yperm) {
   using TACC = typename AccOf<TY>::type;
   // Y is stored in column panels of pw columns: element (row, col) at
   // (col / pw) * npad * pw + row * pw + col % pw, so that the strided tiles of the later passes
   // read rows of one panel rather than rows n' * 8 bytes apart
   const int pws = __builtin_ctz((unsigned)pw);  // pw is a power of two
+  // yperm > 0 (two passes, the first over the low yperm index bits): a row is stored at its index
+  // with the two bit fields swapped, so that a tile of the last pass (rows differing in the high
+  // bits) is one contiguous block of the panel and the first pass writes with the stride instead
+  const int lbits = __builtin_ctzll((unsigned long long)npad);
   auto ypos = [&](int64_t row, int64_t col) {
+    if (yperm > 0) row = ((row & ((1ll << yperm) - 1)) << (lbits - yperm)) | (row >> yperm);
     return (((col >> pws) * npad + row) << pws) + (col & (int64_t)(pw - 1));
   };
   constexpr int VW = 16 / sizeof(TACC);  // columns per vector access
@@ -626,11 +631,11 @@ template <typename TIN, typename TY, typename TOUT, int CW, int MODE, int NF>
 static void wht_launch_cw(int64_t npad, size_t shmem, hipStream_t st, const TIN* A, const TY* Ysrc, TY* Ydst, TOUT* SA,
                           int64_t ldsa, int64_t n, int64_t d, int64_t lda, int s, int b, int zero_bits,
                           const double* eps, const int32_t* pos, double scale, const int32_t* need,
-                          int check_tiles, int pw) {
+                          int check_tiles, int pw, int yperm) {
   const int a_aligned = ((uintptr_t)A % 16) == 0;
   const dim3 grid((unsigned)ceil_div(d, CW), (unsigned)(npad >> b));
   hipLaunchKernelGGL((wht_pass_kernel<TIN, TY, TOUT, CW, MODE, NF>), grid, dim3(256), shmem, st, A, Ysrc, Ydst, SA, ldsa, n,
-                     d, lda, npad, s, b, zero_bits, eps, pos, scale, a_aligned, need, check_tiles, pw);
+                     d, lda, npad, s, b, zero_bits, eps, pos, scale, a_aligned, need, check_tiles, pw, yperm);
   AES_LAUNCH_CHECK();
 }
 
@@ -639,7 +644,8 @@ static void wht_launch_cw(int64_t npad, size_t shmem, hipStream_t st, const TIN*
 template <typename TIN, typename TY, typename TOUT, int MODE>
 static void wht_launch(int64_t npad, hipStream_t st, const TIN* A, const TY* Ysrc, TY* Ydst, TOUT* SA, int64_t ldsa,
                        int64_t n, int64_t d, int64_t lda, int s, int b, int zero_bits, const double* eps,
-                       const int32_t* pos, double scale, const int32_t* need, int check_tiles, int pw) {
+                       const int32_t* pos, double scale, const int32_t* need, int check_tiles, int pw,
+                       int yperm) {
   using TACC = typename AccOf<TY>::type;
   constexpr int CW_WIDE = 256 / sizeof(TACC), CW_NARROW = 128 / sizeof(TACC);
   // the radix-16 register path (one LDS crossing) measured faster for the last pass and for a
@@ -648,15 +654,15 @@ static void wht_launch(int64_t npad, hipStream_t st, const TIN* A, const TY* Ysr
   if (r16)
     wht_launch_cw<TIN, TY, TOUT, CW_WIDE, MODE, 4>(npad, (size_t)(1 << b) * CW_WIDE * sizeof(TACC), st, A, Ysrc, Ydst,
                                                    SA, ldsa, n, d, lda, s, b, zero_bits, eps, pos, scale, need,
-                                                   check_tiles, pw);
+                                                   check_tiles, pw, yperm);
   else if (b <= 8)
     wht_launch_cw<TIN, TY, TOUT, CW_WIDE, MODE, 3>(npad, (size_t)(1 << b) * CW_WIDE * sizeof(TACC), st, A, Ysrc, Ydst,
                                                    SA, ldsa, n, d, lda, s, b, zero_bits, eps, pos, scale, need,
-                                                   check_tiles, pw);
+                                                   check_tiles, pw, yperm);
   else
     wht_launch_cw<TIN, TY, TOUT, CW_NARROW, MODE, 3>(npad, (size_t)(1 << b) * CW_NARROW * sizeof(TACC), st, A, Ysrc, Ydst,
                                                   SA, ldsa, n, d, lda, s, b, zero_bits, eps, pos, scale, need,
-                                                  check_tiles, pw);
+                                                  check_tiles, pw, yperm);
 }
 
 size_t srht_scratch_elems(int64_t npad, int64_t d) { return (size_t)npad * (size_t)round_up(d, 64); }
@@ -687,6 +693,7 @@ void launch_srht_apply(const TIN* A, int64_t n, int64_t d, int64_t lda, const do
   // unless L > 16)
   using TACC = typename AccOf<TY>::type;
   const int pw = (passes > 1 && (L + passes - 1) / passes > 8) ? 128 / (int)sizeof(TACC) : 256 / (int)sizeof(TACC);
+  const int yperm = passes == 2 ? (L + 1) / 2 : 0;
   int s = 0;
   int first_bits = 0;
   for (int p = 0; p < passes; ++p) {
@@ -696,7 +703,7 @@ void launch_srht_apply(const TIN* A, int64_t n, int64_t d, int64_t lda, const do
     const int zero_bits = (p == 1) ? first_bits : 0;
     if (passes == 1) {
       wht_launch<TIN, TY, TOUT, 3>(npad, st, A, (const TY*)nullptr, (TY*)nullptr, SA, ldsa, n, d, lda, s, b, 0, eps, pos,
-                                   scale, nullptr, check_tiles, pw);
+                                   scale, nullptr, check_tiles, pw, 0);
     } else if (p == 0) {
       const int32_t* nd = nullptr;
       if (passes == 2 && need && m <= (1ll << b) / 2) {
@@ -708,14 +715,14 @@ void launch_srht_apply(const TIN* A, int64_t n, int64_t d, int64_t lda, const do
         nd = need;
       }
       wht_launch<TIN, TY, TOUT, 0>(npad, st, A, (const TY*)nullptr, Y, SA, ldsa, n, d, lda, s, b, 0, eps, pos, scale,
-                                   nd, 0, pw);
+                                   nd, 0, pw, yperm);
       first_bits = b;
     } else if (p == passes - 1) {
       wht_launch<TIN, TY, TOUT, 2>(npad, st, A, (const TY*)Y, (TY*)nullptr, SA, ldsa, n, d, lda, s, b, zero_bits, eps,
-                                   pos, scale, nullptr, check_tiles, pw);
+                                   pos, scale, nullptr, check_tiles, pw, yperm);
     } else {
       wht_launch<TIN, TY, TOUT, 1>(npad, st, A, (const TY*)Y, Y, SA, ldsa, n, d, lda, s, b, zero_bits, eps, pos, scale,
-                                   nullptr, 0, pw);
+                                   nullptr, 0, pw, yperm);
     }
     s += b;
   }
