@@ -28,6 +28,8 @@
 #include "kernels.h"
 #include "batch.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 using namespace aes;
 
 // ---------------------------------------------------------------------------------------
@@ -133,6 +135,15 @@ struct aes_ctx_s {
 };
 
 namespace {
+
+// Host range of a phase (sketch and factor, iterate, refinement sweep, batch) for
+// rocprofv3 --marker-trace; a no-op when no profiler is attached.
+struct PhaseRange {
+  explicit PhaseRange(const char* name) { roctxRangePushA(name); }
+  ~PhaseRange() { roctxRangePop(); }
+  PhaseRange(const PhaseRange&) = delete;
+  PhaseRange& operator=(const PhaseRange&) = delete;
+};
 
 struct StatusError : std::runtime_error {
   aes_status st;
@@ -389,6 +400,7 @@ class Solver {
 
   // ---- sketch + factorisation of H_S (Sec. 4.1) ----------------------------------------
   void sketch_factor() {
+    PhaseRange range("aes sketch+factor");
     {
       std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
       AES_HIP(hipEventCreate(&ev.first));
@@ -598,6 +610,7 @@ class Solver {
   // the initial point is 0).  Returns the status; fills the counters.
   aes_status adaptive(const double* rhs, double* x, bool x_is_zero, bool use32, int stop_rule, double stop_scale,
                       bool reuse_factor) {
+    PhaseRange range("aes adaptive solve");
     // Polyak-IHS (heavy-ball appendix) runs the IHS step with momentum: mu_rho, beta_rho of the
     // corollary, x_prev = x_0 at the start and x_t after a resize; the test takes the
     // corollary's finite-time factor alpha(tau, rho) beta_rho^omega(tau) in place of phi^tau
@@ -911,6 +924,7 @@ class Solver {
     for (int j = 0; j < c_; ++j) act[j] = 1;
     std::vector<double> hn(2 * C_);
     for (int sweep = 0; sweep < std::max(1, o_.max_refine); ++sweep) {
+      PhaseRange range("aes refinement sweep");
       ++sweeps_;
       // r = b - H x with the FP64 matrix (compensated once x is close)
       if (x_zero)
@@ -1566,6 +1580,7 @@ class BatchEngine {
   ~BatchEngine() { cleanup(); }
 
   aes_status run(aes_info* infos) {
+    PhaseRange range("aes batched solve");
     const double t0 = now_ms();
     const int np = (int)P_.size();
     AES_HIP(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
