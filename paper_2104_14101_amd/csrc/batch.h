@@ -51,7 +51,7 @@ struct BProb {
   double* flags_out;   // 8 doubles of the packed host-read flag array
   // constants of the method and the stop rule
   double mu, beta;
-  double stop_scale, stop_sr, tol2;
+  double stop_sr, tol2;
   int32_t stop_rule, adaptive;
 };
 
@@ -59,6 +59,7 @@ struct BProb {
 struct BDyn {
   double thr;        // log c + (t+1-I) log phi (or the Polyak-IHS factor)
   double seq;        // step stamp, written to flag 7 when the step runs
+  double stop_scale; // scale of the stop test (changes between refinement sweeps)
   int32_t run;       // 0: the problem takes no part in this step
   int32_t force;     // test hook: reject this step
   int32_t at_cap;    // m has reached its cap (a failed test is accepted)

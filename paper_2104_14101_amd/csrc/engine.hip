@@ -919,7 +919,7 @@ class Solver {
     m_ = std::min<int64_t>(o_.m_init, mcap_);
     k_ = 0;
     const double inner = o_.inner_tol > 0 ? o_.inner_tol : 1e-6;
-    const double inner_scale = nu2_ * min_lambda() * inner * inner;
+    double eta = inner;  // relative tolerance of the current inner solve
     std::vector<int> act(C_, 0);
     for (int j = 0; j < c_; ++j) act[j] = 1;
     std::vector<double> hn(2 * C_);
@@ -933,7 +933,7 @@ class Solver {
         refine_residual(X_, Bv_, Rr);
       AES_HIP(hipMemsetAsync(E, 0, dc * sizeof(double), s_));
       AES_HIP(hipMemcpyAsync(active_, act.data(), C_ * sizeof(int), hipMemcpyHostToDevice, s_));
-      aes_status st = adaptive(Rr, E, true, true, AES_STOP_XREL, inner_scale, !first);
+      aes_status st = adaptive(Rr, E, true, true, AES_STOP_XREL, nu2_ * min_lambda() * eta * eta, !first);
       first = false;
       if (st == AES_ERR_NONFINITE) return st;
       launch_axpy_cols(d_, C_, X_, E, nullptr, s_);
@@ -952,6 +952,7 @@ class Solver {
         done = done && ok;
       }
       if (done) return AES_OK;
+      eta = next_inner_tol(inner, eta);
     }
     return AES_ERR_MAX_ITER;
   }
@@ -1046,6 +1047,7 @@ class Solver {
       bact_.assign(C_, 0);
       for (int j = 0; j < c_; ++j) bact_[j] = 1;
       const double inner = o_.inner_tol > 0 ? o_.inner_tol : 1e-6;
+      binner_eta_ = inner;
       binner_scale_ = nu2_ * min_lambda() * inner * inner;
       bxzero_ = !x0;
       sweep_begin(true);
@@ -1112,6 +1114,15 @@ class Solver {
   // plain product (one pass) gives all the digits the next inner solve can use; once every column's
   // correction is below that, the residual is formed in compensated arithmetic.
   static constexpr double kCompensateBelow = 1e-4;
+  static constexpr double kCertifyTol = 0.1;
+  // Relative tolerance of the next inner solve after a sweep run at `eta` that did not stop:
+  // `inner`, or kCertifyTol for a sweep that only has to confirm convergence (the last correction
+  // times its tolerance, the expected error of x, is already a tenth of the stop threshold; if x
+  // is less accurate than that, the sweep's correction fails the stop test and a full sweep
+  // follows).
+  double next_inner_tol(double inner, double eta) const {
+    return corr_ratio_ * eta <= 0.025 * tol_ ? std::max(inner, kCertifyTol) : inner;
+  }
   void refine_residual(const double* x, const double* b, double* r) {
     if (corr_ratio_ > kCompensateBelow)
       hv(x, r, -1.0, b, 1.0, false);
@@ -1187,20 +1198,11 @@ class Solver {
     bp.flags_out = flags_out;
     bp.mu = bmu_;
     bp.beta = bbeta_;
-    bp.stop_scale = bscale_;
     bp.stop_sr = stop_sr_;
     bp.tol2 = tol2_;
     bp.stop_rule = bstop_;
     bp.adaptive = o_.adaptive;
   }
-  // The iterate and right-hand side of the current inner solve change between sweeps.
-  void batch_refill(BProb& bp) {
-    bp.X = bx_;
-    bp.rhs = brhs_;
-    bp.stop_scale = bscale_;
-    bp.stop_rule = bstop_;
-  }
-
   // Step parameters (before every step of the batch).
   // ready: the problem's eager work (initialisation, resize) has completed; otherwise it sits
   // this step out and takes the next one
@@ -1211,6 +1213,7 @@ class Solver {
     dy.thr = bpolyak_ ? blc_ + polyak_log_bound((double)(bt_ + 1 - bI_), bbeta_) : thr_of(blc_, blphi_, bt_, bI_);
     bseq_ += 1.0;
     dy.seq = bseq_;
+    dy.stop_scale = bscale_;
     dy.force = (o_.adaptive && o_.force_reject_at >= 0 && bt_ == o_.force_reject_at && !bforced_) ? 1 : 0;
     dy.at_cap = m_ >= mcap_ ? 1 : 0;
     dy.parity = (int)(bt_ & 1);
@@ -1348,6 +1351,8 @@ class Solver {
         bdone(AES_ERR_MAX_ITER);
         return;
       }
+      binner_eta_ = next_inner_tol(o_.inner_tol > 0 ? o_.inner_tol : 1e-6, binner_eta_);
+      binner_scale_ = nu2_ * min_lambda() * binner_eta_ * binner_eta_;
       sweep_begin(false);
     } catch (const StatusError& e) {
       h_->set_err(e.what());
@@ -1472,6 +1477,7 @@ class Solver {
   bool bx_zero_ = true, buse32_ = false, bxzero_ = true;
   int bstop_ = 0;
   double bscale_ = 0.0, binner_scale_ = 0.0;
+  double binner_eta_ = 1e-6;  // relative tolerance of the current inner solve (batched refinement)
   int64_t bt_ = 0, bI_ = 0;
   bool bforced_ = false;
   double bseq_ = 0.0;

@@ -660,7 +660,7 @@ __global__ __launch_bounds__(kVT) void bfinish_kernel(const BProb* __restrict__ 
         scal[c] = Dp;
         const double Df = IHS ? 2.0 * Dp : Dp;
         const double D0f = IHS ? 2.0 * scal[4 * C + c] : scal[4 * C + c];
-        if (stop_test(P.stop_rule, Df, D0f, xn_s[c], rz_s[c] == 0.0, P.stop_scale, P.stop_sr, P.tol2)) active[c] = 0;
+        if (stop_test(P.stop_rule, Df, D0f, xn_s[c], rz_s[c] == 0.0, D.stop_scale, P.stop_sr, P.tol2)) active[c] = 0;
       }
       na += active[c] != 0;
       if (scal[c] > maxD) maxD = scal[c];
