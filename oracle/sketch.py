@@ -23,7 +23,9 @@ the three embeddings; uniform marginals of the row sample; Gaussian moments; the
 S with one +-1 per column, its hash against big-integer arithmetic, uniform buckets and the
 closed-form second moment of U^T S^T S U - I; for ``srht_reuse``: its dense matrix form
 from scipy's Hadamard matrix with the signs of index 0, equality with the SRHT at k = 0, the
-isometry at m = n' and the Monte-Carlo mean over k of S_k^T S_k with E_0 fixed.
+isometry at m = n' and the Monte-Carlo mean over k of S_k^T S_k with E_0 fixed; for
+``srht_nested``: its rows as a reordering of the SRHT of index 0, the prefix property, keys in
+increasing order, the incremental Gram identity and the Monte-Carlo mean over seeds.
 """
 import numpy as np
 
@@ -100,6 +102,38 @@ def srht_reuse(A, m, seed, k, problem=0):
     return Y[R] * np.sqrt(npad / m)
 
 
+def srht_nested_rows(seed, n, m, problem=0):
+    """Indices of the padded rows of the nested SRHT of size m, in the order they are listed.
+
+    The m padded rows with the smallest Philox ROW keys of sketch index 0 (the sample rule of
+    ``srht_rows``), listed in increasing key order with ties broken by the smaller index, so
+    that the rows of size m are the first m of every larger size.
+    """
+    npad = padded_size(n)
+    if not 1 <= m <= npad:
+        raise ValueError("SRHT sketch size must lie in [1, n']")
+    keys = philox.row_keys(seed, 0, npad, problem)
+    return np.argsort(keys, kind="stable")[:m]
+
+
+def srht_nested(A, m, seed, problem=0):
+    """S_m A for the nested variant of the transform-reuse SRHT (not the paper's method).
+
+    S_m = sqrt(n'/m) R_m (H / sqrt(n')) E_0 with R_m the first m rows of one random order of the
+    n' padded rows (``srht_nested_rows``): every resize keeps the rows it had and adds new ones.
+    Each S_m on its own is the SRHT of index 0 with its rows reordered, so a bound that holds
+    for one SRHT holds for every S_m (a union bound over the resizes applies).  Its Gram then
+    grows incrementally: with Y the normalised transform and m' > m,
+    (S_m' A)^T S_m' A = (m/m') (S_m A)^T S_m A + (n'/m') sum over the new rows of y y^T.
+    The sketch does not depend on a sketch index.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    npad = padded_size(A.shape[0])
+    Y = srht(A, npad, seed, 0, problem)  # every padded row, in order: Y = (H / sqrt(n')) E_0 A_pad
+    R = srht_nested_rows(seed, A.shape[0], m, problem)
+    return Y[R] * np.sqrt(npad / m)
+
+
 def srht_row(A, m, seed, k, j, problem=0):
     """Row j of S A computed directly from H's closed form, for spot checks at large n."""
     A = np.asarray(A, dtype=np.float64)
@@ -155,6 +189,8 @@ def sketch(A, m, kind, seed, k, problem=0):
         return srht(A, m, seed, k, problem)
     if kind == "srht_reuse":
         return srht_reuse(A, m, seed, k, problem)
+    if kind == "srht_nested":
+        return srht_nested(A, m, seed, problem)
     if kind == "gauss":
         return gaussian(A, m, seed, k, problem)
     if kind == "sjlt":

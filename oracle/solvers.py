@@ -68,7 +68,7 @@ from .factor import NotSPDError, SketchedHessian
 @dataclass
 class Options:
     method: str = "pcg"          # 'pcg' | 'ihs' | 'polyak' (heavy-ball IHS) | 'cg' (unpreconditioned baseline)
-    sketch: str = "srht"         # 'srht' | 'gauss' | 'sjlt' | 'srht_reuse' (transform-reuse variant)
+    sketch: str = "srht"         # 'srht' | 'gauss' | 'sjlt' | 'srht_reuse' | 'srht_nested' (variants)
     rho: float = 0.125
     m_init: int = 1
     m_max: int = 0               # 0 -> n'

@@ -71,6 +71,59 @@ def test_srht_reuse_matrix_form():
     np.testing.assert_allclose(SA.T @ SA, A.T @ A, rtol=1e-12, atol=1e-12)
 
 
+def test_srht_nested_rows_and_prefixes():
+    # the rows of size m are the SRHT sample of index 0 (same rows, same scale), listed in key
+    # order; size m is the first m rows of size 2m up to the scale sqrt(n'/m)
+    rng = np.random.default_rng(8)
+    n, d = 45, 5
+    A = rng.standard_normal((n, d))
+    npad = sk.padded_size(n)
+    keys = philox.row_keys(13, 0, npad)
+    for m in (1, 4, 7, 16, 64):
+        R = sk.srht_nested_rows(13, n, m)
+        np.testing.assert_array_equal(np.sort(R), sk.srht_rows(13, 0, n, m))
+        assert np.all(np.diff(keys[R].astype(object)) > 0)
+        SA = sk.srht_nested(A, m, 13)
+        np.testing.assert_allclose(SA[np.argsort(R)], sk.srht(A, m, 13, 0), rtol=1e-13, atol=1e-13)
+    for m in (1, 3, 8, 32):
+        big = sk.srht_nested(A, 2 * m, 13)
+        np.testing.assert_allclose(sk.srht_nested(A, m, 13) * np.sqrt(m), big[:m] * np.sqrt(2 * m),
+                                   rtol=1e-14, atol=1e-14)
+    # the sketch index plays no part; m = n' is an isometry
+    np.testing.assert_array_equal(sk.sketch(A, 8, "srht_nested", 13, 0), sk.sketch(A, 8, "srht_nested", 13, 5))
+    SA = sk.srht_nested(A, npad, 13)
+    np.testing.assert_allclose(SA.T @ SA, A.T @ A, rtol=1e-12, atol=1e-12)
+
+
+def test_srht_nested_incremental_gram():
+    # (S_m' A)^T S_m' A = (m/m') (S_m A)^T S_m A + Gram of the rows m..m'-1 of S_m' A, for the
+    # doubling step and an uneven one (a capped last resize)
+    rng = np.random.default_rng(9)
+    n, d = 100, 6
+    A = rng.standard_normal((n, d))
+    for m, m2 in ((8, 16), (16, 32), (24, 128), (32, 40)):
+        G_small = sk.srht_nested(A, m, 2).T @ sk.srht_nested(A, m, 2)
+        big = sk.srht_nested(A, m2, 2)
+        inc = (m / m2) * G_small + big[m:].T @ big[m:]
+        np.testing.assert_allclose(inc, big.T @ big, rtol=1e-12, atol=1e-12)
+    # with the old rows re-weighted by 1/2 instead of m/m' the identity fails for m' = 5m/4
+    big = sk.srht_nested(A, 40, 2)
+    G32 = sk.srht_nested(A, 32, 2).T @ sk.srht_nested(A, 32, 2)
+    assert np.max(np.abs(0.5 * G32 + big[32:].T @ big[32:] - big.T @ big)) > 1e-3
+
+
+def test_srht_nested_unbiased_over_seeds():
+    # E[S_m^T S_m] = I over the seed (the sketch index is fixed for this variant)
+    n, m, reps = 16, 4, 600
+    acc = np.zeros((n, n))
+    for seed in range(reps):
+        SA = sk.srht_nested(np.eye(n), m, seed)
+        acc += SA.T @ SA
+    acc /= reps
+    assert np.max(np.abs(acc - np.eye(n))) < 0.25
+    assert abs(np.trace(acc) / n - 1) < 0.05
+
+
 def _sts(kind, n, m, seed, k):
     return np.array(sk.sketch(np.eye(n), m, kind, seed, k)).T @ np.array(sk.sketch(np.eye(n), m, kind, seed, k))
 

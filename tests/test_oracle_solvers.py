@@ -115,7 +115,7 @@ def small():
 
 
 @pytest.mark.parametrize("method", ["pcg", "ihs", "polyak"])
-@pytest.mark.parametrize("kind", ["srht", "gauss", "sjlt", "srht_reuse"])
+@pytest.mark.parametrize("kind", ["srht", "gauss", "sjlt", "srht_reuse", "srht_nested"])
 def test_solution_accuracy(small, method, kind):
     o = solvers.Options(method=method, sketch=kind, m_init=8, tol=1e-10, seed=1)
     x, info = solvers.solve(small["A"], small["b"], small["nu"], small["lam"], o)
