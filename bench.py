@@ -232,7 +232,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="pcg_n65536_d2048")
     ap.add_argument("--method", default="pcg", choices=["pcg", "ihs"])
-    ap.add_argument("--sketch", default="srht", choices=["srht", "gauss", "sjlt", "srht_reuse"])
+    ap.add_argument("--sketch", default="srht", choices=["srht", "gauss", "sjlt", "srht_reuse", "srht_nested"])
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the Gaussian / SJLT / IHS / CG solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -370,11 +370,12 @@ def main():
 
 def variants_leg(aes, torch, A, b, nu, lam, w, P_np, args):
     """The same workload solved with the other sketches and methods (3 timed solves each; srht_reuse
-    is the transform-reuse variant, not the paper's method; polyak the adaptive heavy-ball IHS of
-    the appendix) and by the unpreconditioned CG baseline (one timed solve)."""
+    is the transform-reuse variant and srht_nested its nested form with the incremental Gram, not
+    the paper's method; polyak the adaptive heavy-ball IHS of the appendix) and by the
+    unpreconditioned CG baseline (one timed solve)."""
     res = {}
-    for method, sketch in (("pcg", "gauss"), ("pcg", "sjlt"), ("pcg", "srht_reuse"), ("ihs", "srht"), ("ihs", "sjlt"),
-                           ("polyak", "srht"), ("cg", None)):
+    for method, sketch in (("pcg", "gauss"), ("pcg", "sjlt"), ("pcg", "srht_reuse"), ("pcg", "srht_nested"),
+                           ("ihs", "srht"), ("ihs", "sjlt"), ("polyak", "srht"), ("cg", None)):
         if method == args.method and sketch == args.sketch:
             continue
         opts = dict(method=method, m_init=w.m_init, seed=1, tol=1e-10, max_iter=2000)

@@ -64,8 +64,20 @@ typedef enum { AES_PCG = 0, AES_IHS = 1, AES_CG = 2, AES_POLYAK = 3 } aes_method
  * row sample of index k.  Each S_k alone is an SRHT (Sec. 2.1), so a guarantee stated for one
  * SRHT holds for each of them and a union bound over the resizes applies, but the S_k share E_0
  * and H and are not independent.  A solve transforms A once (n' x d doubles kept in the handle's
- * workspace); every resize then only draws rows of the stored transform. */
-typedef enum { AES_SRHT = 0, AES_GAUSS = 1, AES_SJLT = 2, AES_SRHT_REUSE = 3 } aes_sketch_kind;
+ * workspace); every resize then only draws rows of the stored transform.
+ * AES_SRHT_NESTED: the transform-reuse SRHT with nested row samples (not the paper's method;
+ * FP64 only).  S_m = sqrt(n'/m) R_m (H / sqrt(n')) E_0, R_m the first m padded rows in
+ * increasing order of their row keys of index 0 (ties: smaller row first), so each resize keeps
+ * the rows it had; no sketch index is used.  Each S_m alone is the SRHT of index 0 with its rows
+ * reordered.  Once m >= d the Gram grows incrementally: G_m' = (m/m') G_m plus the Gram of the
+ * m' - m new rows, half the Gram flops of forming it again at a doubling. */
+typedef enum {
+  AES_SRHT = 0,
+  AES_GAUSS = 1,
+  AES_SJLT = 2,
+  AES_SRHT_REUSE = 3,
+  AES_SRHT_NESTED = 4
+} aes_sketch_kind;
 typedef enum {
   AES_FP64 = 0,       /* every step in FP64 */
   AES_MIXED = 1,      /* FP32-stored A for the PCG matvecs and the SRHT or SJLT (FP32 sums,
@@ -298,7 +310,9 @@ aes_status aes_hv_multi(aes_handle h, void* stream, int64_t n, int64_t d, int64_
  * its sign, into sketch row h_i, both from stream SJLT; each sketch row sums its rows in
  * increasing order (n < 2^31; m may exceed n, leaving zero rows);
  * kind AES_SRHT_REUSE: SA = sqrt(n'/m) R_k Y with Y = (1/sqrt n') H E_0 A_pad (signs of index 0,
- * rows of index k), computed from scratch on every call.
+ * rows of index k), computed from scratch on every call;
+ * kind AES_SRHT_NESTED: SA = sqrt(n'/m) Y[order[0..m)] with order the padded rows sorted by
+ * their row keys of index 0 (k is not used; rows listed in that order).
  *   SA: device, m x d output (ld = d).  1 <= m <= n'. */
 aes_status aes_sketch(aes_handle h, void* stream, int kind, int64_t n, int64_t d, const double* A,
                       int64_t lda, int64_t m, uint64_t seed, int32_t problem, int64_t k, double* SA);

@@ -15,7 +15,7 @@ AES_OK, AES_ERR_INVALID_ARG, AES_ERR_NOT_SPD, AES_ERR_NONFINITE, AES_ERR_MAX_ITE
 STATUS_NAMES = {0: "ok", 1: "invalid_arg", 2: "not_spd", 3: "nonfinite", 4: "max_iter", 5: "hip_error", 6: "oom",
                 7: "not_implemented"}
 METHODS = {"pcg": 0, "ihs": 1, "cg": 2, "polyak": 3}
-SKETCHES = {"srht": 0, "gauss": 1, "sjlt": 2, "srht_reuse": 3}
+SKETCHES = {"srht": 0, "gauss": 1, "sjlt": 2, "srht_reuse": 3, "srht_nested": 4}
 PRECISIONS = {"fp64": 0, "mixed": 1, "mixed_fp32": 2}
 STOPS = {"xrel": 0, "dtilde_rel": 1, "fixed": 2, "remark": 3}
 

@@ -188,9 +188,11 @@ void validate(const ProblemDesc& P, double tol, const aes_options& o) {
     bad("unknown method");
   if (o.method == AES_CG && o.precision != AES_FP64) bad("the CG baseline runs in FP64");
   if (o.method == AES_CG && o.stop == AES_STOP_REMARK) bad("the REMARK stop rule needs a sketch");
-  if (o.sketch != AES_SRHT && o.sketch != AES_GAUSS && o.sketch != AES_SJLT && o.sketch != AES_SRHT_REUSE)
+  if (o.sketch != AES_SRHT && o.sketch != AES_GAUSS && o.sketch != AES_SJLT && o.sketch != AES_SRHT_REUSE &&
+      o.sketch != AES_SRHT_NESTED)
     bad("unknown sketch");
-  if (o.sketch == AES_SRHT_REUSE && o.precision != AES_FP64) bad("the transform-reuse SRHT runs in FP64");
+  if ((o.sketch == AES_SRHT_REUSE || o.sketch == AES_SRHT_NESTED) && o.precision != AES_FP64)
+    bad("the transform-reuse SRHT runs in FP64");
   if (o.sketch == AES_SJLT && P.n >= (int64_t(1) << 31)) bad("the SJLT needs n < 2^31");
   if (o.precision < AES_FP64 || o.precision > AES_MIXED_FP32) bad("unknown precision");
   if (o.stop < 0 || o.stop > 3) bad("unknown stop rule");
@@ -420,9 +422,10 @@ class Solver {
       // the sketch itself is kept for the Woodbury form's products; for m >= d only its Gram is
       SA_ = woodbury_ ? B<double>("SA", (size_t)m_ * d_) : S<double>("SAg", (size_t)m_ * d_);
     }
-    if (o_.sketch == AES_SRHT_REUSE) {
-      // transform-reuse variant: Y = (H / sqrt(n')) E_0 A_pad once per solve (the SRHT of
-      // index 0 at m = n', every row kept in order), then rows R_k of Y scaled by sqrt(n'/m)
+    if (o_.sketch == AES_SRHT_REUSE || o_.sketch == AES_SRHT_NESTED) {
+      // transform-reuse variants: Y = (H / sqrt(n')) E_0 A_pad once per solve (the SRHT of
+      // index 0 at m = n', every row kept in order), then rows R_k of Y scaled by sqrt(n'/m);
+      // nested: the first m rows of Y in key order (the key order is sorted once per solve)
       SelectScratch sc;
       sc.keys = S<uint64_t>("sel_keys", npad_);
       sc.pos = S<int32_t>("sel_pos", npad_);
@@ -437,10 +440,20 @@ class Solver {
         launch_srht_apply<double, double, double>(P_.A, n_, d_, P_.lda, eps, npad_, sc.pos, npad_,
                                                   S<double>("Y", srht_scratch_elems(npad_, d_)), yr_, d_,
                                                   S<int32_t>("need", 512), s_);
+        if (o_.sketch == AES_SRHT_NESTED) {
+          korder_ = B<int32_t>("nest_order", npad_);
+          launch_srht_key_order(o_.seed, o_.problem, npad_, key_order_scratch(), korder_, s_);
+          gnest_m_ = 0;
+        }
         yr_ready_ = true;
       }
-      launch_srht_select(o_.seed, o_.problem, k_, npad_, m_, sc, s_);
-      launch_gather_rows(npad_, d_, yr_, sc.pos, std::sqrt((double)npad_ / (double)m_), SA_, d_, s_);
+      const double scale = std::sqrt((double)npad_ / (double)m_);
+      if (o_.sketch == AES_SRHT_NESTED) {
+        launch_gather_ordered(m_, d_, yr_, korder_, scale, SA_, d_, s_);
+      } else {
+        launch_srht_select(o_.seed, o_.problem, k_, npad_, m_, sc, s_);
+        launch_gather_rows(npad_, d_, yr_, sc.pos, scale, SA_, d_, s_);
+      }
     } else if (o_.sketch == AES_SRHT) {
       double* eps = S<double>("eps", n_);
       launch_signs(o_.seed, o_.problem, k_, n_, eps, s_);
@@ -496,6 +509,17 @@ class Solver {
     AES_HIP(hipEventRecord(sk_ev_.back().second, s_));
   }
 
+  KeyOrderScratch key_order_scratch() {
+    KeyOrderScratch k;
+    k.keys = S<uint64_t>("ko_keys", npad_);
+    k.cnt = S<uint32_t>("ko_cnt", npad_);
+    k.cur = S<uint32_t>("ko_cur", npad_);
+    k.off = S<uint32_t>("ko_off", npad_);
+    k.bsum = S<uint32_t>("ko_bsum", keyorder_sum_elems(npad_));
+    k.skey = S<uint64_t>("ko_skey", npad_);
+    return k;
+  }
+
   // Gram of the current sketch, its Cholesky factor and the inverse factor (Sec. 4.1).
   // sk: 0 FP64 sketch (SA_), 1 BF16 (SA16_), 2 FP32 (SA32_)
   void factor_from_sa(int sk, int* flag) {
@@ -515,6 +539,17 @@ class Solver {
         const int splits = gram_splits(h_->num_cu, m_, d_, false);
         float* part = S<float>("gram_part32", (size_t)splits * fp_ * fp_);
         gram_tn_bf16(m_, d_, SA16_, d_, nu2_, lam_, part, splits, G, fp_, s_);
+      } else if (o_.sketch == AES_SRHT_NESTED) {
+        // nested rows: the sketch of the last resize is the first gnest_m_ rows of this one (up
+        // to its scale), so G = (gnest_m_ / m) G_last + the Gram of the new rows; the Gram
+        // without the nu^2 Lambda term is kept for the next resize
+        double* Gn = B<double>("nest_gram", (size_t)fp_ * fp_);
+        const int64_t m0 = gnest_m_ > 0 && gnest_m_ < m_ ? gnest_m_ : 0;
+        const int splits = gram_splits(h_->num_cu, m_ - m0, d_, true);
+        double* part = S<double>("gram_part", (size_t)splits * fp_ * fp_);
+        gram_tn(m_ - m0, d_, SA_ + m0 * d_, d_, nu2_, lam_, part, splits, G, fp_, s_, m0 ? Gn : nullptr,
+                (double)m0 / (double)m_, Gn);
+        gnest_m_ = m_;
       } else {
         const int splits = gram_splits(h_->num_cu, m_, d_, true);
         double* part = S<double>("gram_part", (size_t)splits * fp_ * fp_);
@@ -1440,6 +1475,8 @@ class Solver {
   int64_t npad_, mcap_, m_ = 1, k_ = 0, fp_ = 64;
   double* yr_ = nullptr;   // transform-reuse SRHT: the stored normalised transform of A
   bool yr_ready_ = false;
+  int32_t* korder_ = nullptr;  // nested SRHT: padded rows in increasing key order
+  int64_t gnest_m_ = 0;        // nested SRHT: rows behind the kept Gram (0: none)
   double nu2_;
   bool mixed_ = false, woodbury_ = false;
   double *lam_ = nullptr, *invlam_ = nullptr, *X_ = nullptr, *R_ = nullptr, *Pv_ = nullptr, *Q_ = nullptr,
@@ -2505,6 +2542,30 @@ aes_status aes_sketch(aes_handle h, void* stream, int kind, int64_t n, int64_t d
                                                 h->buf<int32_t>("sk.need", 512), s);
       launch_srht_select(seed, problem, k, npad, m, sc, s);
       launch_gather_rows(npad, d, Yr, sc.pos, std::sqrt((double)npad / (double)m), SA, d, s);
+    } else if (kind == AES_SRHT_NESTED) {
+      double* eps = h->buf<double>("sk.eps", n);
+      launch_signs(seed, problem, 0, n, eps, s);
+      SelectScratch sc;
+      sc.keys = h->buf<uint64_t>("sk.keys", npad);
+      sc.pos = h->buf<int32_t>("sk.pos", npad);
+      sc.hist = h->buf<uint32_t>("sk.hist", 256 * 8);
+      sc.state = h->buf<uint64_t>("sk.state", 4);
+      sc.blk = h->buf<uint32_t>("sk.blk", 2 * select_blocks(npad));
+      launch_srht_select(seed, problem, 0, npad, npad, sc, s);
+      double* Yr = h->buf<double>("sk.Yreuse", (size_t)npad * d);
+      launch_srht_apply<double, double, double>(A, n, d, lda, eps, npad, sc.pos, npad,
+                                                h->buf<double>("sk.Y", srht_scratch_elems(npad, d)), Yr, d,
+                                                h->buf<int32_t>("sk.need", 512), s);
+      KeyOrderScratch ko;
+      ko.keys = sc.keys;
+      ko.cnt = h->buf<uint32_t>("sk.ko_cnt", npad);
+      ko.cur = h->buf<uint32_t>("sk.ko_cur", npad);
+      ko.off = h->buf<uint32_t>("sk.ko_off", npad);
+      ko.bsum = h->buf<uint32_t>("sk.ko_bsum", keyorder_sum_elems(npad));
+      ko.skey = h->buf<uint64_t>("sk.ko_skey", npad);
+      int32_t* order = h->buf<int32_t>("sk.ko_order", npad);
+      launch_srht_key_order(seed, problem, npad, ko, order, s);
+      launch_gather_ordered(m, d, Yr, order, std::sqrt((double)npad / (double)m), SA, d, s);
     } else if (kind == AES_SJLT) {
       if (n >= (int64_t(1) << 31)) throw StatusError(AES_ERR_INVALID_ARG, "the SJLT needs n < 2^31");
       const SjltPlan sp = sjlt_plan(n, d, m, sizeof(double));

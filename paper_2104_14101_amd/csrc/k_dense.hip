@@ -346,10 +346,13 @@ int gram_splits(int num_cu, int64_t m, int64_t d, bool fp64) {
   return 1;
 }
 
-// G[i,j] (lower, padded to dp) = sum_s part[s][i][j] + nu2 lam_i [i == j]; identity padding; upper = 0
+// G[i,j] (lower, padded to dp) = [wprev gprev[i,j] +] sum_s part[s][i][j] + nu2 lam_i [i == j];
+// identity padding; upper = 0.  gkeep[i,j] (lower d x d) gets the value before the diagonal term
+// (gkeep may be gprev: each element is read and written by one thread).
 template <typename TP>
 __global__ void gram_reduce_kernel(const TP* __restrict__ part, int splits, int64_t d, int64_t dp, double nu2,
-                                   const double* __restrict__ lam, double* __restrict__ G) {
+                                   const double* __restrict__ lam, double* __restrict__ G, const double* gprev,
+                                   double wprev, double* gkeep) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= dp * dp) return;
   const int64_t i = e / dp, j = e % dp;
@@ -365,6 +368,8 @@ __global__ void gram_reduce_kernel(const TP* __restrict__ part, int splits, int6
       for (int q = 0; q < 8; ++q) v += (double)x[q];
     }
     for (; s < splits; ++s) v += (double)part[(int64_t)s * dp * dp + i * dp + j];
+    if (gprev) v += wprev * gprev[e];
+    if (gkeep) gkeep[e] = v;
     if (i == j) v += nu2 * (lam ? lam[i] : 1.0);
   } else if (i == j) {
     v = 1.0;
@@ -373,7 +378,7 @@ __global__ void gram_reduce_kernel(const TP* __restrict__ part, int splits, int6
 }
 
 void gram_tn(int64_t m, int64_t d, const double* SA, int64_t ldsa, double nu2, const double* lam, double* part,
-             int splits, double* G, int64_t dp, hipStream_t s) {
+             int splits, double* G, int64_t dp, hipStream_t s, const double* gprev, double wprev, double* gkeep) {
   // split z: rows [z rows, min(m, (z+1) rows)), rows a multiple of 32 (whole K-steps of the
   // vector path); splits past the end contribute zero tiles
   const int64_t rows = round_up(ceil_div(m, splits), 32);
@@ -396,7 +401,7 @@ void gram_tn(int64_t m, int64_t d, const double* SA, int64_t ldsa, double nu2, c
     splits = full + (tail > 0 ? 1 : 0);
   }
   hipLaunchKernelGGL(gram_reduce_kernel<double>, dim3((unsigned)ceil_div(dp * dp, 256)), dim3(256), 0, s, part, splits,
-                     d, dp, nu2, lam, G);
+                     d, dp, nu2, lam, G, gprev, wprev, gkeep);
   AES_LAUNCH_CHECK();
 }
 
@@ -552,7 +557,7 @@ void gram_tn_bf16(int64_t m, int64_t d, const __hip_bfloat16* SA, int64_t ldsa, 
   hipLaunchKernelGGL(gram_bf16_kernel, grid, dim3(256), 0, s, m, d, SA, ldsa, rows, part, dp, vec);
   AES_LAUNCH_CHECK();
   hipLaunchKernelGGL(gram_reduce_kernel<float>, dim3((unsigned)ceil_div(dp * dp, 256)), dim3(256), 0, s, part, splits, d,
-                     dp, nu2, lam, G);
+                     dp, nu2, lam, G, (const double*)nullptr, 0.0, (double*)nullptr);
   AES_LAUNCH_CHECK();
 }
 

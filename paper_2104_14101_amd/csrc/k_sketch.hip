@@ -775,4 +775,173 @@ void launch_gather_rows(int64_t npad, int64_t d, const double* Y, const int32_t*
   AES_LAUNCH_CHECK();
 }
 
+// ---------------------------------------------------------------------------------------
+// Nested SRHT: the key order of the padded rows.  A bucket sort on the top log2(npad) bits of
+// the row key (uniform keys: about one per bucket): count per bucket, exclusive scan of the
+// counts, scatter (integer atomics hand out the slots of a bucket in any order), then each
+// bucket is insertion-sorted by (key, row), so the result does not depend on that order.
+// ---------------------------------------------------------------------------------------
+constexpr int kScanBlk = 1024;
+
+size_t keyorder_sum_elems(int64_t npad) { return (size_t)ceil_div(npad, kScanBlk); }
+
+__device__ __forceinline__ int64_t key_bucket(uint64_t key, int shift) {
+  return shift >= 64 ? 0 : (int64_t)(key >> shift);
+}
+
+__global__ void keyorder_zero_kernel(int64_t npad, uint32_t* __restrict__ cnt, uint32_t* __restrict__ cur) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npad) return;
+  cnt[i] = 0;
+  cur[i] = 0;
+}
+
+__global__ void keyorder_count_kernel(const uint64_t* __restrict__ keys, int64_t npad, int shift,
+                                      uint32_t* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npad) return;
+  atomicAdd(&cnt[key_bucket(keys[i], shift)], 1u);
+}
+
+// off[i] = exclusive prefix of cnt within its block of kScanBlk; bsum[block] = the block's total
+__global__ __launch_bounds__(kScanBlk) void keyorder_scan_block_kernel(const uint32_t* __restrict__ cnt, int64_t npad,
+                                                                       uint32_t* __restrict__ off,
+                                                                       uint32_t* __restrict__ bsum) {
+  __shared__ uint32_t sv[kScanBlk];
+  const int t = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * kScanBlk + t;
+  const uint32_t v = i < npad ? cnt[i] : 0u;
+  sv[t] = v;
+  __syncthreads();
+  for (int o = 1; o < kScanBlk; o <<= 1) {
+    const uint32_t a = t >= o ? sv[t - o] : 0u;
+    __syncthreads();
+    sv[t] += a;
+    __syncthreads();
+  }
+  if (i < npad) off[i] = sv[t] - v;
+  if (t == kScanBlk - 1) bsum[blockIdx.x] = sv[t];
+}
+
+// exclusive scan of the block totals in place (one workgroup, chunks of kScanBlk in order)
+__global__ __launch_bounds__(kScanBlk) void keyorder_scan_sums_kernel(uint32_t* __restrict__ bsum, int64_t nb) {
+  __shared__ uint32_t sv[kScanBlk];
+  __shared__ uint32_t carry;
+  const int t = threadIdx.x;
+  if (t == 0) carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < nb; base += kScanBlk) {
+    const int64_t i = base + t;
+    const uint32_t v = i < nb ? bsum[i] : 0u;
+    sv[t] = v;
+    __syncthreads();
+    for (int o = 1; o < kScanBlk; o <<= 1) {
+      const uint32_t a = t >= o ? sv[t - o] : 0u;
+      __syncthreads();
+      sv[t] += a;
+      __syncthreads();
+    }
+    if (i < nb) bsum[i] = carry + sv[t] - v;
+    __syncthreads();
+    if (t == kScanBlk - 1) carry += sv[t];
+    __syncthreads();
+  }
+}
+
+__global__ void keyorder_scatter_kernel(const uint64_t* __restrict__ keys, int64_t npad, int shift,
+                                        uint32_t* __restrict__ off, const uint32_t* __restrict__ bsum,
+                                        uint32_t* __restrict__ cur, uint64_t* __restrict__ skey,
+                                        int32_t* __restrict__ order) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npad) return;
+  const uint64_t key = keys[i];
+  const int64_t b = key_bucket(key, shift);
+  const int64_t slot = (int64_t)off[b] + bsum[b / kScanBlk] + atomicAdd(&cur[b], 1u);
+  skey[slot] = key;
+  order[slot] = (int32_t)i;
+}
+
+// one thread per bucket: insertion sort of its slots by (key, row)
+__global__ void keyorder_bucket_kernel(int64_t npad, const uint32_t* __restrict__ cnt,
+                                       const uint32_t* __restrict__ off, const uint32_t* __restrict__ bsum,
+                                       uint64_t* __restrict__ skey, int32_t* __restrict__ order) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= npad) return;
+  const uint32_t len = cnt[b];
+  if (len < 2) return;
+  const int64_t base = (int64_t)off[b] + bsum[b / kScanBlk];
+  for (uint32_t j = 1; j < len; ++j) {
+    const uint64_t k = skey[base + j];
+    const int32_t r = order[base + j];
+    uint32_t q = j;
+    while (q > 0) {
+      const uint64_t kp = skey[base + q - 1];
+      const int32_t rp = order[base + q - 1];
+      if (kp < k || (kp == k && rp < r)) break;
+      skey[base + q] = kp;
+      order[base + q] = rp;
+      --q;
+    }
+    skey[base + q] = k;
+    order[base + q] = r;
+  }
+}
+
+void launch_srht_key_order(uint64_t seed, int32_t problem, int64_t npad, const KeyOrderScratch& sc, int32_t* order,
+                           hipStream_t s) {
+  if (npad <= 0) return;
+  const RngKey key = make_key(seed, problem, 0);
+  const int shift = 64 - __builtin_ctzll((unsigned long long)npad);
+  const unsigned g = (unsigned)ceil_div(npad, 256);
+  const int64_t nb = ceil_div(npad, kScanBlk);
+  hipLaunchKernelGGL(rowkeys_kernel, dim3(g), dim3(256), 0, s, key.k0, key.k1, npad, sc.keys);
+  AES_LAUNCH_CHECK();
+  hipLaunchKernelGGL(keyorder_zero_kernel, dim3(g), dim3(256), 0, s, npad, sc.cnt, sc.cur);
+  AES_LAUNCH_CHECK();
+  hipLaunchKernelGGL(keyorder_count_kernel, dim3(g), dim3(256), 0, s, sc.keys, npad, shift, sc.cnt);
+  AES_LAUNCH_CHECK();
+  hipLaunchKernelGGL(keyorder_scan_block_kernel, dim3((unsigned)nb), dim3(kScanBlk), 0, s, sc.cnt, npad, sc.off,
+                     sc.bsum);
+  AES_LAUNCH_CHECK();
+  hipLaunchKernelGGL(keyorder_scan_sums_kernel, dim3(1), dim3(kScanBlk), 0, s, sc.bsum, nb);
+  AES_LAUNCH_CHECK();
+  hipLaunchKernelGGL(keyorder_scatter_kernel, dim3(g), dim3(256), 0, s, sc.keys, npad, shift, sc.off, sc.bsum, sc.cur,
+                     sc.skey, order);
+  AES_LAUNCH_CHECK();
+  hipLaunchKernelGGL(keyorder_bucket_kernel, dim3(g), dim3(256), 0, s, npad, sc.cnt, sc.off, sc.bsum, sc.skey, order);
+  AES_LAUNCH_CHECK();
+}
+
+// SA[r, :] = scale * Y[order[r], :] for r < m: one wave per output row, four 8-byte loads in
+// flight per lane.
+__global__ __launch_bounds__(256) void gather_ordered_kernel(int64_t m, int64_t d, const double* __restrict__ Y,
+                                                             const int32_t* __restrict__ order, double scale,
+                                                             double* __restrict__ SA, int64_t ldsa) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t r = wave; r < m; r += nwaves) {
+    const double* src = Y + (int64_t)order[r] * d;
+    double* dst = SA + r * ldsa;
+    int64_t j = lane;
+    for (; j + 3 * 64 < d; j += 4 * 64) {
+      double v[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] = src[j + 64 * k];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) dst[j + 64 * k] = v[k] * scale;
+    }
+    for (; j < d; j += 64) dst[j] = src[j] * scale;
+  }
+}
+
+void launch_gather_ordered(int64_t m, int64_t d, const double* Y, const int32_t* order, double scale, double* SA,
+                           int64_t ldsa, hipStream_t s) {
+  if (m <= 0 || d <= 0) return;
+  int64_t blocks = ceil_div(m, 4);
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(gather_ordered_kernel, dim3((unsigned)blocks), dim3(256), 0, s, m, d, Y, order, scale, SA, ldsa);
+  AES_LAUNCH_CHECK();
+}
+
 }  // namespace aes

@@ -128,6 +128,23 @@ void launch_srht_apply(const TIN* A, int64_t n, int64_t d, int64_t lda, const do
 // (Y: the stored normalised transform, npad x d, ld d; pos from launch_srht_select).
 void launch_gather_rows(int64_t npad, int64_t d, const double* Y, const int32_t* pos, double scale, double* SA,
                         int64_t ldsa, hipStream_t s);
+// Nested SRHT: order[r] (r < npad) = the padded row with the r-th smallest row key of sketch
+// index 0, ties to the smaller row.  Scratch: keys (npad), cnt / cur / off (npad each), skey
+// (npad) and bsum (keyorder_sum_elems(npad)).
+struct KeyOrderScratch {
+  uint64_t* keys;
+  uint32_t* cnt;
+  uint32_t* cur;
+  uint32_t* off;
+  uint32_t* bsum;
+  uint64_t* skey;
+};
+size_t keyorder_sum_elems(int64_t npad);
+void launch_srht_key_order(uint64_t seed, int32_t problem, int64_t npad, const KeyOrderScratch& sc, int32_t* order,
+                           hipStream_t s);
+// SA[r, :] = scale * Y[order[r], :] for r < m (Y: the stored normalised transform, ld d).
+void launch_gather_ordered(int64_t m, int64_t d, const double* Y, const int32_t* order, double scale, double* SA,
+                           int64_t ldsa, hipStream_t s);
 // Gaussian sketch SA (m x d, ld d) = G A / sqrt(m): the plan sizes the generated slab of G
 // (gt_elems doubles) and the split-K partials (part_elems doubles, none with one split).
 struct GaussPlan {
@@ -179,9 +196,13 @@ void launch_sum_parts(int64_t count, int splits, int64_t stride, const double* p
 void narrow_f64(int64_t count, const double* src, float* dst, hipStream_t s);
 // Gram of a sketch with split-K: G (dp x dp, ld dp) lower = SA^T SA + nu2 diag(lam) (padding
 // rows/cols beyond d get identity).  part: scratch of splits * dp * dp doubles.
+// Incremental form: with gprev (dp x dp lower, a Gram without the nu2 diag(lam) term) the sum
+// becomes wprev * gprev + SA^T SA; gkeep (may equal gprev) receives that sum before the diagonal
+// term is added.
 int gram_splits(int num_cu, int64_t m, int64_t d, bool fp64);
 void gram_tn(int64_t m, int64_t d, const double* SA, int64_t ldsa, double nu2, const double* lam,
-             double* part, int splits, double* G, int64_t dp, hipStream_t s);
+             double* part, int splits, double* G, int64_t dp, hipStream_t s, const double* gprev = nullptr,
+             double wprev = 0.0, double* gkeep = nullptr);
 // BF16 SA (m x d, ld ldsa) with FP32 accumulation on MFMA; G as above in FP64.
 void gram_tn_bf16(int64_t m, int64_t d, const __hip_bfloat16* SA, int64_t ldsa, double nu2,
                   const double* lam, float* part, int splits, double* G, int64_t dp, hipStream_t s);

@@ -84,7 +84,8 @@ def test_binding_enums_match_the_header():
     vals = {k: int(v) for k, v in re.findall(r"\b(AES_[A-Z0-9_]+)\s*=\s*(\d+)", hdr)}
     expect = {
         "METHODS": {"pcg": "AES_PCG", "ihs": "AES_IHS", "cg": "AES_CG", "polyak": "AES_POLYAK"},
-        "SKETCHES": {"srht": "AES_SRHT", "gauss": "AES_GAUSS", "sjlt": "AES_SJLT", "srht_reuse": "AES_SRHT_REUSE"},
+        "SKETCHES": {"srht": "AES_SRHT", "gauss": "AES_GAUSS", "sjlt": "AES_SJLT", "srht_reuse": "AES_SRHT_REUSE",
+                     "srht_nested": "AES_SRHT_NESTED"},
         "PRECISIONS": {"fp64": "AES_FP64", "mixed": "AES_MIXED", "mixed_fp32": "AES_MIXED_FP32"},
         "STOPS": {"xrel": "AES_STOP_XREL", "dtilde_rel": "AES_STOP_DTILDE_REL", "fixed": "AES_STOP_FIXED",
                   "remark": "AES_STOP_REMARK"},

@@ -93,6 +93,27 @@ def test_srht_reuse_float_data(n, d, m, k):
     np.testing.assert_allclose(SA, osk.srht_reuse(A, m, 4, k), rtol=1e-15, atol=0)
 
 
+@pytest.mark.parametrize("n,d,m", [(4000, 33, 1024), (16384, 64, 256), (16384, 64, 16384), (13, 3, 4), (3, 2, 1)])
+def test_srht_nested_bit_exact_on_integers(n, d, m):
+    # n' and n'/m powers of 4: exact transform and rescale; the row order (the device's bucket
+    # sort of the row keys) must equal the oracle's stable argsort, prefix by prefix
+    rng = np.random.default_rng(n + d + m + 1)
+    A = rng.integers(-50, 51, size=(n, d)).astype(np.float64)
+    for k in (0, 3):  # the sketch index plays no part
+        SA = aes.sketch(to_dev(A), m, "srht_nested", seed=21, k=k).cpu().numpy()
+        np.testing.assert_array_equal(SA, osk.srht_nested(A, m, 21))
+
+
+@pytest.mark.parametrize("n,d,m", [(3000, 70, 100), ((1 << 20) + 5, 4, 1 << 20)])
+def test_srht_nested_float_data(n, d, m):
+    # the second case has n' = 2^21: 2048 blocks of the bucket-count scan (two chunks of the
+    # block-total scan) and a million rows whose order is checked
+    rng = np.random.default_rng(7)
+    A = rng.standard_normal((n, d))
+    SA = aes.sketch(to_dev(A), m, "srht_nested", seed=4, k=0).cpu().numpy()
+    np.testing.assert_allclose(SA, osk.srht_nested(A, m, 4), rtol=1e-15, atol=0)
+
+
 def test_srht_full_size_sampled_rows():
     P = synth.make_problem(65536, 2048, "pow:1", 1e-3, seed=12, backend="torch", device="cuda")
     A = P["A"]

@@ -79,6 +79,23 @@ def test_srht_reuse_trajectory_and_accuracy(small, method):
         aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], sketch="srht_reuse", precision="mixed")
 
 
+@pytest.mark.parametrize("method", ["pcg", "ihs"])
+def test_srht_nested_trajectory_and_accuracy(small, method):
+    # d = 256: the resizes from m = 256 on form the Gram incrementally on the device, the oracle
+    # forms it from the whole sketch
+    kw = dict(method=method, sketch="srht_nested", m_init=8, seed=1, tol=1e-10)
+    x, info = aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], trace_cap=256, **kw)
+    xo, io = solvers.solve(small["A"], small["b"], small["nu"], small["lam"], solvers.Options(**kw))
+    assert info["status"] == "ok"
+    assert _traj_gpu(info) == _traj_cpu(io)
+    assert info["final_m"] == io.final_m and info["a_passes"] == io.a_passes
+    assert info["final_m"] >= 1024  # at least two incremental Grams
+    assert reference.rel_error(x.cpu().numpy(), small["xref"]) <= 1e-10
+    assert reference.rel_error(x.cpu().numpy(), xo) <= 1e-9
+    with pytest.raises(aes.AesError, match="invalid_arg"):
+        aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], sketch="srht_nested", precision="mixed")
+
+
 @pytest.mark.parametrize("kw", [dict(m_init=8), dict(m_init=512, adaptive=False)])
 def test_polyak_trajectory_and_accuracy(small, kw):
     kw = dict(method="polyak", seed=1, tol=1e-10, max_iter=500, **kw)
