@@ -396,7 +396,8 @@ def variants_leg(aes, torch, A, b, nu, lam, w, P_np, args):
 def paper_leg(aes, torch, synth, n, d, nus, cross=False, cg_iters=20000):
     """The synthetic experiments of Sec. 5 (sigma_j = 0.995^j, Lambda = I, b = A^T y) at n x d over
     a sweep of nu, with the paper's comparison set: adaptive PCG and IHS from m = 1 (SRHT and
-    SJLT), PCG with the fixed size m = 2d, and unpreconditioned CG; plus adaptive PCG with the
+    SJLT), PCG with the fixed size m = 2d, unpreconditioned CG and the direct Cholesky solve of
+    the full H (one untimed and one timed solve); plus adaptive PCG with the
     transform-reuse SRHT (a variant; not with cross=True, to keep E3's footprint).  One timed solve each (the
     first solve of each problem is repeated untimed).  Error against the oracle's refined
     reference; with cross=True (sizes the host oracle cannot take) against a PCG solve at
@@ -418,7 +419,8 @@ def paper_leg(aes, torch, synth, n, d, nus, cross=False, cg_iters=20000):
             ("adaptive_ihs_sjlt", dict(method="ihs", sketch="sjlt", m_init=1)),
             ("pcg_m2d_srht", dict(method="pcg", sketch="srht", m_init=2 * d, adaptive=False)),
             ("pcg_m2d_sjlt", dict(method="pcg", sketch="sjlt", m_init=2 * d, adaptive=False)),
-            ("cg", dict(method="cg", max_iter=cg_iters))]
+            ("cg", dict(method="cg", max_iter=cg_iters)),
+            ("direct", None)]
     if not cross:
         # the stored transform of the reuse variant would add n' x d doubles (58.7 GB in E3)
         runs.insert(2, ("adaptive_pcg_srht_reuse", dict(method="pcg", sketch="srht_reuse", m_init=1)))
@@ -433,6 +435,18 @@ def paper_leg(aes, torch, synth, n, d, nus, cross=False, cg_iters=20000):
             xr = reference.reference_solution(P_np["A"], P_np["b"], nu, None, spectral=(P_np["V"], P_np["sigma"]))
         res = {"d_e": reference.effective_dimension_closed(P["sigma"], nu)}
         for name, kw in runs:
+            if name == "direct":
+                # the direct baseline: one untimed and one timed Cholesky solve of the full H
+                aes.solve_direct(A, b, nu)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x = aes.solve_direct(A, b, nu)
+                torch.cuda.synchronize()
+                sec = time.perf_counter() - t0
+                err = float(np.max(reference.rel_error(x.cpu().numpy(), xr)))
+                res[name] = {"s_per_solve": sec, "rel_err": err, "valid": bool(err <= 1e-10), "status": "ok"}
+                print(json.dumps({"paper": [n, d, nu, name, round(sec, 5)]}), file=sys.stderr, flush=True)
+                continue
             opts = dict(seed=1, tol=1e-10, max_iter=2000)
             opts.update(kw)
             x, infos, sec = timed_solves(aes, torch, A, b, nu, None, opts, 1, 1 if name == runs[0][0] else 0)

@@ -179,6 +179,23 @@ aes_status aes_solve(aes_handle h, void* stream, int64_t n, int64_t d, int64_t c
                      int64_t ldx, aes_info* info);
 
 /*
+ * aes_solve_direct -- the direct baseline of Sec. 5 (a Cholesky factorisation of the full
+ * Hessian): G = A^T A + nu^2 Lambda in FP64 (O(n d^2) on MFMA), its lower Cholesky factor and
+ * inverse factor (O(d^3)), then x = L^-T (L^-1 b).  No sketch, no iteration; the error of x is
+ * that of a Cholesky solve, about kappa(H) times the unit roundoff.
+ *   A       device, n x d, row-major, lda >= d; 1 <= d <= 32768
+ *   b       device, d x c, ldb >= c, 1 <= c <= 32
+ *   lambda  device, length d, all > 0; NULL means Lambda = I
+ *   x       device, d x c output, ldx >= c (written only on success)
+ * Workspace: four (d rounded up to 64)^2 FP64 matrices (plus split-K partials of the Gram) in the
+ * handle's pool.  Synchronises `stream` to read the factorisation flag.  Returns AES_OK,
+ * AES_ERR_INVALID_ARG (x untouched) or AES_ERR_NOT_SPD (a pivot was not positive; x untouched).
+ */
+aes_status aes_solve_direct(aes_handle h, void* stream, int64_t n, int64_t d, int64_t c, const double* A,
+                            int64_t lda, const double* b, int64_t ldb, double nu, const double* lambda, double* x,
+                            int64_t ldx);
+
+/*
  * aes_solve_dual -- the same problem H x = b through its dual (Sec. 1, eq. "dual optimization
  * problem"), for n < d: with B = Lambda^{-1/2} A^T (d x n) the dual variable w in R^n solves
  * (B^T B + nu^2 I_n) w = A Lambda^{-1} b, which aes_solve's algorithm handles with data matrix B

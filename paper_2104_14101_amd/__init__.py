@@ -252,6 +252,31 @@ def solve_dual(A, b, nu, lam=None, tol=1e-10, x=None, check=True, **opts):
     return (x.reshape(d) if squeeze else x), out
 
 
+def solve_direct(A, b, nu, lam=None, x=None):
+    """The direct baseline of Sec. 5: Cholesky of the full H = A^T A + nu^2 Lambda.  Returns x.
+
+    A (n x d), b (d or d x c, c <= 32), lam and x as for ``solve``; FP64 only.
+    """
+    _req(A, "A", (2,))
+    _req(b, "b", (1, 2))
+    A, lda = _rowmajor(A)
+    n, d = A.shape
+    squeeze = b.dim() == 1
+    b2 = b.reshape(d, 1) if squeeze else b
+    b2, ldb = _rowmajor(b2)
+    c = b2.shape[1]
+    if b2.device != A.device:
+        raise ValueError(f"b is on {b2.device}, A on {A.device}")
+    lam = _lam(lam, d, A.device)
+    given = x
+    x = _out(x, d, c, A.device, squeeze)
+    _check(*_call(A.device, _lib().aes_solve_direct, _stream(A.device), n, d, c, _ptr(A), lda, _ptr(b2), ldb,
+                  float(nu), _ptr(lam), _ptr(x), x.stride(0)))
+    if given is not None:
+        return given
+    return x.reshape(d) if squeeze else x
+
+
 def solve_batched(problems, tol=1e-10, **opts):
     """Solve a list of problems dict(A, b, nu, lam=None); problem p uses Philox stream p.
 

@@ -59,6 +59,8 @@ _PROTOS = {
                           c_void_p, c_double, POINTER(Options), c_void_p, c_int64, POINTER(Info)]),
     "aes_solve_dual": (c_int, [c_void_p, c_void_p, c_int64, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_int64,
                                c_double, c_void_p, c_double, POINTER(Options), c_void_p, c_int64, POINTER(Info)]),
+    "aes_solve_direct": (c_int, [c_void_p, c_void_p, c_int64, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_int64,
+                                 c_double, c_void_p, c_void_p, c_int64]),
     "aes_solve_batched": (c_int, [c_void_p, c_void_p, c_int64, POINTER(Problem), c_double, POINTER(Options),
                                   POINTER(Info)]),
     "aes_solve_keep": (c_int, [c_void_p, c_void_p, c_int64, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_int64,

@@ -2622,6 +2622,48 @@ aes_status aes_factor(aes_handle h, void* stream, int64_t m, int64_t d, const do
   });
 }
 
+aes_status aes_solve_direct(aes_handle h, void* stream, int64_t n, int64_t d, int64_t c, const double* A, int64_t lda,
+                            const double* b, int64_t ldb, double nu, const double* lambda, double* x, int64_t ldx) {
+  // The direct baseline of Sec. 5: H = A^T A + nu^2 Lambda formed in full (the Gram kernel with
+  // S = I, O(n d^2)), its Cholesky factor and inverse factor (O(d^3)), x = L^-T (L^-1 b).
+  if (!h) return AES_ERR_INVALID_ARG;
+  return guard(h, [&] {
+    auto bad = [](const char* m) { throw StatusError(AES_ERR_INVALID_ARG, m); };
+    if (n < 1 || d < 1 || c < 1) bad("n, d and c must be >= 1");
+    if (c > 32) bad("at most 32 right-hand sides");
+    if (d > kMaxD) bad("d must be <= 32768");
+    if (lda < d) bad("lda < d");
+    if (ldb < c || ldx < c) bad("ldb and ldx must be >= c");
+    if (!A || !b || !x) bad("A, b and x must be non-null");
+    if (!(nu > 0) || !std::isfinite(nu)) bad("nu must be finite and > 0");
+    set_device(h);
+    hipStream_t s = (hipStream_t)stream;
+    const int C = (int)next_pow2(c);
+    const int64_t fp = round_up(d, 64);
+    double* G = h->buf<double>("dir.G", (size_t)fp * fp);
+    const int splits = gram_splits(h->num_cu, n, d, true);
+    double* part = h->buf<double>("dir.part", (size_t)splits * fp * fp);
+    gram_tn(n, d, A, lda, nu * nu, lambda, part, splits, G, fp, s);
+    int* flag = h->buf<int>("dir.flag", 1);
+    AES_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+    double* linv = h->buf<double>("dir.linv", (size_t)fp * fp);
+    double* linvT = h->buf<double>("dir.linvT", (size_t)fp * fp);
+    cholinv(G, fp, linv, h->buf<double>("dir.tmp", cholinv_tmp_size(fp)), flag, false, s);
+    launch_transpose(fp, fp, linv, fp, linvT, fp, s);
+    double* bc = h->buf<double>("dir.b", (size_t)d * C);
+    double* t = h->buf<double>("dir.t", (size_t)d * C);
+    double* xc = h->buf<double>("dir.x", (size_t)d * C);
+    launch_copy_cols(d, C, b, ldb, (int)c, bc, C, s);
+    launch_rowdot(d, d, linv, fp, 1, bc, C, nullptr, 1.0, nullptr, nullptr, 1.0, t, s);
+    launch_rowdot(d, d, linvT, fp, 2, t, C, nullptr, 1.0, nullptr, nullptr, 1.0, xc, s);
+    int hf = 0;
+    AES_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    AES_HIP(hipStreamSynchronize(s));
+    if (hf) throw StatusError(AES_ERR_NOT_SPD, "Cholesky pivot is not positive");
+    launch_copy_cols(d, (int)c, xc, C, (int)c, x, ldx, s);
+  });
+}
+
 aes_status aes_precond_apply(aes_handle h, void* stream, int64_t m, int64_t d, int64_t c, const double* SA, double nu,
                              const double* lambda, const double* z, double* v) {
   if (!h) return AES_ERR_INVALID_ARG;

@@ -96,6 +96,47 @@ def test_srht_nested_trajectory_and_accuracy(small, method):
         aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], sketch="srht_nested", precision="mixed")
 
 
+def _cholesky_bound(A, nu, lam):
+    # forward error of a Cholesky solve of H (and of applying its inverse factors): a small
+    # multiple of d kappa(H) u
+    H = A.T @ A + nu ** 2 * np.diag(lam)
+    return 8 * A.shape[1] * np.linalg.cond(H) * np.finfo(np.float64).eps
+
+
+def test_direct_baseline_full_size_fixture(small):
+    x = aes.solve_direct(small["dA"], small["db"], small["nu"], small["dlam"]).cpu().numpy()
+    err = reference.rel_error(x, small["xref"])
+    assert err <= _cholesky_bound(small["A"], small["nu"], small["lam"])
+    assert err <= 1e-8
+
+
+@pytest.mark.parametrize("n,d,c,nu", [(1000, 70, 3, 1.0), (5000, 300, 1, 0.5), (777, 130, 32, 0.3)])
+def test_direct_baseline_ragged(n, d, c, nu):
+    # d = 70: the small-d Gram path and a padded factor (d -> 128); d = 300 and 130: the tiled Gram
+    # with ragged tiles; 3 and 32 right-hand sides, b and x strided
+    P = synth.make_problem(n, d, "geo:0.99", nu, lam="uniform1_10", nrhs=c, seed=n + d)
+    A, lam = P["A"], P["lam"]
+    b = P["b"].reshape(d, c)
+    xref = reference.reference_solution(A, b, nu, lam)
+    db = torch.zeros((d, c + 2), dtype=torch.float64, device="cuda")
+    db[:, :c] = to_dev(b)
+    dx = torch.full((d, c + 3), 7.0, dtype=torch.float64, device="cuda")
+    aes.solve_direct(to_dev(A), db[:, :c], nu, to_dev(lam), x=dx[:, :c])
+    assert np.all(dx[:, c:].cpu().numpy() == 7.0)
+    err = reference.rel_error(dx[:, :c].cpu().numpy(), xref)
+    assert np.max(err) <= min(1e-11, _cholesky_bound(A, nu, lam))
+
+
+def test_direct_baseline_rejects_bad_arguments(small):
+    dx = torch.full((256,), 3.0, dtype=torch.float64, device="cuda")
+    with pytest.raises(aes.AesError, match="invalid_arg"):
+        aes.solve_direct(small["dA"], small["db"], 0.0, small["dlam"], x=dx)
+    b33 = torch.zeros((256, 33), dtype=torch.float64, device="cuda")
+    with pytest.raises(aes.AesError, match="invalid_arg"):
+        aes.solve_direct(small["dA"], b33, small["nu"], small["dlam"])
+    assert torch.all(dx == 3.0)
+
+
 @pytest.mark.parametrize("kw", [dict(m_init=8), dict(m_init=512, adaptive=False)])
 def test_polyak_trajectory_and_accuracy(small, kw):
     kw = dict(method="polyak", seed=1, tol=1e-10, max_iter=500, **kw)
