@@ -39,6 +39,7 @@ Extra legs (outside the timed region of the headline value):
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -449,12 +450,20 @@ def paper_leg(aes, torch, synth, n, d, nus, cross=False, cg_iters=20000):
                 continue
             opts = dict(seed=1, tol=1e-10, max_iter=2000)
             opts.update(kw)
+            if kw.get("method") != "cg":
+                opts["trace_cap"] = 1024  # the per-attempt series (the axes of the paper's plots)
             x, infos, sec = timed_solves(aes, torch, A, b, nu, None, opts, 1, 1 if name == runs[0][0] else 0)
             err = float(np.max(reference.rel_error(x.cpu().numpy(), xr)))
             i = infos[-1]
             res[name] = {"s_per_solve": sec, "rel_err": err, "valid": bool(err <= 1e-10), "status": i["status"],
                          "iterations": i["iterations"], "final_m": i["final_m"], "a_passes": i["a_passes"],
                          "time_sketch_ms": i["time_sketch_ms"]}
+            if i.get("trace"):
+                tr = i["trace"]
+                res[name]["series"] = {
+                    "t": [e["t"] for e in tr], "m": [e["m"] for e in tr], "accept": [int(e["accept"]) for e in tr],
+                    "log10_dtilde": [round(math.log10(e["dtilde"]), 3) if e["dtilde"] > 0 else None for e in tr],
+                    "time_ms": [round(e["time_ms"], 2) for e in tr]}
             print(json.dumps({"paper": [n, d, nu, name, round(sec, 5), i["iterations"], i["final_m"]]}),
                   file=sys.stderr, flush=True)
         out["nu"][f"{nu:g}"] = res

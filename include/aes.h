@@ -103,6 +103,10 @@ typedef struct {
   double threshold;   /* log c + (t+1-I) log phi */
   int32_t accept;
   int32_t pad_;
+  double dtilde;      /* max over active columns of D (the preconditioned residual quantity of the
+                         method) at the current iterate after the attempt: D_{t+1} when accepted,
+                         else the unchanged D_t */
+  double time_ms;     /* host milliseconds from the start of the solve to the attempt's flags */
 } aes_trace_entry;
 
 typedef struct {

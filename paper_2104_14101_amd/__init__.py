@@ -179,7 +179,8 @@ def _info_dict(info, buf):
     d = info.as_dict()
     if buf is not None:
         d["trace"] = [dict(t=buf[i].t, m=buf[i].m, k=buf[i].k, log_ratio=buf[i].log_ratio,
-                           threshold=buf[i].threshold, accept=bool(buf[i].accept)) for i in range(info.trace_len)]
+                           threshold=buf[i].threshold, accept=bool(buf[i].accept), dtilde=buf[i].dtilde,
+                           time_ms=buf[i].time_ms) for i in range(info.trace_len)]
     return d
 
 

@@ -22,7 +22,7 @@ STOPS = {"xrel": 0, "dtilde_rel": 1, "fixed": 2, "remark": 3}
 
 class TraceEntry(ctypes.Structure):
     _fields_ = [("t", c_int64), ("m", c_int64), ("k", c_int64), ("log_ratio", c_double), ("threshold", c_double),
-                ("accept", c_int32), ("pad_", c_int32)]
+                ("accept", c_int32), ("pad_", c_int32), ("dtilde", c_double), ("time_ms", c_double)]
 
 
 class Options(ctypes.Structure):

@@ -637,6 +637,8 @@ class Solver {
       e.threshold = thr;
       e.accept = accept ? 1 : 0;
       e.pad_ = 0;
+      e.dtilde = fl_[5];
+      e.time_ms = now_ms() - t0_ms_;
     }
   }
 
@@ -1494,6 +1496,7 @@ class Solver {
   double stop_scale_ = 0, stop_sr_ = 1, tol2_ = 0;
   double fl_[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int64_t iters_ = 0, attempts_ = 0, resketches_ = 0, a_passes_ = 0, sweeps_ = 0, trace_len_ = 0;
+  double t0_ms_ = now_ms();  // start of the solve (trace time stamps)
   int m_cap_reached_ = 0;
   int64_t n_events_ = 0;
   std::vector<int64_t> skip_events_;  // timing events of speculative steps that did not run

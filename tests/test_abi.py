@@ -32,6 +32,7 @@ int main(void) {
          sizeof(aes_info), sizeof(aes_trace_entry), sizeof(aes_problem));
   P(aes_options, rho); P(aes_options, seed); P(aes_options, force_reject_at); P(aes_options, trace);
   P(aes_options, x0); P(aes_info, dtilde_final); P(aes_info, status); P(aes_problem, nu); P(aes_problem, ldx);
+  P(aes_trace_entry, log_ratio); P(aes_trace_entry, dtilde); P(aes_trace_entry, time_ms);
   return 0;
 }
 ''')
@@ -46,7 +47,8 @@ int main(void) {
     for key, val in out.items():
         if "." in key:
             T, f = key.split(".")
-            cls = {"aes_options": B.Options, "aes_info": B.Info, "aes_problem": B.Problem}[T]
+            cls = {"aes_options": B.Options, "aes_info": B.Info, "aes_problem": B.Problem,
+                   "aes_trace_entry": B.TraceEntry}[T]
             fname = {"lam": "lam"}.get(f, f)
             assert getattr(cls, fname).offset == int(val), key
 

@@ -90,6 +90,16 @@ def test_srht_nested_trajectory_and_accuracy(small, method):
     assert _traj_gpu(info) == _traj_cpu(io)
     assert info["final_m"] == io.final_m and info["a_passes"] == io.a_passes
     assert info["final_m"] >= 1024  # at least two incremental Grams
+    # trace series: D after each attempt; within one sketch (same m), accepted attempts'
+    # log D differences equal their log-ratio differences (one right-hand side); time stamps grow
+    tr = info["trace"]
+    assert all(e["dtilde"] > 0 for e in tr)
+    assert all(b_["time_ms"] >= a["time_ms"] >= 0 for a, b_ in zip(tr, tr[1:]))
+    acc = [e for e in tr if e["accept"]]
+    pairs = [(a, b_) for a, b_ in zip(acc, acc[1:]) if a["m"] == b_["m"] and a["t"] + 1 == b_["t"]]
+    assert pairs
+    for a, b_ in pairs:
+        assert np.isclose(np.log(b_["dtilde"] / a["dtilde"]), b_["log_ratio"] - a["log_ratio"], rtol=0, atol=1e-9)
     assert reference.rel_error(x.cpu().numpy(), small["xref"]) <= 1e-10
     assert reference.rel_error(x.cpu().numpy(), xo) <= 1e-9
     with pytest.raises(aes.AesError, match="invalid_arg"):
