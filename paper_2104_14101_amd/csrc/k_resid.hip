@@ -85,21 +85,24 @@ __global__ __launch_bounds__(kRT) void resid_ax_kernel(int64_t n, int64_t d, con
   }
 }
 
-// pass 1 for C >= 8: a workgroup owns RB = 512 / C consecutive rows; thread t takes column
-// c = t % C of rows t / C and t / C + 256 / C, summing k in increasing order.  K-chunks of 64
-// columns of the row block and the matching 64 rows of x are staged in LDS, so x is read once
-// per RB rows rather than once per row.
+// pass 1 for C >= 8: a workgroup owns RB = R 256 / C consecutive rows (R = 4 for C >= 16, else
+// 2); thread t takes column c = t % C of rows t / C + q 256 / C (q < R), R independent chains,
+// summing k in increasing order.  K-chunks of 64 columns of the row block and the matching 64
+// rows of x are staged in LDS, so x is read once per RB rows rather than once per row.
 constexpr int kRK = 64;
+constexpr int ax_tiled_rows(int C) { return (C >= 16 ? 4 : 2) * (kRT / C); }
 template <int C>
 __global__ __launch_bounds__(kRT) void resid_ax_tiled_kernel(int64_t n, int64_t d, const double* __restrict__ A,
                                                              int64_t lda, const double* __restrict__ x,
                                                              double* __restrict__ zh, double* __restrict__ zl) {
-  constexpr int TR = kRT / C, RB = 2 * TR;
+  constexpr int TR = kRT / C, RB = ax_tiled_rows(C), R = RB / TR;
   __shared__ double As[RB][kRK + 1];
   __shared__ double Xs[kRK][C];
   const int t = threadIdx.x, c = t % C, tr = t / C;
   const int64_t i0 = (int64_t)blockIdx.x * RB;
-  double h0 = 0.0, l0 = 0.0, h1 = 0.0, l1 = 0.0;
+  double h[R], l[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) h[q] = l[q] = 0.0;
   for (int64_t k0 = 0; k0 < d; k0 += kRK) {
     const int kc = (int)(d - k0 < kRK ? d - k0 : kRK);
     // row block: element e = t + 256 q -> (row e / 64, column e % 64), 512 consecutive bytes per row
@@ -118,19 +121,18 @@ __global__ __launch_bounds__(kRT) void resid_ax_tiled_kernel(int64_t n, int64_t 
     __syncthreads();
     for (int k = 0; k < kc; ++k) {
       const double xv = Xs[k][c];
-      dd_fma(h0, l0, As[tr][k], xv, 0.0);
-      dd_fma(h1, l1, As[tr + TR][k], xv, 0.0);
+#pragma unroll
+      for (int q = 0; q < R; ++q) dd_fma(h[q], l[q], As[tr + TR * q][k], xv, 0.0);
     }
     __syncthreads();
   }
-  const int64_t ia = i0 + tr, ib = i0 + tr + TR;
-  if (ia < n) {
-    zh[ia * C + c] = h0;
-    zl[ia * C + c] = l0;
-  }
-  if (ib < n) {
-    zh[ib * C + c] = h1;
-    zl[ib * C + c] = l1;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int64_t i = i0 + tr + TR * q;
+    if (i < n) {
+      zh[i * C + c] = h[q];
+      zl[i * C + c] = l[q];
+    }
   }
 }
 
@@ -198,11 +200,12 @@ __global__ __launch_bounds__(kRT) void resid_atz_tiled_kernel(int64_t n, int64_t
       Zs[1][r][cc] = r < rc ? zl[(i0 + r) * C + cc] : 0.0;
     }
     __syncthreads();
+    // no column bound here: columns past d hold zeros in As and add nothing (their sums are never
+    // stored), and a branch per accumulator would serialise the S independent chains
     for (int r = 0; r < rc; ++r) {
       const double h = Zs[0][r][c], l = Zs[1][r][c];
 #pragma unroll
-      for (int s = 0; s < S; ++s)
-        if (j0 + jj + J * s < d) dd_fma(hi[s], lo[s], As[r][jj + J * s], h, l);
+      for (int s = 0; s < S; ++s) dd_fma(hi[s], lo[s], As[r][jj + J * s], h, l);
     }
     __syncthreads();
   }
@@ -367,7 +370,7 @@ void launch_residual_dd(int num_cu, int64_t n, int64_t d, int C, const double* A
 #define AES_RESID_CASE(CV)                                                                                        \
   case CV:                                                                                                        \
     if (CV >= 8)                                                                                                  \
-      hipLaunchKernelGGL(resid_ax_tiled_kernel<(CV >= 8 ? CV : 8)>, dim3((unsigned)ceil_div(n, 512 / (CV >= 8 ? CV : 8))), \
+      hipLaunchKernelGGL(resid_ax_tiled_kernel<(CV >= 8 ? CV : 8)>, dim3((unsigned)ceil_div(n, ax_tiled_rows(CV >= 8 ? CV : 8))), \
                          dim3(kRT), 0, s, n, d, A, lda, x, zh, zl);                                               \
     else                                                                                                          \
       hipLaunchKernelGGL(resid_ax_kernel<CV>, dim3(g1), dim3(kRT), 0, s, n, d, A, lda, x, zh, zl);                \
