@@ -120,13 +120,21 @@ def test_direct_baseline_full_size_fixture(small):
     assert err <= 1e-8
 
 
-@pytest.mark.parametrize("n,d,c,nu", [(1000, 70, 3, 1.0), (5000, 300, 1, 0.5), (777, 130, 32, 0.3)])
+@pytest.mark.parametrize("n,d,c,nu", [(1000, 70, 3, 1.0), (5000, 300, 1, 0.5), (777, 130, 32, 0.3),
+                                      (100, 300, 2, 0.5)])
 def test_direct_baseline_ragged(n, d, c, nu):
     # d = 70: the small-d Gram path and a padded factor (d -> 128); d = 300 and 130: the tiled Gram
-    # with ragged tiles; 3 and 32 right-hand sides, b and x strided
-    P = synth.make_problem(n, d, "geo:0.99", nu, lam="uniform1_10", nrhs=c, seed=n + d)
-    A, lam = P["A"], P["lam"]
-    b = P["b"].reshape(d, c)
+    # with ragged tiles; n = 100 < d = 300: H is nu^2 Lambda plus a rank-100 term; 3 and 32
+    # right-hand sides, b and x strided
+    if n >= d:
+        P = synth.make_problem(n, d, "geo:0.99", nu, lam="uniform1_10", nrhs=c, seed=n + d)
+        A, lam = P["A"], P["lam"]
+        b = P["b"].reshape(d, c)
+    else:
+        rng = np.random.default_rng(n + d)
+        A = rng.standard_normal((n, d)) / np.sqrt(n)
+        lam = 1.0 + 9.0 * rng.random(d)
+        b = rng.standard_normal((d, c))
     xref = reference.reference_solution(A, b, nu, lam)
     db = torch.zeros((d, c + 2), dtype=torch.float64, device="cuda")
     db[:, :c] = to_dev(b)
