@@ -155,6 +155,22 @@ def test_direct_baseline_rejects_bad_arguments(small):
     assert torch.all(dx == 3.0)
 
 
+@pytest.mark.parametrize("kw,final_m", [(dict(m_init=8, m_max=600), 600), (dict(method="ihs", m_init=8, m_max=600), 600),
+                                        (dict(m_init=512), 1024)])
+def test_srht_nested_uneven_cap_and_cholesky_start(small, kw, final_m):
+    # m_max = 600: the last resize grows 512 -> 600, so the kept Gram enters with weight 512/600;
+    # m_init = 512 >= d: the first sketch already takes the Cholesky branch (a full Gram), the
+    # next one is incremental
+    kw = dict(sketch="srht_nested", seed=1, tol=1e-10, **kw)
+    x, info = aes.solve(small["dA"], small["db"], small["nu"], small["dlam"], trace_cap=256, **kw)
+    xo, io = solvers.solve(small["A"], small["b"], small["nu"], small["lam"], solvers.Options(**kw))
+    assert info["status"] == "ok"
+    assert _traj_gpu(info) == _traj_cpu(io)
+    assert info["final_m"] == io.final_m == final_m
+    assert reference.rel_error(x.cpu().numpy(), small["xref"]) <= 1e-10
+    assert reference.rel_error(x.cpu().numpy(), xo) <= 1e-9
+
+
 @pytest.mark.parametrize("kw", [dict(m_init=8), dict(m_init=512, adaptive=False)])
 def test_polyak_trajectory_and_accuracy(small, kw):
     kw = dict(method="polyak", seed=1, tol=1e-10, max_iter=500, **kw)
@@ -368,22 +384,24 @@ def test_mixed_precision(small):
     assert info["refine_sweeps"] >= 2
 
 
-def test_batched_equals_singles():
+@pytest.mark.parametrize("sketch", ["srht", "srht_nested"])
+def test_batched_equals_singles(sketch):
     probs = []
     for i, (n, d) in enumerate([(2048, 64), (3000, 128), (1024, 256)]):
         P = synth.make_problem(n, d, "geo:0.98", 10.0 ** (-1 - i), nrhs=2, seed=20 + i)
         probs.append(dict(A=to_dev(P["A"]), b=to_dev(P["b"]), nu=P["nu"], xref=reference.reference_solution(
             P["A"], P["b"], P["nu"])))
-    res = aes.solve_batched(probs, tol=1e-10, m_init=16, seed=3)
+    res = aes.solve_batched(probs, tol=1e-10, m_init=16, seed=3, sketch=sketch)
     for p, (x, info) in enumerate(res):
         assert info["status"] == "ok"
         assert np.all(reference.rel_error(x.cpu().numpy(), probs[p]["xref"]) <= 1e-10)
-        xs, _ = aes.solve(probs[p]["A"], probs[p]["b"], probs[p]["nu"], m_init=16, seed=3, problem=p)
+        xs, _ = aes.solve(probs[p]["A"], probs[p]["b"], probs[p]["nu"], m_init=16, seed=3, problem=p, sketch=sketch)
         assert torch.equal(xs, x)
 
 
 # the adjoint solve runs the forward solve's method and sketch
 @pytest.mark.parametrize("opts", [dict(m_init=16), dict(m_init=16, sketch="srht_reuse"),
+                                  dict(m_init=16, sketch="srht_nested"),
                                   dict(method="polyak", m_init=512, adaptive=False)])
 def test_autograd_adjoint(opts):
     P = synth.make_problem(2048, 64, "pow:0.5", 1e-2, seed=31, with_xt=True)
