@@ -23,11 +23,11 @@ Extra legs (outside the timed region of the headline value):
   * adjoint (skip with --no-adjoint): forward + backward of the autograd Function on n = 131072,
     d = 1024 (sigma_j = j^-1/2, nu = 1e-2), gradients validated against the dense oracle;
   * variants (skip with --no-variants): the headline workload solved with the Gaussian and
-    SJLT sketches, with the transform-reuse SRHT (a variant), by adaptive IHS, by adaptive
-    Polyak-IHS, and by the unpreconditioned CG baseline;
+    SJLT sketches, with the transform-reuse SRHT and its nested form (variants), by adaptive
+    IHS, by adaptive Polyak-IHS, and by the unpreconditioned CG baseline;
   * --skip-main --paper / --paper-large / --paper-e3: the synthetic nu-sweeps of the paper's
     numerical section (n = 16384 or 131072, d = 7000; n = 524288, d = 14000; sigma_j = 0.995^j)
-    with its comparison set;
+    with its comparison set (including the direct Cholesky baseline);
   * --skip-main --dual: n < d through the dual problem (the OVA-Lung shape n = 1545, d = 10936,
     c = 2, and n = 8192, d = 32768) next to the primal solve; --dual-wide: the dual solve alone;
     --dual-large: the dual solve at n = 16384, d = 131072 with a primal-residual check.
@@ -35,6 +35,7 @@ Extra legs (outside the timed region of the headline value):
 --hv-only runs just fused H.v launches and a calibration copy (for rocprofv3 counter runs);
 --sketch-only M runs just sketches (--sketch kind) of size M of the workload's A.
 --factor-only M runs just factorisations (aes_factor) of an M x d Gaussian sketch.
+--direct-only N D runs just the direct baseline (aes_solve_direct) on an N x D matrix.
 """
 import argparse
 import hashlib
@@ -226,6 +227,31 @@ def factor_only(args):
     print(json.dumps({"factorisations": args.steps, "m": m, "d": w.d, "ms_per_factor": ms}))
 
 
+def direct_only(args):
+    """aes_solve_direct (the direct baseline of Sec. 5: Gram of the whole A with nu^2 Lambda,
+    Cholesky and inverse factor, two triangular products) on an N x D matrix of N(0, 1/N)
+    entries, nu = 1e-2, Lambda = I, one right-hand side.  Values do not change the kernels' work."""
+    import torch
+
+    import paper_2104_14101_amd as aes
+
+    n, d = args.direct_only
+    g = torch.Generator(device="cuda")
+    g.manual_seed(8)
+    A = torch.randn((n, d), dtype=torch.float64, device="cuda", generator=g) / n ** 0.5
+    b = torch.randn(d, dtype=torch.float64, device="cuda", generator=g)
+    for _ in range(max(args.warmup, 1)):
+        aes.solve_direct(A, b, 1e-2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        aes.solve_direct(A, b, 1e-2)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    print(json.dumps({"direct_solves": args.steps, "n": n, "d": d, "ms_per_solve": ms,
+                      "gram_flops": n * d * (d + 1)}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -239,6 +265,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--hv-only", action="store_true")
     ap.add_argument("--sketch-only", type=int, default=0, metavar="M")
+    ap.add_argument("--direct-only", type=int, nargs=2, default=None, metavar=("N", "D"),
+                    help="only the direct baseline (aes_solve_direct) on an N x D matrix")
     ap.add_argument("--factor-only", type=int, default=0, metavar="M",
                     help="only aes_factor of an M x d sketch of the workload's width")
     ap.add_argument("--batched", action="store_true", help="with --skip-main: the batched leg")
@@ -274,6 +302,8 @@ def main():
         return sketch_only(args)
     if args.factor_only:
         return factor_only(args)
+    if args.direct_only:
+        return direct_only(args)
 
     import numpy as np
     import torch
