@@ -231,6 +231,11 @@ class Solver {
     pinned_ = h->pinned;
   }
   ~Solver() {
+    if (ss_) {
+      (void)hipStreamSynchronize(ss_);
+      (void)hipStreamDestroy(ss_);
+    }
+    if (spec_done_) (void)hipEventDestroy(spec_done_);
     for (hipEvent_t& e : fev_)
       if (e) (void)hipEventDestroy(e);
     for (auto& e : sk_ev_) {
@@ -454,6 +459,12 @@ class Solver {
         launch_srht_select(o_.seed, o_.problem, k_, npad_, m_, sc, s_);
         launch_gather_rows(npad_, d_, yr_, sc.pos, scale, SA_, d_, s_);
       }
+    } else if (o_.sketch == AES_SRHT && !bf && !f32 && spec_pending_ && spec_k_ == k_ && spec_m_ == m_) {
+      // this resize's sketch (same seed, index and size) was formed ahead on the side stream
+      AES_HIP(hipStreamWaitEvent(s_, spec_done_, 0));
+      SA_ = spec_out_;
+      spec_cur_ = spec_tgt_;
+      spec_pending_ = false;
     } else if (o_.sketch == AES_SRHT) {
       double* eps = S<double>("eps", n_);
       launch_signs(o_.seed, o_.problem, k_, n_, eps, s_);
@@ -500,6 +511,7 @@ class Solver {
       launch_gauss_sketch(gp, P_.A, n_, d_, P_.lda, m_, o_.seed, o_.problem, k_, SA_, S<double>("gauss_gt", gp.gt_elems),
                           gp.part_elems ? S<double>("gauss_part", gp.part_elems) : nullptr, s_);
     }
+    if (!bf && !f32) sketch_ahead();
     int* flag = B<int>("chol_flag", 1);  // read by the problem's next initialisation
     AES_HIP(hipMemsetAsync(flag, 0, sizeof(int), s_));
     factor_from_sa(bf ? 1 : (f32 ? 2 : 0), flag);
@@ -507,6 +519,47 @@ class Solver {
     // block, which the host reads next
     chol_flag_ = flag;
     AES_HIP(hipEventRecord(sk_ev_.back().second, s_));
+  }
+
+  // FP64 SRHT solves of one problem: form the sketch of the next resize (index k + 1, size
+  // min(2m, cap)) on a side stream while this resize's Gram, factorisation and the following
+  // attempts run on the main one.  The sketch does not depend on the attempts, so a resize takes
+  // it as it is (the same values a sketch at the resize would give); when no resize comes it is
+  // discarded.  It writes one of two buffers in turn: the other holds the sketch in use, and the
+  // one written last held the sketch of two resizes ago, whose readers have finished (the host
+  // decided this resize after reading the flags of a later step).  Its scratch is its own.
+  void enable_sketch_ahead() {
+    if (o_.sketch != AES_SRHT || mixed_ || !o_.adaptive || cg_) return;
+    const double bytes = 8.0 * ((double)srht_scratch_elems(npad_, d_) + 2.0 * (double)mcap_ * (double)d_);
+    spec_ok_ = bytes <= kSketchAheadBytes;
+  }
+  void sketch_ahead() {
+    if (!spec_ok_ || m_ >= mcap_) return;
+    const int64_t m2 = std::min<int64_t>(2 * m_, mcap_);
+    if (!ss_) {
+      AES_HIP(hipStreamCreateWithFlags(&ss_, hipStreamNonBlocking));
+      AES_HIP(hipEventCreateWithFlags(&spec_done_, hipEventDisableTiming));
+    }
+    const int tgt = spec_cur_ == 0 ? 1 : 0;
+    double* out = B<double>(tgt ? "ahead_SA1" : "ahead_SA0", (size_t)m2 * d_);
+    double* eps = S<double>("ahead_eps", n_);
+    SelectScratch sc;
+    sc.keys = S<uint64_t>("ahead_keys", npad_);
+    sc.pos = S<int32_t>("ahead_pos", npad_);
+    sc.hist = S<uint32_t>("ahead_hist", 256 * 8);
+    sc.state = S<uint64_t>("ahead_state", 4);
+    sc.blk = S<uint32_t>("ahead_blk", 2 * select_blocks(npad_));
+    double* Y = S<double>("ahead_Y", srht_scratch_elems(npad_, d_));
+    int32_t* need = S<int32_t>("ahead_need", 512);
+    launch_signs(o_.seed, o_.problem, k_ + 1, n_, eps, ss_);
+    launch_srht_select(o_.seed, o_.problem, k_ + 1, npad_, m2, sc, ss_);
+    launch_srht_apply<double, double, double>(P_.A, n_, d_, P_.lda, eps, npad_, sc.pos, m2, Y, out, d_, need, ss_);
+    AES_HIP(hipEventRecord(spec_done_, ss_));
+    spec_pending_ = true;
+    spec_k_ = k_ + 1;
+    spec_m_ = m2;
+    spec_tgt_ = tgt;
+    spec_out_ = out;
   }
 
   KeyOrderScratch key_order_scratch() {
@@ -906,6 +959,9 @@ class Solver {
       st = AES_ERR_INVALID_ARG;
       h_->set_err(e.what());
     }
+    // a sketch formed ahead for a resize that did not come still reads A: finish it before the
+    // call returns
+    if (ss_ && hipStreamSynchronize(ss_) != hipSuccess && st == AES_OK) st = AES_ERR_HIP;
     double hv_ms = 0.0;
     int64_t hv_n = 0;
     if (o_.profile && st != AES_ERR_HIP) {
@@ -1478,6 +1534,14 @@ class Solver {
   double* yr_ = nullptr;   // transform-reuse SRHT: the stored normalised transform of A
   bool yr_ready_ = false;
   int32_t* korder_ = nullptr;  // nested SRHT: padded rows in increasing key order
+  // sketch of the next resize formed ahead (FP64 SRHT, one problem)
+  static constexpr double kSketchAheadBytes = 4.0 * 1024 * 1024 * 1024;
+  bool spec_ok_ = false, spec_pending_ = false;
+  hipStream_t ss_ = nullptr;
+  hipEvent_t spec_done_ = nullptr;
+  int64_t spec_k_ = -1, spec_m_ = 0;
+  int spec_cur_ = -1, spec_tgt_ = 0;
+  double* spec_out_ = nullptr;
   int64_t gnest_m_ = 0;        // nested SRHT: rows behind the kept Gram (0: none)
   double nu2_;
   bool mixed_ = false, woodbury_ = false;
@@ -2138,6 +2202,7 @@ static aes_status solve_impl(aes_handle h, void* stream, const ProblemDesc& P, d
     return st != AES_OK ? st : bst;
   }
   auto* solver = new Solver(h, (hipStream_t)stream, P, o, tol, ns);
+  if (!keep) solver->enable_sketch_ahead();
   st = solver->run(info);
   if (keep)
     *keep = solver;
