@@ -236,6 +236,7 @@ class Solver {
       (void)hipStreamDestroy(ss_);
     }
     if (spec_done_) (void)hipEventDestroy(spec_done_);
+    if (spec_go_) (void)hipEventDestroy(spec_go_);
     for (hipEvent_t& e : fev_)
       if (e) (void)hipEventDestroy(e);
     for (auto& e : sk_ev_) {
@@ -459,10 +460,15 @@ class Solver {
         launch_srht_select(o_.seed, o_.problem, k_, npad_, m_, sc, s_);
         launch_gather_rows(npad_, d_, yr_, sc.pos, scale, SA_, d_, s_);
       }
-    } else if (o_.sketch == AES_SRHT && !bf && !f32 && spec_pending_ && spec_k_ == k_ && spec_m_ == m_) {
-      // this resize's sketch (same seed, index and size) was formed ahead on the side stream
+    } else if (o_.sketch == AES_SRHT && spec_pending_ && spec_k_ == k_ && spec_m_ == m_) {
+      // this resize's sketch (same seed, index, size and type) was formed ahead on the side stream
       AES_HIP(hipStreamWaitEvent(s_, spec_done_, 0));
-      SA_ = spec_out_;
+      if (bf)
+        SA16_ = static_cast<__hip_bfloat16*>(spec_out_);
+      else if (f32)
+        SA32_ = static_cast<float*>(spec_out_);
+      else
+        SA_ = static_cast<double*>(spec_out_);
       spec_cur_ = spec_tgt_;
       spec_pending_ = false;
     } else if (o_.sketch == AES_SRHT) {
@@ -511,7 +517,7 @@ class Solver {
       launch_gauss_sketch(gp, P_.A, n_, d_, P_.lda, m_, o_.seed, o_.problem, k_, SA_, S<double>("gauss_gt", gp.gt_elems),
                           gp.part_elems ? S<double>("gauss_part", gp.part_elems) : nullptr, s_);
     }
-    if (!bf && !f32) sketch_ahead();
+    sketch_ahead(bf, f32);
     int* flag = B<int>("chol_flag", 1);  // read by the problem's next initialisation
     AES_HIP(hipMemsetAsync(flag, 0, sizeof(int), s_));
     factor_from_sa(bf ? 1 : (f32 ? 2 : 0), flag);
@@ -521,27 +527,32 @@ class Solver {
     AES_HIP(hipEventRecord(sk_ev_.back().second, s_));
   }
 
-  // FP64 SRHT solves of one problem: form the sketch of the next resize (index k + 1, size
+  // SRHT solves of one problem: form the sketch of the next resize (index k + 1, size
   // min(2m, cap)) on a side stream while this resize's Gram, factorisation and the following
   // attempts run on the main one.  The sketch does not depend on the attempts, so a resize takes
   // it as it is (the same values a sketch at the resize would give); when no resize comes it is
   // discarded.  It writes one of two buffers in turn: the other holds the sketch in use, and the
   // one written last held the sketch of two resizes ago, whose readers have finished (the host
-  // decided this resize after reading the flags of a later step).  Its scratch is its own.
+  // decided this resize after reading the flags of a later step).  Its scratch is its own; it is
+  // used while the extra scratch fits in an eighth of the device's memory.
   void enable_sketch_ahead() {
-    if (o_.sketch != AES_SRHT || mixed_ || !o_.adaptive || cg_) return;
-    const double bytes = 8.0 * ((double)srht_scratch_elems(npad_, d_) + 2.0 * (double)mcap_ * (double)d_);
-    spec_ok_ = bytes <= kSketchAheadBytes;
+    if (o_.sketch != AES_SRHT || !o_.adaptive || cg_) return;
+    // the mixed modes sketch the FP32 copy (FP32 scratch) into BF16 (AES_MIXED) or FP32 output
+    const double ey = mixed_ ? 4.0 : 8.0, es = !mixed_ ? 8.0 : (sketch32_ ? 4.0 : 2.0);
+    const double bytes = ey * (double)srht_scratch_elems(npad_, d_) + 2.0 * es * (double)mcap_ * (double)d_;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return;
+    spec_ok_ = bytes <= (double)total_b / kSketchAheadShare;
   }
-  void sketch_ahead() {
+  void sketch_ahead(bool bf, bool f32) {
     if (!spec_ok_ || m_ >= mcap_) return;
     const int64_t m2 = std::min<int64_t>(2 * m_, mcap_);
     if (!ss_) {
       AES_HIP(hipStreamCreateWithFlags(&ss_, hipStreamNonBlocking));
+      AES_HIP(hipEventCreateWithFlags(&spec_go_, hipEventDisableTiming));
       AES_HIP(hipEventCreateWithFlags(&spec_done_, hipEventDisableTiming));
     }
     const int tgt = spec_cur_ == 0 ? 1 : 0;
-    double* out = B<double>(tgt ? "ahead_SA1" : "ahead_SA0", (size_t)m2 * d_);
     double* eps = S<double>("ahead_eps", n_);
     SelectScratch sc;
     sc.keys = S<uint64_t>("ahead_keys", npad_);
@@ -549,11 +560,32 @@ class Solver {
     sc.hist = S<uint32_t>("ahead_hist", 256 * 8);
     sc.state = S<uint64_t>("ahead_state", 4);
     sc.blk = S<uint32_t>("ahead_blk", 2 * select_blocks(npad_));
-    double* Y = S<double>("ahead_Y", srht_scratch_elems(npad_, d_));
     int32_t* need = S<int32_t>("ahead_need", 512);
+    // ordered after everything enqueued on the main stream so far (the caller's writes of A, the
+    // FP32 cast); this resize's Gram and factorisation come after this point and overlap it
+    AES_HIP(hipEventRecord(spec_go_, s_));
+    AES_HIP(hipStreamWaitEvent(ss_, spec_go_, 0));
     launch_signs(o_.seed, o_.problem, k_ + 1, n_, eps, ss_);
     launch_srht_select(o_.seed, o_.problem, k_ + 1, npad_, m2, sc, ss_);
-    launch_srht_apply<double, double, double>(P_.A, n_, d_, P_.lda, eps, npad_, sc.pos, m2, Y, out, d_, need, ss_);
+    void* out;
+    if (bf) {
+      auto* o16 = B<__hip_bfloat16>(tgt ? "ahead_SA16_1" : "ahead_SA16_0", (size_t)m2 * d_);
+      launch_srht_apply<float, float, __hip_bfloat16>(A32_, n_, d_, d_, eps, npad_, sc.pos, m2,
+                                                      S<float>("ahead_Y32", srht_scratch_elems(npad_, d_)), o16, d_,
+                                                      need, ss_);
+      out = o16;
+    } else if (f32) {
+      auto* o32 = B<float>(tgt ? "ahead_SA32_1" : "ahead_SA32_0", (size_t)m2 * d_);
+      launch_srht_apply<float, float, float>(A32_, n_, d_, d_, eps, npad_, sc.pos, m2,
+                                             S<float>("ahead_Y32", srht_scratch_elems(npad_, d_)), o32, d_, need, ss_);
+      out = o32;
+    } else {
+      auto* o64 = B<double>(tgt ? "ahead_SA1" : "ahead_SA0", (size_t)m2 * d_);
+      launch_srht_apply<double, double, double>(P_.A, n_, d_, P_.lda, eps, npad_, sc.pos, m2,
+                                                S<double>("ahead_Y", srht_scratch_elems(npad_, d_)), o64, d_, need,
+                                                ss_);
+      out = o64;
+    }
     AES_HIP(hipEventRecord(spec_done_, ss_));
     spec_pending_ = true;
     spec_k_ = k_ + 1;
@@ -1535,13 +1567,13 @@ class Solver {
   bool yr_ready_ = false;
   int32_t* korder_ = nullptr;  // nested SRHT: padded rows in increasing key order
   // sketch of the next resize formed ahead (FP64 SRHT, one problem)
-  static constexpr double kSketchAheadBytes = 4.0 * 1024 * 1024 * 1024;
+  static constexpr double kSketchAheadShare = 8.0;  // extra scratch at most total memory / 8
   bool spec_ok_ = false, spec_pending_ = false;
   hipStream_t ss_ = nullptr;
-  hipEvent_t spec_done_ = nullptr;
+  hipEvent_t spec_done_ = nullptr, spec_go_ = nullptr;
   int64_t spec_k_ = -1, spec_m_ = 0;
   int spec_cur_ = -1, spec_tgt_ = 0;
-  double* spec_out_ = nullptr;
+  void* spec_out_ = nullptr;
   int64_t gnest_m_ = 0;        // nested SRHT: rows behind the kept Gram (0: none)
   double nu2_;
   bool mixed_ = false, woodbury_ = false;
